@@ -1,0 +1,198 @@
+/*
+ * chop_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-threaded CPU statement of T-method island chopping
+ * for one calorimeter fill, written from the paper (Gohn, "Data Acquisition
+ * with GPUs: The DAQ for the Muon g-2 Experiment at Fermilab", ICHEP 2016):
+ * Section 3 (the T-method paragraph) and Table 2 ("CUDA kernel routines used
+ * to process each muon fill").
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this library. The product (the HIP library) never calls it and
+ * shares no code with it: no header, helper, table or constant.
+ *
+ * Every quantity is an integer; nothing here is approximate. Each step is the
+ * plain definition, in the order Table 2 and the T-method paragraph give:
+ *
+ *   1. pedestal of channel c  = mean of its first Np samples (Table 2,
+ *      pedestal row: Np = 100 there), rounded half up to an integer;
+ *   2. calorimeter sum S[t]   = sum over channels of x[c][t] minus the sum of
+ *      the channel pedestals (Table 2, waveform-sum row);
+ *   3. threshold flag F[t]    = S[t] < thr, one flag per time sample
+ *      (Table 2, threshold row; Section 3, T-method paragraph: one thread
+ *      per sample);
+ *   4. dilation               = every flagged sample t marks the window
+ *      [t-pre, t+post] clipped to the fill (Table 2, pre/post-sample row);
+ *   5. merging and the island array = every maximal run of marked samples is
+ *      one island, so windows that overlap or touch become one island
+ *      (Table 2, merge-check and island-array rows);
+ *   6. chopped islands        = each island's raw samples of every channel,
+ *      packed back to back (Section 3, description of the GPU thread).
+ *
+ * Readings where the paper is silent (all listed in the design notes):
+ *   - integer pedestal: round half up of the exact mean, i.e.
+ *     floor((2 P + n) / (2 n)) with n = min(Np, N); ped = 0 when N = 0;
+ *   - a sample crosses the threshold when S < thr (strict);
+ *   - level, not edge: every flagged sample is dilated;
+ *   - windows are clipped at 0 and N-1, never dropped;
+ *   - abutting windows merge (a union of marks);
+ *   - island records are (start, stop, offset), stop exclusive, offset = sum
+ *     of the lengths of the earlier islands, islands in increasing start;
+ *   - gathered samples are the raw int16 values, not pedestal-subtracted.
+ *
+ * Layout: x is channel-major, x[c * stride + t], 0 <= t < N.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Mathematical floor of a / b for b > 0 (C division truncates toward 0). */
+static int64_t floor_div(int64_t a, int64_t b)
+{
+    int64_t q = a / b;
+    if ((a % b) != 0 && (a < 0))
+        q -= 1;
+    return q;
+}
+
+/* Step 1, Table 2 pedestal row: per-channel pedestal, the mean of the first
+ * min(Np, N) samples rounded half up. */
+void orc_pedestals(const int16_t *x, int32_t C, int64_t N, int64_t stride,
+                   int32_t Np, int32_t *ped)
+{
+    int64_t n = (N < (int64_t)Np) ? N : (int64_t)Np;
+    for (int32_t c = 0; c < C; c++) {
+        if (n <= 0) {
+            ped[c] = 0;
+            continue;
+        }
+        int64_t P = 0;
+        for (int64_t t = 0; t < n; t++)
+            P += x[(int64_t)c * stride + t];
+        ped[c] = (int32_t)floor_div(2 * P + n, 2 * n);
+    }
+}
+
+/* Step 2, Table 2 waveform-sum row: pedestal-subtracted calorimeter sum for
+ * every time sample. */
+void orc_calo_sum(const int16_t *x, int32_t C, int64_t N, int64_t stride,
+                  const int32_t *ped, int64_t *S)
+{
+    int64_t ped_total = 0;
+    for (int32_t c = 0; c < C; c++)
+        ped_total += ped[c];
+    for (int64_t t = 0; t < N; t++) {
+        int64_t s = 0;
+        for (int32_t c = 0; c < C; c++)
+            s += x[(int64_t)c * stride + t];
+        S[t] = s - ped_total;
+    }
+}
+
+/* Step 3, Table 2 threshold row: one threshold flag per time sample. */
+void orc_threshold(const int64_t *S, int64_t N, int32_t thr, uint8_t *F)
+{
+    for (int64_t t = 0; t < N; t++)
+        F[t] = (S[t] < (int64_t)thr) ? 1 : 0;
+}
+
+/* Step 4, Table 2 pre/post-sample row: every flagged sample marks pre samples
+ * before it and post samples after it, clipped to the fill. */
+void orc_dilate(const uint8_t *F, int64_t N, int32_t pre, int32_t post,
+                uint8_t *M)
+{
+    memset(M, 0, (size_t)N);
+    for (int64_t t = 0; t < N; t++) {
+        if (!F[t])
+            continue;
+        int64_t lo = t - pre;
+        int64_t hi = t + post;
+        if (lo < 0)
+            lo = 0;
+        if (hi > N - 1)
+            hi = N - 1;
+        for (int64_t u = lo; u <= hi; u++)
+            M[u] = 1;
+    }
+}
+
+/* Step 5, Table 2 merge-check and island-array rows: maximal runs of marked
+ * samples are the islands (so overlapping or touching windows are one
+ * island), saved in increasing start with their offsets in the packed
+ * output.
+ * islands[3*i + 0] = start, [3*i + 1] = stop (exclusive), [3*i + 2] = offset.
+ * Records past cap are counted but not stored. Returns the island count. */
+int64_t orc_islands(const uint8_t *M, int64_t N, int64_t *islands,
+                    int64_t cap, int64_t *total_len)
+{
+    int64_t n = 0;
+    int64_t offset = 0;
+    int64_t t = 0;
+    while (t < N) {
+        if (!M[t]) {
+            t++;
+            continue;
+        }
+        int64_t start = t;
+        while (t < N && M[t])
+            t++;
+        if (n < cap) {
+            islands[3 * n + 0] = start;
+            islands[3 * n + 1] = t;
+            islands[3 * n + 2] = offset;
+        }
+        offset += t - start;
+        n++;
+    }
+    *total_len = offset;
+    return n;
+}
+
+/* Step 6, Section 3 (GPU thread): every channel's raw samples of every
+ * island, packed at the island's offset. */
+void orc_gather(const int16_t *x, int32_t C, int64_t stride,
+                const int64_t *islands, int64_t n, int16_t *out,
+                int64_t out_stride)
+{
+    for (int64_t i = 0; i < n; i++) {
+        int64_t start = islands[3 * i + 0];
+        int64_t stop = islands[3 * i + 1];
+        int64_t offset = islands[3 * i + 2];
+        for (int32_t c = 0; c < C; c++)
+            for (int64_t k = 0; k < stop - start; k++)
+                out[(int64_t)c * out_stride + offset + k] =
+                    x[(int64_t)c * stride + start + k];
+    }
+}
+
+/* Steps 1-6 in order for one fill. out may be NULL (no gather); otherwise it
+ * must hold C rows of out_stride >= total_len elements. Returns the island
+ * count, or -1 when scratch memory cannot be allocated. */
+int64_t orc_chop(const int16_t *x, int32_t C, int64_t N, int64_t stride,
+                 int32_t Np, int32_t thr, int32_t pre, int32_t post,
+                 int32_t *ped, int64_t *islands, int64_t cap,
+                 int64_t *total_len, int16_t *out, int64_t out_stride)
+{
+    size_t n = (size_t)(N > 0 ? N : 1);
+    int64_t *S = (int64_t *)malloc(n * sizeof(int64_t));
+    uint8_t *F = (uint8_t *)malloc(n);
+    uint8_t *M = (uint8_t *)malloc(n);
+    if (!S || !F || !M) {
+        free(S);
+        free(F);
+        free(M);
+        return -1;
+    }
+    orc_pedestals(x, C, N, stride, Np, ped);
+    orc_calo_sum(x, C, N, stride, ped, S);
+    orc_threshold(S, N, thr, F);
+    orc_dilate(F, N, pre, post, M);
+    int64_t count = orc_islands(M, N, islands, cap, total_len);
+    if (out != NULL)
+        orc_gather(x, C, stride, islands, count < cap ? count : cap, out,
+                   out_stride);
+    free(S);
+    free(F);
+    free(M);
+    return count;
+}
