@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""Throughput of T-method island chopping on one MI355X.
+
+Workload: 16 synthetic calorimeter fills of 54 channels x 560,000 int16
+samples (12-bit values; 700 us at 800 MSPS, Section 3 of the paper) at 3x the
+nominal initial pulse rate, threshold -200 ADC on the pedestal-subtracted
+calorimeter sum, pre 8 / post 24 samples. A step chops all 16 fills: island
+tables, counts, pedestals and the packed raw samples of every channel, in one
+persistent batched launch replayed from a captured HIP graph (schedule from
+the library's autotuner). Inputs are resident in HBM before timing starts.
+
+Printed (one JSON line): raw ADC GB/s (value) and its fraction of the HBM
+peak, p50/p99 fill latency for the batched and the plain per-fill forms, the
+fused kernel's roofline figures timed live with HIP events over the timed
+region, and the CPU oracle's throughput on a bounded sample.
+"""
+import argparse
+import concurrent.futures as cf
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "raw ADC GB/s island-chopped & % HBM peak; p99 fill latency, batched vs plain"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "chop_fused_16fills_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1611_04959_amd", "csrc", "chop_kernels.hip")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def pct(vals, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(vals, dtype=np.float64), q)) if vals else None
+
+
+def kernel_sha():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--fills", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="wall-clock budget of the CPU oracle sample (0 = skip)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-fill comparison")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default schedule")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(fills are independent units; see the sharding notes). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1611_04959_amd as daq
+    import synth
+
+    specs = synth.config_c1(args.fills)
+    C, N = synth.CHANNELS, specs[0].n_samples
+    raw_bytes = sum(s.raw_bytes for s in specs)
+    log("rendering %d fills (%.1f MB raw)" % (len(specs), raw_bytes / 1e6))
+    xs = synth.render_many(specs)
+    xd = synth.to_device(xs)
+    fills = [daq.Fill(d, s.n_samples, threshold=s.threshold, pre=s.pre, post=s.post,
+                      ped_samples=s.ped_samples) for d, s in zip(xd, specs)]
+    outs = [daq.alloc_out(f) for f in fills]
+    stream = torch.cuda.current_stream()
+    ctx = daq.Context(0)
+
+    # ---- schedule ---------------------------------------------------------
+    if not args.no_tune:
+        log("autotuning the fused kernel schedule")
+        best = ctx.daq_autotune(fills, outs)
+        sched = (best.threads, best.wgs_per_cu, best.resident)
+    else:
+        s = ctx.get_schedule()
+        sched = (s.threads, s.wgs_per_cu, s.resident)
+    log("schedule threads=%d wgs_per_cu=%d resident=%d" % sched)
+    ctx.set_graphs(True)
+
+    # ---- batched: warm-up then the timed region --------------------------------
+    for _ in range(args.warmup):
+        ctx.daq_process_batch(fills, outs, stream)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    log("timing %d batched steps" % args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        ctx.daq_process_batch(fills, outs, stream)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern_ms = ctx.kernel_times_ms()
+    ctx.set_timing(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    step_ms = [a.elapsed_time(b) for a, b in ev]
+    value = raw_bytes / (ms_per_step * 1e-3) / 1e9
+
+    # ---- results of the timed steps, checked against the oracle on a sample --
+    counts = [o.counts.cpu().numpy() for o in outs]
+    n_isl = [int(c[0]) for c in counts]
+    tot = [int(c[1]) for c in counts]
+    status = [int(c[2]) & 0xFFFFFFFF for c in counts]
+    assert all(s == 0 for s in status), status
+    parity = None
+    try:
+        import oracle
+        ref = oracle.chop(xs[0], n_samples=N, ped_samples=specs[0].ped_samples,
+                          threshold=specs[0].threshold, pre=specs[0].pre, post=specs[0].post)
+        isl, n, total, st, ped, out = outs[0].host()
+        parity = bool(n == ref.n_islands and total == ref.total_len and
+                      np.array_equal(isl, ref.islands) and np.array_equal(ped, ref.ped) and
+                      np.array_equal(out, ref.out))
+    except ImportError:
+        parity = None
+
+    # ---- roofline of the fused kernel -------------------------------------------
+    alg_bytes = sum(2 * C * s.n_samples for s in specs) + sum(2 * C * t for t in tot) \
+        + sum(24 * n for n in n_isl) + len(specs) * (24 + 4 * C)
+    kmean = float(np.mean(kern_ms)) if kern_ms else None
+    achieved = alg_bytes / (kmean * 1e-3) / 1e9 if kmean else None
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("kernel_sha") == kernel_sha() and tr.get("fills") == len(specs):
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                "traffic": traffic, "kernel": "k_chop (fused find + gather)",
+                "kernel_ms_mean": round(kmean, 4) if kmean else None,
+                "kernel_launches_timed": len(kern_ms),
+                "algorithmic_bytes_per_launch": alg_bytes}
+
+    # ---- plain per-fill launches (the form batching must beat) ---------------------
+    plain = {}
+    if not args.no_plain:
+        for mode in ("fused", "twopass"):
+            lat = []
+            per_fill = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                        for _ in range(len(fills))]
+            for _ in range(max(2, args.warmup // 2)):
+                for f, o in zip(fills, outs):
+                    if mode == "fused":
+                        ctx.daq_chop_fill(f, o, stream)
+                    else:
+                        ctx.daq_find_islands(f, o, stream)
+                        ctx.daq_gather_islands(f, o, stream)
+            torch.cuda.synchronize()
+            steps = max(3, args.steps // 4)
+            tp0 = time.perf_counter()
+            for _ in range(steps):
+                for i, (f, o) in enumerate(zip(fills, outs)):
+                    per_fill[i][0].record(stream)
+                    if mode == "fused":
+                        ctx.daq_chop_fill(f, o, stream)
+                    else:
+                        ctx.daq_find_islands(f, o, stream)
+                        ctx.daq_gather_islands(f, o, stream)
+                    per_fill[i][1].record(stream)
+                torch.cuda.synchronize()
+                lat += [a.elapsed_time(b) for a, b in per_fill]
+            tp1 = time.perf_counter()
+            pms = (tp1 - tp0) * 1e3 / steps
+            plain[mode] = {"gbs": round(raw_bytes / (pms * 1e-3) / 1e9, 1), "ms_per_step": round(pms, 4),
+                           "p50_fill_ms": round(pct(lat, 50), 4), "p99_fill_ms": round(pct(lat, 99), 4)}
+            log("plain %s: %.1f GB/s" % (mode, plain[mode]["gbs"]))
+
+    # ---- CPU oracle on a bounded sample --------------------------------------------------
+    cpu = None
+    if args.cpu_seconds > 0:
+        try:
+            import oracle
+            cores = min(os.cpu_count() or 1, 16)
+            log("CPU oracle baseline on %d threads for ~%.0f s" % (cores, args.cpu_seconds))
+            done = 0
+            tc0 = time.perf_counter()
+
+            def one(i):
+                oracle.chop(xs[i], n_samples=N, ped_samples=specs[i].ped_samples,
+                            threshold=specs[i].threshold, pre=specs[i].pre, post=specs[i].post)
+                return specs[i].raw_bytes
+
+            with cf.ThreadPoolExecutor(cores) as ex:
+                while time.perf_counter() - tc0 < args.cpu_seconds:
+                    done += sum(ex.map(one, range(len(specs))))
+            tc1 = time.perf_counter()
+            cpu = {"value": round(done / (tc1 - tc0) / 1e9, 3), "unit": "GB/s", "cores": cores,
+                   "kind": "oracle",
+                   "sample": "the same %d fills, repeated for %.1f s (%.2f GB raw), one fill per thread"
+                             % (len(specs), tc1 - tc0, done / 1e9)}
+        except ImportError:
+            cpu = None
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "16 fills x 54 ch x 560,000 int16 samples, 3x pulse rate, "
+                               "thr -200, pre 8, post 24; batched persistent launch (graph)",
+                   "fills": len(specs), "channels": C, "samples": N, "rate": 3.0,
+                   "threshold": -200, "pre": 8, "post": 24, "ped_samples": 100,
+                   "schedule": {"threads": sched[0], "wgs_per_cu": sched[1], "resident": sched[2]}},
+        "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
+        "batched": {"gbs": round(value, 1), "p50_fill_ms": round(pct(step_ms, 50), 4),
+                    "p99_fill_ms": round(pct(step_ms, 99), 4)},
+        "plain": plain,
+        "islands_per_fill": round(float(np.mean(n_isl)), 1),
+        "occupancy": round(sum(tot) / (N * len(specs)), 4),
+        "parity_fill0": parity,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

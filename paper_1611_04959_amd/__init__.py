@@ -1,0 +1,304 @@
+"""Python binding of libdaqisland (include/daq.h): T-method island chopping of
+waveform-digitizer fills on MI355X (gfx950).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libdaqisland.so``. PyTorch supplies device memory and streams.
+The functions keep the C names; ``Context`` wraps a ``daq_ctx``.
+
+Layouts (device tensors, ``torch.int16`` etc. on a ROCm device):
+  raw      int16 [C, row_stride]  channel-major fill, row_stride % 8 == 0
+  islands  int64 [capacity, 3]    (start, stop, offset) per island
+  counts   int64 [3]              n_islands, total_len, status (low 32 bits)
+  ped      int32 [C]              pedestals (optional)
+  out      int16 [C, out_stride]  packed island samples (optional)
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdaqisland.so")
+
+DAQ_OK = 0
+DAQ_EINVAL = -1
+DAQ_EALIGN = -2
+DAQ_EHIP = -3
+DAQ_ENOMEM = -4
+DAQ_EAGAIN = -5
+DAQ_ERANGE = -6
+DAQ_EMISMATCH = -7
+DAQ_STATUS_CAPACITY = 1
+DAQ_STATUS_OUT_STRIDE = 2
+DAQ_MAX_WINDOW = 32768
+
+
+class daq_fill(ctypes.Structure):
+    _fields_ = [("raw", ctypes.c_void_p), ("n_samples", ctypes.c_int64),
+                ("row_stride", ctypes.c_int64), ("n_channels", ctypes.c_int32),
+                ("ped_samples", ctypes.c_int32), ("threshold", ctypes.c_int32),
+                ("pre", ctypes.c_int32), ("post", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class daq_fill_out(ctypes.Structure):
+    _fields_ = [("islands", ctypes.c_void_p), ("capacity", ctypes.c_int64),
+                ("counts", ctypes.c_void_p), ("ped", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("out_stride", ctypes.c_int64)]
+
+
+class daq_schedule(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
+                ("resident", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class DaqError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        lib = _lib_or_none()
+        msg = lib.daq_strerror(code).decode() if lib else str(code)
+        extra = ""
+        if lib is not None and code == DAQ_EHIP:
+            extra = " (hip error %d)" % lib.daq_last_hip_error()
+        super().__init__("%s failed: %s%s" % (where, msg, extra))
+        self.code = code
+
+
+_lib = None
+
+
+def _lib_or_none():
+    return _lib
+
+
+def load_library():
+    """Loads libdaqisland.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libdaqisland.so is not built (run __graft_entry__.build() or "
+                          "python paper_1611_04959_amd/build.py); there is no CPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "daq_version": ([], ctypes.c_char_p),
+        "daq_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "daq_last_hip_error": ([], ctypes.c_int),
+        "daq_max_islands": ([i64, i32, i32], i64),
+        "daq_ctx_create": ([ctypes.POINTER(vp), ctypes.c_int], ctypes.c_int),
+        "daq_ctx_destroy": ([vp], None),
+        "daq_find_islands": ([vp, ctypes.POINTER(daq_fill), vp, i64, vp, vp, vp], ctypes.c_int),
+        "daq_gather_islands": ([vp, ctypes.POINTER(daq_fill), vp, i64, vp, vp, i64, vp], ctypes.c_int),
+        "daq_chop_fill": ([vp, ctypes.POINTER(daq_fill), ctypes.POINTER(daq_fill_out), vp], ctypes.c_int),
+        "daq_process_batch": ([vp, ctypes.POINTER(daq_fill), ctypes.POINTER(daq_fill_out), i32, vp],
+                              ctypes.c_int),
+        "daq_ctx_set_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
+        "daq_ctx_get_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
+        "daq_ctx_set_graphs": ([vp, ctypes.c_int], ctypes.c_int),
+        "daq_ctx_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
+        "daq_ctx_kernel_time": ([vp, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+        "daq_ctx_kernel_times": ([vp, ctypes.POINTER(ctypes.c_float), i32], ctypes.c_int),
+        "daq_autotune": ([vp, ctypes.POINTER(daq_fill), ctypes.POINTER(daq_fill_out), i32, vp,
+                          ctypes.c_char_p, ctypes.POINTER(daq_schedule)], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str):
+    if rc != DAQ_OK:
+        raise DaqError(rc, where)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream or None
+
+
+def daq_max_islands(n_samples: int, pre: int, post: int) -> int:
+    return int(load_library().daq_max_islands(n_samples, pre, post))
+
+
+def padded(n: int) -> int:
+    return (int(n) + 7) // 8 * 8
+
+
+@dataclasses.dataclass
+class Fill:
+    """One calorimeter fill on the device and its chopping parameters."""
+    raw: object                 # torch.int16 [C, row_stride] (row_stride % 8 == 0)
+    n_samples: int
+    threshold: int = -200
+    pre: int = 8
+    post: int = 24
+    ped_samples: int = 100
+
+    def c_struct(self) -> daq_fill:
+        r = self.raw
+        if r.dim() != 2 or r.stride(1) != 1:
+            raise ValueError("raw must be a 2-D tensor with contiguous rows")
+        return daq_fill(r.data_ptr(), int(self.n_samples), int(r.stride(0)), int(r.shape[0]),
+                        int(self.ped_samples), int(self.threshold), int(self.pre), int(self.post), 0)
+
+
+@dataclasses.dataclass
+class FillOut:
+    """Device buffers for one fill's results."""
+    islands: object             # torch.int64 [capacity, 3]
+    counts: object              # torch.int64 [3]
+    ped: object = None          # torch.int32 [C] or None
+    out: object = None          # torch.int16 [C, out_stride] or None
+
+    def c_struct(self) -> daq_fill_out:
+        cap = int(self.islands.shape[0]) if self.islands is not None else 0
+        ost = int(self.out.stride(0)) if self.out is not None else 0
+        return daq_fill_out(_ptr(self.islands), cap, _ptr(self.counts), _ptr(self.ped),
+                            _ptr(self.out), ost)
+
+    def host(self):
+        """Copies the results back: (islands[n], n_islands, total_len, status, ped, out[:, :total])."""
+        cnt = self.counts.cpu().numpy()
+        n, total, status = int(cnt[0]), int(cnt[1]), int(cnt[2]) & 0xFFFFFFFF
+        isl = self.islands[:min(n, self.islands.shape[0])].cpu().numpy()
+        ped = self.ped.cpu().numpy() if self.ped is not None else None
+        out = None
+        if self.out is not None:
+            out = self.out[:, :min(total, self.out.shape[1])].cpu().numpy()
+        return isl, n, total, status, ped, out
+
+
+def alloc_out(fill: Fill, capacity: Optional[int] = None, gather: bool = True,
+              device=None) -> FillOut:
+    """Output buffers that can never overflow (capacity = daq_max_islands)."""
+    import torch
+    dev = device or fill.raw.device
+    C = int(fill.raw.shape[0])
+    cap = daq_max_islands(fill.n_samples, fill.pre, fill.post) if capacity is None else capacity
+    isl = torch.empty((max(cap, 0), 3), dtype=torch.int64, device=dev)
+    counts = torch.zeros(3, dtype=torch.int64, device=dev)
+    ped = torch.empty(C, dtype=torch.int32, device=dev)
+    out = torch.empty((C, max(padded(fill.n_samples), 8)), dtype=torch.int16, device=dev) if gather else None
+    return FillOut(isl, counts, ped, out)
+
+
+class Context:
+    """A daq_ctx on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self._lib = load_library()
+        h = ctypes.c_void_p()
+        _check(self._lib.daq_ctx_create(ctypes.byref(h), int(device)), "daq_ctx_create")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            self._lib.daq_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- the C calls -----------------------------------------------------
+    def daq_find_islands(self, fill: Fill, fo: FillOut, stream=None):
+        cap = int(fo.islands.shape[0]) if fo.islands is not None else 0
+        f = fill.c_struct()
+        _check(self._lib.daq_find_islands(self.handle, ctypes.byref(f), _ptr(fo.islands), cap,
+                                          _ptr(fo.counts), _ptr(fo.ped), _stream_handle(stream)),
+               "daq_find_islands")
+
+    def daq_gather_islands(self, fill: Fill, fo: FillOut, stream=None):
+        cap = int(fo.islands.shape[0]) if fo.islands is not None else 0
+        f = fill.c_struct()
+        _check(self._lib.daq_gather_islands(self.handle, ctypes.byref(f), _ptr(fo.islands), cap,
+                                            _ptr(fo.counts), _ptr(fo.out),
+                                            int(fo.out.stride(0)) if fo.out is not None else 0,
+                                            _stream_handle(stream)),
+               "daq_gather_islands")
+
+    def daq_chop_fill(self, fill: Fill, fo: FillOut, stream=None):
+        f = fill.c_struct()
+        o = fo.c_struct()
+        _check(self._lib.daq_chop_fill(self.handle, ctypes.byref(f), ctypes.byref(o),
+                                       _stream_handle(stream)), "daq_chop_fill")
+
+    def _arrays(self, fills: Sequence[Fill], outs: Sequence[FillOut]):
+        if len(fills) != len(outs):
+            raise ValueError("fills and outs differ in length")
+        n = len(fills)
+        fa = (daq_fill * max(n, 1))()
+        oa = (daq_fill_out * max(n, 1))()
+        for i, (f, o) in enumerate(zip(fills, outs)):
+            fa[i] = f.c_struct()
+            oa[i] = o.c_struct()
+        return fa, oa, n
+
+    def daq_process_batch(self, fills: Sequence[Fill], outs: Sequence[FillOut], stream=None):
+        fa, oa, n = self._arrays(fills, outs)
+        _check(self._lib.daq_process_batch(self.handle, fa, oa, n, _stream_handle(stream)),
+               "daq_process_batch")
+
+    def daq_autotune(self, fills: Sequence[Fill], outs: Sequence[FillOut], stream=None,
+                     cache_path: Optional[str] = None) -> daq_schedule:
+        fa, oa, n = self._arrays(fills, outs)
+        best = daq_schedule()
+        _check(self._lib.daq_autotune(self.handle, fa, oa, n, _stream_handle(stream),
+                                      cache_path.encode() if cache_path else None,
+                                      ctypes.byref(best)), "daq_autotune")
+        return best
+
+    # -- settings ----------------------------------------------------------
+    def set_schedule(self, threads: int = 256, wgs_per_cu: int = 4, resident: int = 0):
+        s = daq_schedule(threads, wgs_per_cu, resident, 0)
+        _check(self._lib.daq_ctx_set_schedule(self.handle, ctypes.byref(s)), "daq_ctx_set_schedule")
+
+    def get_schedule(self) -> daq_schedule:
+        s = daq_schedule()
+        _check(self._lib.daq_ctx_get_schedule(self.handle, ctypes.byref(s)), "daq_ctx_get_schedule")
+        return s
+
+    def set_graphs(self, enable: bool):
+        _check(self._lib.daq_ctx_set_graphs(self.handle, int(bool(enable))), "daq_ctx_set_graphs")
+
+    def set_timing(self, enable: bool):
+        _check(self._lib.daq_ctx_set_timing(self.handle, int(bool(enable))), "daq_ctx_set_timing")
+
+    def kernel_times_ms(self, max_n: int = 1 << 14) -> List[float]:
+        buf = (ctypes.c_float * max_n)()
+        n = self._lib.daq_ctx_kernel_times(self.handle, buf, max_n)
+        if n < 0:
+            _check(n, "daq_ctx_kernel_times")
+        return [float(buf[i]) for i in range(n)]
+
+    def kernel_time_ms(self) -> float:
+        ms = ctypes.c_float()
+        _check(self._lib.daq_ctx_kernel_time(self.handle, ctypes.byref(ms)), "daq_ctx_kernel_time")
+        return float(ms.value)
+
+
+def version() -> str:
+    return load_library().daq_version().decode()
+
+
+__all__: List[str] = ["Context", "Fill", "FillOut", "alloc_out", "daq_max_islands", "load_library",
+                      "version", "DaqError", "padded", "daq_schedule"]

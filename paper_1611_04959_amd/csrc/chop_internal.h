@@ -1,0 +1,79 @@
+// chop_internal.h -- structures shared by the host runtime and the kernels of
+// libdaqisland (not part of the public ABI; see include/daq.h for that).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "daq.h"
+
+namespace daqk {
+
+// Samples per thread: one 16-byte load per channel row.
+constexpr int kVec = 8;
+// Halo groups on one side for the largest window (post + 1 or pre + 1).
+constexpr int kMaxHaloGroups = (DAQ_MAX_WINDOW + 1 + kVec - 1) / kVec;
+// Channel count of one calorimeter (a 6 x 9 crystal grid, Section 3): the
+// count for which the fused kernel can keep a whole tile in registers.
+constexpr int kResidentChannels = 54;
+
+// Device-side view of one fill and where its results go.
+struct FillDev {
+    const int16_t *raw;
+    int64_t n;          // samples
+    int64_t stride;     // elements between channel rows
+    int32_t C;
+    int32_t np;         // pedestal samples
+    int32_t thr;
+    int32_t pre;
+    int32_t post;
+    int32_t pad0;
+    int64_t tile_base;  // global index of the fill's first tile in the launch
+    int64_t n_tiles;
+    daq_island *isl;
+    int64_t cap;
+    daq_counts *counts;
+    int32_t *ped;       // may be null
+    int16_t *out;       // may be null (find only)
+    int64_t out_stride;
+};
+
+// Per-launch sizes kept in device memory so that a captured graph can be
+// replayed for any batch that fits the scratch it was captured with.
+struct BatchHdr {
+    int32_t n_fills;
+    int32_t pad;
+    int64_t total_tiles;
+};
+
+struct KArgs {
+    const FillDev *table;  // device table of n_fills entries, or null: use `one`
+    const BatchHdr *hdr;   // device header, or null: use the two fields below
+    int32_t n_fills;
+    int32_t pad;
+    int64_t total_tiles;
+    uint64_t *tile_state;  // one look-back word per tile
+    uint32_t *ticket;      // tile dispenser
+    int64_t *thr_eff;      // per fill: threshold + sum of pedestals
+    FillDev one;
+};
+
+struct GatherArgs {
+    const int16_t *raw;
+    int64_t stride;
+    int32_t C;
+    int32_t pad;
+    const daq_island *isl;
+    int64_t cap;
+    daq_counts *counts;
+    int16_t *out;
+    int64_t out_stride;
+};
+
+hipError_t launch_prepare(const KArgs &a, int blocks, hipStream_t s);
+hipError_t launch_chop(const KArgs &a, int threads, bool resident, int grid, hipStream_t s);
+hipError_t launch_gather(const GatherArgs &g, int grid, hipStream_t s);
+// Resource use of each chop variant (for the autotuner's candidate list).
+int chop_max_threads(int threads, bool resident);
+
+}  // namespace daqk

@@ -1,0 +1,703 @@
+// daq_runtime.cpp -- host runtime and C ABI of libdaqisland (include/daq.h).
+//
+// Owns per-stream scratch (look-back words, tile dispenser, effective
+// thresholds, device descriptor tables and their pinned staging ring),
+// validates arguments, lays out tiles, launches the kernels directly or by
+// replaying captured HIP graphs, times the fused kernel on request and runs
+// the schedule autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "chop_internal.h"
+#include "daq.h"
+
+using daqk::BatchHdr;
+using daqk::FillDev;
+using daqk::GatherArgs;
+using daqk::KArgs;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_fail(hipError_t e) {
+    g_last_hip = (int)e;
+    return e == hipErrorOutOfMemory ? DAQ_ENOMEM : DAQ_EHIP;
+}
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return hip_fail(e_);     \
+    } while (0)
+
+constexpr int kRing = 4;          // pinned staging slots per stream
+constexpr int kPrepareBlocks = 64;
+
+struct GraphKey {
+    int threads = 0, wgs = 0, resident = 0;
+    const void *table = nullptr;
+    const void *state = nullptr;
+    bool operator==(const GraphKey &o) const {
+        return threads == o.threads && wgs == o.wgs && resident == o.resident && table == o.table &&
+               state == o.state;
+    }
+};
+
+struct Scratch {
+    hipStream_t stream = nullptr;
+    uint64_t *tile_state = nullptr;
+    int64_t tile_cap = 0;
+    uint32_t *ticket = nullptr;
+    int64_t *thr_eff = nullptr;
+    FillDev *table = nullptr;   // device
+    BatchHdr *hdr = nullptr;    // device
+    int32_t fill_cap = 0;
+    void *ring_host[kRing] = {};
+    hipEvent_t ring_ev[kRing] = {};
+    bool ring_used[kRing] = {};
+    int ring_pos = 0;
+    hipGraphExec_t g_prep = nullptr, g_chop = nullptr;
+    GraphKey key;
+    uint64_t *digest = nullptr;  // autotune digests
+    int32_t digest_cap = 0;
+};
+
+}  // namespace
+
+struct daq_ctx {
+    int device = 0;
+    int n_cu = 0;
+    std::string name;
+    std::vector<Scratch *> scratch;
+    daq_schedule sched{256, 4, 0, 0};
+    bool graphs = true;
+    bool timing = false;
+    // event pairs bracketing fused-kernel launches while timing is on;
+    // launches [t_read, t_next) have not been reported yet
+    std::vector<hipEvent_t> ev_start, ev_stop;
+    uint64_t t_next = 0, t_read = 0;
+    hipStream_t capture = nullptr;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+constexpr size_t kMaxTimed = 1 << 14;  // event pairs kept between reads
+
+// Records the start event of a timed launch; returns its slot.
+int timing_begin(daq_ctx *ctx, hipStream_t stream, size_t *slot) {
+    const size_t i = (size_t)(ctx->t_next % kMaxTimed);
+    if (i >= ctx->ev_start.size()) {
+        hipEvent_t a = nullptr, b = nullptr;
+        HIP_TRY(hipEventCreate(&a));
+        hipError_t e = hipEventCreate(&b);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return hip_fail(e);
+        }
+        ctx->ev_start.push_back(a);
+        ctx->ev_stop.push_back(b);
+    }
+    *slot = i;
+    HIP_TRY(hipEventRecord(ctx->ev_start[i], stream));
+    return DAQ_OK;
+}
+
+int timing_end(daq_ctx *ctx, hipStream_t stream, size_t slot) {
+    HIP_TRY(hipEventRecord(ctx->ev_stop[slot], stream));
+    ctx->t_next++;
+    if (ctx->t_next - ctx->t_read > kMaxTimed) ctx->t_read = ctx->t_next - kMaxTimed;
+    return DAQ_OK;
+}
+
+void free_graphs(Scratch *s) {
+    if (s->g_prep) (void)hipGraphExecDestroy(s->g_prep);
+    if (s->g_chop) (void)hipGraphExecDestroy(s->g_chop);
+    s->g_prep = s->g_chop = nullptr;
+    s->key = GraphKey{};
+}
+
+void free_scratch(Scratch *s) {
+    free_graphs(s);
+    (void)hipFree(s->tile_state);
+    (void)hipFree(s->ticket);
+    (void)hipFree(s->thr_eff);
+    (void)hipFree(s->table);
+    (void)hipFree(s->hdr);
+    (void)hipFree(s->digest);
+    for (int i = 0; i < kRing; i++) {
+        if (s->ring_ev[i]) (void)hipEventDestroy(s->ring_ev[i]);
+        if (s->ring_host[i]) (void)hipHostFree(s->ring_host[i]);
+    }
+    delete s;
+}
+
+Scratch *scratch_for(daq_ctx *ctx, hipStream_t stream) {
+    for (Scratch *s : ctx->scratch)
+        if (s->stream == stream) return s;
+    Scratch *s = new Scratch();
+    s->stream = stream;
+    ctx->scratch.push_back(s);
+    return s;
+}
+
+// Grows the scratch of one stream; waits for that stream first because the
+// old buffers may still be in use by queued work or captured graphs.
+int ensure_scratch(Scratch *s, int64_t tiles, int32_t fills) {
+    if (!s->ticket) HIP_TRY(hipMalloc(&s->ticket, 64));
+    if (tiles <= s->tile_cap && fills <= s->fill_cap && s->ring_host[0]) return DAQ_OK;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    free_graphs(s);
+    if (tiles > s->tile_cap) {
+        int64_t cap = std::max<int64_t>(tiles + tiles / 2, 4096);
+        (void)hipFree(s->tile_state);
+        s->tile_state = nullptr;
+        s->tile_cap = 0;
+        HIP_TRY(hipMalloc(&s->tile_state, (size_t)cap * sizeof(uint64_t)));
+        s->tile_cap = cap;
+    }
+    if (fills > s->fill_cap || !s->ring_host[0]) {
+        int32_t cap = std::max<int32_t>(fills + fills / 2, 64);
+        (void)hipFree(s->thr_eff);
+        (void)hipFree(s->table);
+        (void)hipFree(s->hdr);
+        s->thr_eff = nullptr;
+        s->table = nullptr;
+        s->hdr = nullptr;
+        s->fill_cap = 0;
+        HIP_TRY(hipMalloc(&s->thr_eff, (size_t)cap * sizeof(int64_t)));
+        HIP_TRY(hipMalloc(&s->table, (size_t)cap * sizeof(FillDev)));
+        HIP_TRY(hipMalloc(&s->hdr, sizeof(BatchHdr)));
+        for (int i = 0; i < kRing; i++) {
+            if (s->ring_used[i]) HIP_TRY(hipEventSynchronize(s->ring_ev[i]));
+            if (s->ring_host[i]) (void)hipHostFree(s->ring_host[i]);
+            s->ring_host[i] = nullptr;
+            s->ring_used[i] = false;
+            HIP_TRY(hipHostMalloc(&s->ring_host[i], sizeof(BatchHdr) + (size_t)cap * sizeof(FillDev),
+                                  hipHostMallocDefault));
+            if (!s->ring_ev[i]) HIP_TRY(hipEventCreateWithFlags(&s->ring_ev[i], hipEventDisableTiming));
+        }
+        s->fill_cap = cap;
+    }
+    return DAQ_OK;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+int check_fill(const daq_fill *f) {
+    if (!f) return DAQ_EINVAL;
+    if (f->reserved != 0) return DAQ_EINVAL;
+    if (f->n_samples < 0 || f->row_stride < f->n_samples) return DAQ_EINVAL;
+    if (f->n_samples > DAQ_MAX_SAMPLES) return DAQ_ERANGE;
+    if (f->n_channels < 1 || f->ped_samples < 1 || f->pre < 0 || f->post < 0) return DAQ_EINVAL;
+    if (f->n_channels > DAQ_MAX_CHANNELS || f->pre > DAQ_MAX_WINDOW || f->post > DAQ_MAX_WINDOW)
+        return DAQ_ERANGE;
+    if (f->row_stride > DAQ_MAX_SAMPLES + 8) return DAQ_ERANGE;
+    if (f->n_samples > 0 && !f->raw) return DAQ_EINVAL;
+    if ((f->row_stride % daqk::kVec) != 0 || !aligned16(f->raw)) return DAQ_EALIGN;
+    return DAQ_OK;
+}
+
+int check_out(const daq_fill_out *o) {
+    if (!o || !o->counts) return DAQ_EINVAL;
+    if (o->capacity < 0 || (o->capacity > 0 && !o->islands)) return DAQ_EINVAL;
+    if (o->out && o->out_stride < 0) return DAQ_EINVAL;
+    return DAQ_OK;
+}
+
+int64_t tiles_of(int64_t n, int threads) {
+    const int64_t T = (int64_t)threads * daqk::kVec;
+    return (n + T - 1) / T;
+}
+
+FillDev make_desc(const daq_fill &f, const daq_fill_out &o, int64_t tile_base, int threads) {
+    FillDev d{};
+    d.raw = f.raw;
+    d.n = f.n_samples;
+    d.stride = f.row_stride;
+    d.C = f.n_channels;
+    d.np = f.ped_samples;
+    d.thr = f.threshold;
+    d.pre = f.pre;
+    d.post = f.post;
+    d.tile_base = tile_base;
+    d.n_tiles = tiles_of(f.n_samples, threads);
+    d.isl = o.islands;
+    d.cap = o.capacity;
+    d.counts = o.counts;
+    d.ped = o.ped;
+    d.out = o.out;
+    d.out_stride = o.out ? o.out_stride : 0;
+    return d;
+}
+
+int chop_grid(const daq_ctx *ctx, const daq_schedule &s, int64_t total_tiles) {
+    int64_t g = s.wgs_per_cu > 0 ? (int64_t)s.wgs_per_cu * ctx->n_cu : total_tiles;
+    g = std::min<int64_t>(std::max<int64_t>(g, 1), total_tiles > 0 ? total_tiles : 1);
+    return (int)std::min<int64_t>(g, 1 << 30);
+}
+
+bool all_resident(const daq_fill *fills, int32_t n) {
+    for (int32_t i = 0; i < n; i++)
+        if (fills[i].n_channels != daqk::kResidentChannels) return false;
+    return true;
+}
+
+int launch_pair(daq_ctx *ctx, const KArgs &a, int64_t total_tiles, hipStream_t stream,
+                bool resident) {
+    const daq_schedule &s = ctx->sched;
+    int prep_blocks = (int)std::min<int64_t>(kPrepareBlocks, std::max<int64_t>(1, (total_tiles + 2047) / 2048));
+    prep_blocks = std::max(prep_blocks, std::min(a.n_fills, kPrepareBlocks));
+    HIP_TRY(daqk::launch_prepare(a, prep_blocks, stream));
+    if (total_tiles == 0) return DAQ_OK;
+    size_t slot = 0;
+    if (ctx->timing) {
+        int rc = timing_begin(ctx, stream, &slot);
+        if (rc) return rc;
+    }
+    HIP_TRY(daqk::launch_chop(a, s.threads, resident, chop_grid(ctx, s, total_tiles), stream));
+    if (ctx->timing) return timing_end(ctx, stream, slot);
+    return DAQ_OK;
+}
+
+// Captures the two kernels of a table-driven launch (sizes read from the
+// device header) into two graph execs bound to this scratch.
+int capture_graphs(daq_ctx *ctx, Scratch *s, bool resident) {
+    free_graphs(s);
+    if (!ctx->capture) HIP_TRY(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+    KArgs a{};
+    a.table = s->table;
+    a.hdr = s->hdr;
+    a.tile_state = s->tile_state;
+    a.ticket = s->ticket;
+    a.thr_eff = s->thr_eff;
+    hipGraph_t g = nullptr;
+    // prepare: grid covers the largest table this scratch holds
+    HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+    hipError_t e = daqk::launch_prepare(a, kPrepareBlocks, ctx->capture);
+    hipError_t e2 = hipStreamEndCapture(ctx->capture, &g);
+    if (e != hipSuccess) return hip_fail(e);
+    if (e2 != hipSuccess) return hip_fail(e2);
+    e = hipGraphInstantiate(&s->g_prep, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e);
+    const daq_schedule &sc = ctx->sched;
+    HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+    e = daqk::launch_chop(a, sc.threads, resident, sc.wgs_per_cu * ctx->n_cu, ctx->capture);
+    e2 = hipStreamEndCapture(ctx->capture, &g);
+    if (e != hipSuccess) return hip_fail(e);
+    if (e2 != hipSuccess) return hip_fail(e2);
+    e = hipGraphInstantiate(&s->g_chop, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e);
+    s->key.threads = sc.threads;
+    s->key.wgs = sc.wgs_per_cu;
+    s->key.resident = resident;
+    s->key.table = s->table;
+    s->key.state = s->tile_state;
+    return DAQ_OK;
+}
+
+// The fused pass over n fills. n == 1 without `force_table` passes the one
+// descriptor in the kernel arguments; otherwise the descriptors go through a
+// pinned staging slot into the device table (and graphs may be replayed).
+int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int32_t n,
+              hipStream_t stream, bool force_table) {
+    if (!ctx || n < 0 || (n > 0 && (!fills || !outs))) return DAQ_EINVAL;
+    for (int32_t i = 0; i < n; i++) {
+        int rc = check_fill(&fills[i]);
+        if (rc) return rc;
+        rc = check_out(&outs[i]);
+        if (rc) return rc;
+    }
+    if (n == 0) return DAQ_OK;
+    DeviceGuard guard(ctx->device);
+    const daq_schedule sc = ctx->sched;
+    const bool resident = sc.resident && all_resident(fills, n);
+    int64_t total = 0;
+    std::vector<int64_t> base((size_t)n);
+    for (int32_t i = 0; i < n; i++) {
+        base[(size_t)i] = total;
+        total += tiles_of(fills[i].n_samples, sc.threads);
+    }
+    Scratch *s = scratch_for(ctx, stream);
+    int rc = ensure_scratch(s, total, n);
+    if (rc) return rc;
+    KArgs a{};
+    a.tile_state = s->tile_state;
+    a.ticket = s->ticket;
+    a.thr_eff = s->thr_eff;
+    a.n_fills = n;
+    a.total_tiles = total;
+    if (n == 1 && !force_table) {
+        a.one = make_desc(fills[0], outs[0], 0, sc.threads);
+        return launch_pair(ctx, a, total, stream, resident);
+    }
+    // stage the descriptors
+    const int rs = s->ring_pos;
+    s->ring_pos = (s->ring_pos + 1) % kRing;
+    if (s->ring_used[rs]) HIP_TRY(hipEventSynchronize(s->ring_ev[rs]));
+    BatchHdr *h = reinterpret_cast<BatchHdr *>(s->ring_host[rs]);
+    FillDev *tab = reinterpret_cast<FillDev *>(h + 1);
+    h->n_fills = n;
+    h->pad = 0;
+    h->total_tiles = total;
+    for (int32_t i = 0; i < n; i++) tab[i] = make_desc(fills[i], outs[i], base[(size_t)i], sc.threads);
+    HIP_TRY(hipMemcpyAsync(s->hdr, h, sizeof(BatchHdr), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(s->table, tab, (size_t)n * sizeof(FillDev), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipEventRecord(s->ring_ev[rs], stream));
+    s->ring_used[rs] = true;
+    a.table = s->table;
+    a.hdr = s->hdr;
+    const bool use_graph = ctx->graphs && sc.wgs_per_cu > 0;
+    if (!use_graph) return launch_pair(ctx, a, total, stream, resident);
+    GraphKey want;
+    want.threads = sc.threads;
+    want.wgs = sc.wgs_per_cu;
+    want.resident = resident;
+    want.table = s->table;
+    want.state = s->tile_state;
+    if (!s->g_chop || !(s->key == want)) {
+        rc = capture_graphs(ctx, s, resident);
+        if (rc) return rc;
+    }
+    HIP_TRY(hipGraphLaunch(s->g_prep, stream));
+    size_t slot = 0;
+    if (ctx->timing) {
+        rc = timing_begin(ctx, stream, &slot);
+        if (rc) return rc;
+    }
+    HIP_TRY(hipGraphLaunch(s->g_chop, stream));
+    if (ctx->timing) return timing_end(ctx, stream, slot);
+    return DAQ_OK;
+}
+
+// ---- autotune ---------------------------------------------------------------
+
+__global__ void k_digest(const FillDev *tab, int n, uint64_t *out) {
+    // order-independent digest of island records, counts and packed samples
+    // of fill blockIdx.y; blocks along x split the packed rows
+    const int f = blockIdx.y;
+    if (f >= n) return;
+    const FillDev d = tab[f];
+    auto mix = [](uint64_t z) {
+        z += 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    uint64_t acc = 0;
+    const int64_t n_isl = d.counts->n_islands;
+    const int64_t tl = d.counts->total_len;
+    const int64_t nrec = n_isl < d.cap ? n_isl : d.cap;
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+    if (gtid == 0) acc += mix(mix((uint64_t)n_isl) ^ mix((uint64_t)tl + 7) ^ (uint64_t)d.counts->status);
+    for (int64_t i = gtid; i < nrec; i += gsz)
+        acc += mix(mix((uint64_t)i * 3 + 1) ^ mix((uint64_t)d.isl[i].start) ^ mix((uint64_t)d.isl[i].stop << 1) ^
+                   mix((uint64_t)d.isl[i].offset << 2));
+    if (d.out) {
+        const int64_t lim = tl < d.out_stride ? tl : d.out_stride;
+        for (int c = 0; c < d.C; c++)
+            for (int64_t p = gtid; p < lim; p += gsz)
+                acc += mix(((uint64_t)c << 40) ^ ((uint64_t)p << 8) ^ mix((uint64_t)(uint16_t)d.out[(int64_t)c * d.out_stride + p]));
+    }
+    for (int dd = 32; dd > 0; dd >>= 1) acc += __shfl_xor(acc, dd, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd((unsigned long long *)&out[f], (unsigned long long)acc);
+}
+
+int digest_batch(daq_ctx *ctx, Scratch *s, int32_t n, hipStream_t stream, std::vector<uint64_t> &host) {
+    if (s->digest_cap < n) {
+        (void)hipFree(s->digest);
+        s->digest = nullptr;
+        HIP_TRY(hipMalloc(&s->digest, (size_t)n * sizeof(uint64_t)));
+        s->digest_cap = n;
+    }
+    HIP_TRY(hipMemsetAsync(s->digest, 0, (size_t)n * sizeof(uint64_t), stream));
+    hipLaunchKernelGGL(k_digest, dim3(64, n), dim3(256), 0, stream, s->table, n, s->digest);
+    HIP_TRY(hipGetLastError());
+    host.assign((size_t)n, 0);
+    HIP_TRY(hipMemcpyAsync(host.data(), s->digest, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    (void)ctx;
+    return DAQ_OK;
+}
+
+std::string shape_key(const daq_ctx *ctx, const daq_fill *fills, int32_t n) {
+    int64_t tot = 0, mx = 0;
+    int cmax = 0, wmax = 0;
+    for (int32_t i = 0; i < n; i++) {
+        tot += fills[i].n_samples;
+        mx = std::max<int64_t>(mx, fills[i].n_samples);
+        cmax = std::max(cmax, fills[i].n_channels);
+        wmax = std::max(wmax, fills[i].pre + fills[i].post);
+    }
+    int lg = 0;
+    while ((int64_t)1 << (lg + 1) <= std::max<int64_t>(tot, 1)) lg++;
+    std::ostringstream o;
+    std::string name = ctx->name;
+    std::replace(name.begin(), name.end(), ' ', '_');
+    o << name << " n" << n << " C" << cmax << " log2N" << lg << " w" << (wmax <= 64 ? 64 : wmax);
+    return o.str();
+}
+
+}  // namespace
+
+// ---- C ABI --------------------------------------------------------------------
+
+extern "C" {
+
+const char *daq_version(void) { return "libdaqisland 1.0 (gfx950)"; }
+
+const char *daq_strerror(int code) {
+    switch (code) {
+        case DAQ_OK: return "ok";
+        case DAQ_EINVAL: return "invalid argument";
+        case DAQ_EALIGN: return "raw base not 16-byte aligned or row stride not a multiple of 8";
+        case DAQ_EHIP: return "HIP runtime error";
+        case DAQ_ENOMEM: return "out of memory";
+        case DAQ_EAGAIN: return "resource busy, try again";
+        case DAQ_ERANGE: return "size exceeds a documented limit";
+        case DAQ_EMISMATCH: return "autotune candidates produced different results";
+        default: return "unknown error";
+    }
+}
+
+int daq_last_hip_error(void) { return g_last_hip; }
+
+int64_t daq_max_islands(int64_t n_samples, int32_t pre, int32_t post) {
+    if (pre < 0 || post < 0) return -1;
+    if (n_samples <= 0) return 0;
+    return (n_samples - 1) / ((int64_t)pre + (int64_t)post + 2) + 1;
+}
+
+int daq_ctx_create(daq_ctx **out, int device) {
+    if (!out) return DAQ_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return DAQ_EINVAL;
+    DeviceGuard guard(device);
+    daq_ctx *c = new daq_ctx();
+    c->device = device;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e);
+    }
+    c->n_cu = prop.multiProcessorCount;
+    c->name = prop.gcnArchName;
+    *out = c;
+    return DAQ_OK;
+}
+
+void daq_ctx_destroy(daq_ctx *ctx) {
+    if (!ctx) return;
+    DeviceGuard guard(ctx->device);
+    for (Scratch *s : ctx->scratch) {
+        (void)hipStreamSynchronize(s->stream);
+        free_scratch(s);
+    }
+    if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
+    for (hipEvent_t e : ctx->ev_start) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->ev_stop) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+int daq_find_islands(daq_ctx *ctx, const daq_fill *fill, daq_island *d_islands, int64_t capacity,
+                     daq_counts *d_counts, int32_t *d_ped, void *stream) {
+    daq_fill_out o{};
+    o.islands = d_islands;
+    o.capacity = capacity;
+    o.counts = d_counts;
+    o.ped = d_ped;
+    o.out = nullptr;
+    o.out_stride = 0;
+    return run_fused(ctx, fill, &o, 1, (hipStream_t)stream, false);
+}
+
+int daq_gather_islands(daq_ctx *ctx, const daq_fill *fill, const daq_island *d_islands, int64_t capacity,
+                       daq_counts *d_counts, int16_t *d_out, int64_t out_stride, void *stream) {
+    if (!ctx) return DAQ_EINVAL;
+    int rc = check_fill(fill);
+    if (rc) return rc;
+    if (!d_counts || !d_out || out_stride < 0 || capacity < 0 || (capacity > 0 && !d_islands))
+        return DAQ_EINVAL;
+    if (capacity == 0 || fill->n_samples == 0) return DAQ_OK;
+    DeviceGuard guard(ctx->device);
+    GatherArgs g{};
+    g.raw = fill->raw;
+    g.stride = fill->row_stride;
+    g.C = fill->n_channels;
+    g.isl = d_islands;
+    g.cap = capacity;
+    g.counts = d_counts;
+    g.out = d_out;
+    g.out_stride = out_stride;
+    const int64_t most = std::min<int64_t>(fill->n_samples, out_stride);
+    int grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * 4, std::max<int64_t>(1, (most + 2047) / 2048));
+    HIP_TRY(daqk::launch_gather(g, grid, (hipStream_t)stream));
+    return DAQ_OK;
+}
+
+int daq_chop_fill(daq_ctx *ctx, const daq_fill *fill, const daq_fill_out *out, void *stream) {
+    return run_fused(ctx, fill, out, 1, (hipStream_t)stream, false);
+}
+
+int daq_process_batch(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int32_t n,
+                      void *stream) {
+    return run_fused(ctx, fills, outs, n, (hipStream_t)stream, true);
+}
+
+int daq_ctx_set_schedule(daq_ctx *ctx, const daq_schedule *s) {
+    if (!ctx || !s) return DAQ_EINVAL;
+    if ((s->threads != 256 && s->threads != 512) || s->wgs_per_cu < 0 || s->wgs_per_cu > 16 ||
+        (s->resident != 0 && s->resident != 1) || s->reserved != 0)
+        return DAQ_EINVAL;
+    ctx->sched = *s;
+    return DAQ_OK;
+}
+
+int daq_ctx_get_schedule(daq_ctx *ctx, daq_schedule *s) {
+    if (!ctx || !s) return DAQ_EINVAL;
+    *s = ctx->sched;
+    return DAQ_OK;
+}
+
+int daq_ctx_set_graphs(daq_ctx *ctx, int enable) {
+    if (!ctx) return DAQ_EINVAL;
+    ctx->graphs = enable != 0;
+    return DAQ_OK;
+}
+
+int daq_ctx_set_timing(daq_ctx *ctx, int enable) {
+    if (!ctx) return DAQ_EINVAL;
+    ctx->timing = enable != 0;
+    ctx->t_read = ctx->t_next;
+    return DAQ_OK;
+}
+
+int daq_ctx_kernel_times(daq_ctx *ctx, float *ms, int32_t max) {
+    if (!ctx || max < 0 || (max > 0 && !ms)) return DAQ_EINVAL;
+    DeviceGuard guard(ctx->device);
+    int32_t n = 0;
+    while (ctx->t_read < ctx->t_next && n < max) {
+        const size_t i = (size_t)(ctx->t_read % kMaxTimed);
+        HIP_TRY(hipEventSynchronize(ctx->ev_stop[i]));
+        HIP_TRY(hipEventElapsedTime(&ms[n], ctx->ev_start[i], ctx->ev_stop[i]));
+        n++;
+        ctx->t_read++;
+    }
+    return n;
+}
+
+int daq_ctx_kernel_time(daq_ctx *ctx, float *ms) {
+    if (!ctx || !ms) return DAQ_EINVAL;
+    if (ctx->t_next == 0 || ctx->t_read >= ctx->t_next) return DAQ_EINVAL;
+    DeviceGuard guard(ctx->device);
+    const size_t i = (size_t)((ctx->t_next - 1) % kMaxTimed);
+    HIP_TRY(hipEventSynchronize(ctx->ev_stop[i]));
+    HIP_TRY(hipEventElapsedTime(ms, ctx->ev_start[i], ctx->ev_stop[i]));
+    ctx->t_read = ctx->t_next;
+    return DAQ_OK;
+}
+
+int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int32_t n, void *stream,
+                 const char *cache_path, daq_schedule *best) {
+    if (!ctx || n <= 0 || !fills || !outs) return DAQ_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const std::string key = shape_key(ctx, fills, n);
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            const size_t bar = line.find('|');
+            if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+            daq_schedule s{};
+            if (sscanf(line.c_str() + bar + 1, "%d %d %d", &s.threads, &s.wgs_per_cu, &s.resident) == 3 &&
+                daq_ctx_set_schedule(ctx, &s) == DAQ_OK) {
+                if (best) *best = s;
+                return DAQ_OK;
+            }
+        }
+    }
+    std::vector<daq_schedule> cand;
+    const bool res_ok = all_resident(fills, n);
+    for (int threads : {256, 512})
+        for (int wgs : {1, 2, 4, 8})
+            for (int res : {0, 1}) {
+                if (res && !res_ok) continue;
+                if (threads * wgs > 2048) continue;  // a CU holds at most 32 waves
+                cand.push_back(daq_schedule{threads, wgs, res, 0});
+            }
+    const daq_schedule saved = ctx->sched;
+    const bool saved_timing = ctx->timing;
+    ctx->timing = true;
+    DeviceGuard guard(ctx->device);
+    std::vector<uint64_t> ref, dig;
+    float best_ms = 1e30f;
+    daq_schedule best_s = saved;
+    int rc = DAQ_OK;
+    for (size_t k = 0; k < cand.size() && rc == DAQ_OK; k++) {
+        ctx->sched = cand[k];
+        rc = run_fused(ctx, fills, outs, n, st, true);  // warm-up (and capture)
+        if (rc) break;
+        Scratch *s = scratch_for(ctx, st);
+        rc = digest_batch(ctx, s, n, st, dig);
+        if (rc) break;
+        if (k == 0) ref = dig;
+        else if (dig != ref) {
+            rc = DAQ_EMISMATCH;
+            break;
+        }
+        float tot = 0.f;
+        const int reps = 5;
+        for (int r = 0; r < reps && rc == DAQ_OK; r++) {
+            rc = run_fused(ctx, fills, outs, n, st, true);
+            float ms = 0.f;
+            if (!rc) rc = daq_ctx_kernel_time(ctx, &ms);
+            tot += ms;
+        }
+        if (!rc && tot / reps < best_ms) {
+            best_ms = tot / reps;
+            best_s = cand[k];
+        }
+    }
+    ctx->timing = saved_timing;
+    ctx->t_read = ctx->t_next;
+    if (rc) {
+        ctx->sched = saved;
+        return rc;
+    }
+    ctx->sched = best_s;
+    if (best) *best = best_s;
+    if (cache_path) {
+        std::ofstream o(cache_path, std::ios::app);
+        o << key << "|" << best_s.threads << " " << best_s.wgs_per_cu << " " << best_s.resident << " "
+          << best_ms << "\n";
+    }
+    return DAQ_OK;
+}
+
+}  // extern "C"

@@ -176,3 +176,20 @@ def config_c4(n_fills: int = 4, n_calos: int = 24) -> List[FillSpec]:
     10x rate, thr -100, post 48; every calorimeter is its own 54-channel unit."""
     return [FillSpec(seed=fill_seed("c4", cal, f), rate=10.0, threshold=-100, pre=8, post=48)
             for f in range(n_fills) for cal in range(n_calos)]
+
+
+# ---------------------------------------------------------------------------
+# Staging: host arrays for a list of fills, and their device copies.
+# ---------------------------------------------------------------------------
+
+def render_many(specs: List[FillSpec], nthreads: Optional[int] = None) -> List[np.ndarray]:
+    """One host array [54, row_stride] per spec."""
+    return [render(s, nthreads=nthreads) for s in specs]
+
+
+def to_device(arrays: List[np.ndarray], device="cuda"):
+    """Device copies (torch.int16, same shape); synchronises the copies."""
+    import torch
+    out = [torch.from_numpy(a).to(device) for a in arrays]
+    torch.cuda.synchronize()
+    return out

@@ -1,0 +1,74 @@
+"""The C ABI library loads and exports every call include/daq.h declares
+(CPU only: nothing here launches GPU work)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1611_04959_amd as daq
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "daq.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(daq_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("daq_find_islands", "daq_gather_islands", "daq_chop_fill", "daq_process_batch",
+                     "daq_max_islands", "daq_ctx_create", "daq_ctx_destroy", "daq_autotune"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = daq.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", daq.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (daq_[a-z_0-9]+)$", out, flags=re.M))
+    assert set(declared_functions()) <= exported
+
+
+def test_library_is_built_for_gfx950_only():
+    # the offload bundle names each device target it carries
+    blob = open(daq.LIB_PATH, "rb").read()
+    targets = set(re.findall(rb"hipv4-amdgcn-amd-amdhsa--(gfx[0-9a-z]+)", blob))
+    assert targets == {b"gfx950"}
+
+
+def test_version_and_strerror():
+    assert "gfx950" in daq.version()
+    lib = daq.load_library()
+    for code in range(-8, 1):
+        assert lib.daq_strerror(code)
+
+
+def test_max_islands_bound():
+    for N, pre, post in ((0, 8, 24), (1, 8, 24), (560_000, 8, 24), (100, 0, 0), (7, 1, 1)):
+        expect = 0 if N <= 0 else (N - 1) // (pre + post + 2) + 1
+        assert daq.daq_max_islands(N, pre, post) == expect
+    assert daq.daq_max_islands(10, -1, 0) == -1
+    # the configuration bound quoted for the plain workload
+    assert daq.daq_max_islands(560_000, 8, 24) == 16_471
+
+
+def test_null_context_is_rejected_without_touching_a_gpu():
+    lib = daq.load_library()
+    f = daq.daq_fill(0, 0, 0, 1, 100, -200, 8, 24, 0)
+    rc = lib.daq_find_islands(None, ctypes.byref(f), None, 0, None, None, None)
+    assert rc == daq.DAQ_EINVAL
+    rc = lib.daq_process_batch(None, None, None, 0, None)
+    assert rc == daq.DAQ_EINVAL
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(daq.daq_fill) == 48
+    assert ctypes.sizeof(daq.daq_fill_out) == 48
+    assert ctypes.sizeof(daq.daq_schedule) == 16
