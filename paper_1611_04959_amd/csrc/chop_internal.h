@@ -27,7 +27,11 @@ struct FillDev {
     int32_t thr;
     int32_t pre;
     int32_t post;
-    int32_t pad0;
+    int32_t gl;         // halo groups of 8 samples left of a tile: ceil((post + 1) / 8)
+    int32_t gr;         // halo groups right of a tile: ceil((pre + 1) / 8)
+    int32_t wide;       // 0: halo groups are ordinary thread groups of the tile;
+                        // 1: extra groups loaded by a separate loop (wide windows)
+    int64_t tout;       // samples a tile owns (decides and writes)
     int64_t tile_base;  // global index of the fill's first tile in the launch
     int64_t n_tiles;
     daq_island *isl;
@@ -69,6 +73,22 @@ struct GatherArgs {
     int16_t *out;
     int64_t out_stride;
 };
+
+// Tile geometry of one fill for a work-group of `threads`: halo groups, mode
+// and the samples each tile owns. Windows up to a quarter of the work-group
+// keep the halo inside the work-group's own groups.
+struct TileShape {
+    int32_t gl, gr, wide;
+    int64_t tout;
+};
+inline TileShape tile_shape(int32_t pre, int32_t post, int threads) {
+    TileShape t;
+    t.gl = (post + 1 + kVec - 1) / kVec;
+    t.gr = (pre + 1 + kVec - 1) / kVec;
+    t.wide = (t.gl + t.gr) * 4 > threads ? 1 : 0;
+    t.tout = (int64_t)(t.wide ? threads : threads - t.gl - t.gr) * kVec;
+    return t;
+}
 
 hipError_t launch_prepare(const KArgs &a, int blocks, hipStream_t s);
 hipError_t launch_chop(const KArgs &a, int threads, bool resident, int grid, hipStream_t s);

@@ -6,19 +6,23 @@
 //
 // k_prepare  per fill: pedestals (Table 2 pedestal row) and the effective
 //            threshold thr + sum(ped); clears the look-back words.
-// k_chop     the fused pass. A work-group owns a tile of T = threads x 8
-//            consecutive samples of every channel of one fill:
-//              1. 16-byte loads of each channel row, int32 sums per sample
-//                 (Table 2 waveform-sum row), compare (threshold row) ->
-//                 one flag bit per sample, written to an LDS bitmap that also
-//                 covers a halo of post + 1 samples on the left and pre + 1 on
-//                 the right (flags there are recomputed from the raw data);
+// k_chop     the fused pass. Each thread of a work-group takes 8 consecutive
+//            samples (one 16-byte load per channel row); the work-group's
+//            groups cover a tile of the fill plus a halo of post + 1 samples
+//            on the left and pre + 1 on the right, whose flags are recomputed
+//            from the raw data (wide windows load the halo in a separate
+//            loop instead). Per tile:
+//              1. int32 sums per sample over all channels (Table 2 waveform-
+//                 sum row), compare (threshold row) -> one flag bit per
+//                 sample in an LDS bitmap;
 //              2. dilation (pre/post row) as "some flag in [t - post, t + pre]"
 //                 via popcount prefixes of the bitmap; island edges follow;
 //              3. a decoupled look-back over the fill's earlier tiles gives
 //                 the number of island samples and islands before the tile;
 //              4. island records (island-array row) and, when requested, the
-//                 packed raw samples of every channel (the chopped islands).
+//                 packed raw samples of every channel (the chopped islands),
+//                 staged through LDS so that the global stores are whole,
+//                 aligned 16-byte chunks.
 //            Each record field has exactly one writer: the tile holding an
 //            island's first sample writes start and offset, the tile holding
 //            its last sample writes stop. No second pass is needed.
@@ -52,12 +56,6 @@ __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v, int lane) {
 }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
-}
-
-__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
     return v;
@@ -113,12 +111,24 @@ __device__ uint32_t group_flags(const int16_t *p, int64_t stride, int C, int32_t
     return flags8(s, thr_eff, valid);
 }
 
-// Number of set bits of the LDS bitmap below bit q.
-__device__ __forceinline__ uint32_t prefix_bits(const uint64_t *words, const uint32_t *pc, int q) {
-    const int w = q >> 6;
-    const int b = q & 63;
-    const uint64_t below = b ? (words[w] & ((1ull << b) - 1ull)) : 0ull;
-    return pc[w] + (uint32_t)__popcll(below);
+// Set bits of the LDS bitmap below bit x0 + j, for j = 0 .. 9 (the window
+// of ten consecutive prefix counts one thread needs; x0 + 9 <= 64 * Wn).
+__device__ __forceinline__ void prefix_bits10(const uint64_t *words, const uint32_t *pc, int x0,
+                                              uint32_t (&out)[10]) {
+    const int w = x0 >> 6;
+    const int b = x0 & 63;
+    const uint64_t w0 = words[w];
+    const uint64_t w1 = words[w + 1];
+    const uint32_t base = pc[w];
+    const uint32_t all0 = (uint32_t)__popcll(w0);
+#pragma unroll
+    for (int j = 0; j < 10; j++) {
+        const int q = b + j;
+        uint32_t c;
+        if (q < 64) c = (uint32_t)__popcll(q ? (w0 & ((1ull << q) - 1ull)) : 0ull);
+        else c = all0 + (uint32_t)__popcll((q - 64) ? (w1 & ((1ull << (q - 64)) - 1ull)) : 0ull);
+        out[j] = base + c;
+    }
 }
 
 // Sum of the published values of this fill's tiles [0, lt): the exclusive
@@ -146,65 +156,121 @@ __device__ uint64_t look_back(uint64_t *st, int64_t lt, int lane) {
     }
 }
 
-// Packed-output store of a thread's 8 samples of one channel row.
-__device__ __forceinline__ void store_packed(int16_t *orow, int64_t pos0, uint32_t mm,
-                                             const uint4 v, int64_t ostride) {
+// Puts the island samples (mask mm) of one 8-sample chunk into an LDS row at
+// index idx0 onwards, packed. Dense chunks use the widest aligned stores.
+__device__ __forceinline__ void stage_put(int16_t *row, int idx0, uint32_t mm, const uint4 v) {
     const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-    if (mm == 0xFFu && pos0 + kVec <= ostride) {
-        int16_t *dst = orow + pos0;
-        const uintptr_t addr = reinterpret_cast<uintptr_t>(dst);
-        if ((addr & 15u) == 0) {
-            *reinterpret_cast<uint4 *>(dst) = v;
-            return;
-        }
-        if ((addr & 3u) == 0) {
+    if (mm == 0xFFu) {
+        if ((idx0 & 7) == 0) {
+            *reinterpret_cast<uint4 *>(row + idx0) = v;
+        } else if ((idx0 & 1) == 0) {
 #pragma unroll
-            for (int i = 0; i < 4; i++) reinterpret_cast<uint32_t *>(dst)[i] = w[i];
-            return;
+            for (int i = 0; i < 4; i++) reinterpret_cast<uint32_t *>(row + idx0)[i] = w[i];
+        } else {
+            row[idx0] = (int16_t)(w[0] & 0xFFFFu);
+            uint32_t *d = reinterpret_cast<uint32_t *>(row + idx0 + 1);
+            d[0] = (w[1] << 16) | (w[0] >> 16);
+            d[1] = (w[2] << 16) | (w[1] >> 16);
+            d[2] = (w[3] << 16) | (w[2] >> 16);
+            row[idx0 + 7] = (int16_t)(w[3] >> 16);
         }
+        return;
     }
-    int64_t pos = pos0;
+    int idx = idx0;
 #pragma unroll
     for (int k = 0; k < kVec; k++) {
         if ((mm >> k) & 1u) {
-            if (pos < ostride) {
-                const uint32_t word = w[k >> 1];
-                orow[pos] = (int16_t)((k & 1) ? (word >> 16) : (word & 0xFFFFu));
-            }
-            pos++;
+            const uint32_t word = w[k >> 1];
+            row[idx++] = (int16_t)((k & 1) ? (word >> 16) : (word & 0xFFFFu));
         }
     }
 }
 
+// Element offset of a row's packed position `pos` within its 16-byte line.
+__device__ __forceinline__ int line_phase(const int16_t *row, int64_t pos) {
+    return (int)((((uintptr_t)row >> 1) + (uint64_t)pos) & 7u);
+}
+
+// Writes `len` staged samples of up to CB channel rows [c0, c0 + CB) to the
+// packed output at position m0: LDS row cl holds element j at index
+// phase(row, m0) + j, so every full 16-byte LDS chunk maps onto one aligned
+// 16-byte global chunk.
+template <int NT, int CB>
+__device__ __forceinline__ void stage_flush(const int16_t *stage, int rs, int16_t *out, int64_t ostride,
+                                            int c0, int C, int64_t m0, int len) {
+    const int nch = (len + 7 + 7) >> 3;
+    for (int i = threadIdx.x; i < CB * nch; i += NT) {
+        const int cl = i / nch;
+        const int q = i - cl * nch;
+        const int c = c0 + cl;
+        if (c >= C) continue;
+        int16_t *row = out + (int64_t)c * ostride;
+        const int ph = line_phase(row, m0);
+        const int j0 = q * 8 - ph;  // element of chunk lane 0
+        if (j0 >= len) continue;
+        const int16_t *src = stage + cl * rs + q * 8;
+        const int64_t g0 = m0 + j0;
+        if (j0 >= 0 && j0 + 8 <= len && g0 + 8 <= ostride) {
+            *reinterpret_cast<uint4 *>(row + g0) = *reinterpret_cast<const uint4 *>(src);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int j = j0 + e;
+                if (j >= 0 && j < len && m0 + j < ostride) row[m0 + j] = src[e];
+            }
+        }
+    }
+}
+
+template <int NT>
+struct ChopLds {
+    static constexpr int kGroups = 2 * kMaxHaloGroups + NT;  // widest bitmap
+    static constexpr int kWords = (kGroups + 7) / 8 + 1;
+    static constexpr int kBitsBytes = kWords * 8 + (kWords + 1) * 4;
+    static constexpr int kCB = NT == 256 ? 8 : 4;            // channels staged per round
+    static constexpr int kRowStride = NT * kVec + 16;        // elements per staged row
+    static constexpr int kStageBytes = kCB * kRowStride * 2;
+    static constexpr int kBytes = kBitsBytes > kStageBytes ? kBitsBytes : kStageBytes;
+};
+
 template <int NT, bool RESIDENT>
-__device__ __forceinline__ void chop_tile(const KArgs &a, const FillDev &fd, int f, int64_t tile, uint8_t *s_bits,
-                          uint32_t *s_pc, uint32_t *s_wsum, uint64_t *s_excl) {
-    constexpr int T = NT * kVec;
+__device__ __forceinline__ void chop_tile(const KArgs &a, const FillDev &fd, int f, int64_t tile, uint8_t *lds,
+                                          uint32_t *s_wsum, uint64_t *s_excl) {
     constexpr int NW = NT / 64;
     constexpr int CR = RESIDENT ? kResidentChannels : 1;
+    constexpr int CB = ChopLds<NT>::kCB;
+    constexpr int RS = ChopLds<NT>::kRowStride;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
 
     const int64_t lt = tile - fd.tile_base;
-    const int64_t t0 = lt * T;
     const int64_t N = fd.n;
-    const int C = fd.C;
+    const int C = RESIDENT ? kResidentChannels : fd.C;
     const int64_t stride = fd.stride;
     const int16_t *raw = fd.raw;
-    const int gl = (fd.post + 1 + kVec - 1) / kVec;  // left halo groups
-    const int gr = (fd.pre + 1 + kVec - 1) / kVec;   // right halo groups
-    const int G = gl + NT + gr;
-    const int64_t base = t0 - (int64_t)gl * kVec;    // sample at bitmap bit 0
+    const int gl = fd.gl;
+    const int gr = fd.gr;
+    const bool wide = fd.wide != 0;
+    const int G = wide ? gl + NT + gr : NT;           // bitmap groups
+    const int64_t t0 = lt * fd.tout;                  // first sample the tile owns
+    const int64_t base = t0 - (int64_t)gl * kVec;     // sample at bitmap bit 0
+    const int g = wide ? gl + tid : tid;              // this thread's group
+    const bool owner = wide || (tid >= gl && tid < NT - gr);
+    const int64_t p = base + (int64_t)g * kVec;       // its first sample
     int64_t te = a.thr_eff[f];
     te = te > 2147483647LL ? 2147483647LL : (te < -2147483648LL ? -2147483648LL : te);
     const int32_t thr_eff = (int32_t)te;
 
-    // 1a. main group: 8 samples of every channel
-    const int64_t p = t0 + (int64_t)tid * kVec;
+    uint8_t *s_bits = lds;
+    uint32_t *s_pc = reinterpret_cast<uint32_t *>(lds + ChopLds<NT>::kWords * 8);
+    int16_t *s_stage = reinterpret_cast<int16_t *>(lds);
+
+    // 1. flags of this thread's 8 samples from all channel rows (Table 2
+    //    waveform-sum and threshold rows); halo groups of wide windows apart
     uint4 xr[CR];
     uint32_t fb = 0;
-    if (p < N) {
+    if (p >= 0 && p < N) {
         if constexpr (RESIDENT) {
 #pragma unroll
             for (int c = 0; c < kResidentChannels; c++) xr[c] = load16(raw + p + (int64_t)c * stride);
@@ -216,17 +282,18 @@ __device__ __forceinline__ void chop_tile(const KArgs &a, const FillDev &fd, int
             fb = group_flags(raw + p, stride, C, thr_eff, N - p);
         }
     }
-    s_bits[gl + tid] = (uint8_t)fb;
-    // 1b. halo groups (flags only)
-    for (int h = tid; h < gl + gr; h += NT) {
-        const int g = (h < gl) ? h : (NT + h);
-        const int64_t q = base + (int64_t)g * kVec;
-        uint32_t hb = 0;
-        if (q >= 0 && q < N) hb = group_flags(raw + q, stride, C, thr_eff, N - q);
-        s_bits[g] = (uint8_t)hb;
+    s_bits[g] = (uint8_t)fb;
+    if (wide) {
+        for (int h = tid; h < gl + gr; h += NT) {
+            const int hg = (h < gl) ? h : (NT + h);
+            const int64_t q = base + (int64_t)hg * kVec;
+            uint32_t hb = 0;
+            if (q >= 0 && q < N) hb = group_flags(raw + q, stride, C, thr_eff, N - q);
+            s_bits[hg] = (uint8_t)hb;
+        }
     }
     const int Wn = (G + 7) >> 3;  // bitmap words; word Wn stays zero
-    for (int g = G + tid; g < (Wn + 1) * 8; g += NT) s_bits[g] = 0;
+    for (int z = G + tid; z < (Wn + 1) * 8; z += NT) s_bits[z] = 0;
     __syncthreads();
 
     // 2a. exclusive popcount prefix over the bitmap words (wave 0)
@@ -243,17 +310,19 @@ __device__ __forceinline__ void chop_tile(const KArgs &a, const FillDev &fd, int
     }
     __syncthreads();
 
-    // 2b. dilated mask for samples p-1 .. p+8 and island edges of p .. p+7
+    // 2b. dilation (Table 2 pre/post row): sample t is inside an island when
+    //     a flag lies in [t - post, t + pre]; masks for p-1 .. p+8
     uint32_t m10 = 0;
-    {
-        const int r0 = (gl + tid) * kVec;
+    if (owner) {
+        const int r0 = g * kVec;
+        uint32_t lo[10], hi[10];
+        prefix_bits10(words, s_pc, r0 - 1 - fd.post, lo);
+        prefix_bits10(words, s_pc, r0 + fd.pre, hi);
 #pragma unroll
-        for (int k = -1; k <= kVec; k++) {
-            const int64_t t = p + k;
-            const uint32_t lo = prefix_bits(words, s_pc, r0 + k - fd.post);
-            const uint32_t hi = prefix_bits(words, s_pc, r0 + k + fd.pre + 1);
-            const bool in = (hi != lo) && t >= 0 && t < N;
-            m10 |= (in ? 1u : 0u) << (k + 1);
+        for (int j = 0; j < 10; j++) {
+            const int64_t t = p + j - 1;
+            const bool in = (hi[j] != lo[j]) && t >= 0 && t < N;
+            m10 |= (in ? 1u : 0u) << j;
         }
     }
     const uint32_t mm = (m10 >> 1) & 0xFFu;
@@ -273,7 +342,7 @@ __device__ __forceinline__ void chop_tile(const KArgs &a, const FillDev &fd, int
         total += v;
     }
     const uint32_t excl = before + inc - mine;
-    const int64_t th_m = excl >> 16, th_i = excl & 0xFFFFu;
+    const int th_m = (int)(excl >> 16), th_i = (int)(excl & 0xFFFFu);
     const uint64_t tile_m = total >> 16, tile_i = total & 0xFFFFu;
 
     // 3. decoupled look-back over the fill's earlier tiles (wave 0)
@@ -298,7 +367,7 @@ __device__ __forceinline__ void chop_tile(const KArgs &a, const FillDev &fd, int
     const int64_t mbase = m_before + th_m;  // packed position of this thread's first island sample
     const int64_t ibase = i_before + th_i;  // islands starting before this thread's samples
 
-    // 4a. island records
+    // 4a. island records (Table 2 island-array row)
     if (rise | fall) {
         daq_island *isl = fd.isl;
         const int64_t cap = fd.cap;
@@ -318,17 +387,47 @@ __device__ __forceinline__ void chop_tile(const KArgs &a, const FillDev &fd, int
         }
     }
 
-    // 4b. packed raw samples of every channel (chopped islands)
-    if (fd.out != nullptr && mm != 0) {
+    // 4b. chopped islands: the packed raw samples of every channel, staged in
+    //     LDS per CB channels so that global stores are aligned 16-byte lines
+    if (fd.out != nullptr && tile_m > 0) {
+        int16_t *out = fd.out;
         const int64_t ostride = fd.out_stride;
+        const int len = (int)tile_m;
         if constexpr (RESIDENT) {
 #pragma unroll
-            for (int c = 0; c < kResidentChannels; c++)
-                store_packed(fd.out + (int64_t)c * ostride, mbase, mm, xr[c], ostride);
+            for (int c0 = 0; c0 < kResidentChannels; c0 += CB) {
+                if (mm) {
+#pragma unroll
+                    for (int cl = 0; cl < CB; cl++) {
+                        if (c0 + cl < kResidentChannels) {
+                            const int ph = line_phase(out + (int64_t)(c0 + cl) * ostride, m_before);
+                            stage_put(s_stage + cl * RS, ph + th_m, mm, xr[c0 + cl]);
+                        }
+                    }
+                }
+                __syncthreads();
+                stage_flush<NT, CB>(s_stage, RS, out, ostride, c0, kResidentChannels, m_before, len);
+                __syncthreads();
+            }
         } else {
-            for (int c = 0; c < C; c++)
-                store_packed(fd.out + (int64_t)c * ostride, mbase, mm, load16(raw + p + (int64_t)c * stride),
-                             ostride);
+            for (int c0 = 0; c0 < C; c0 += CB) {
+                if (mm) {
+                    uint4 v[CB];
+#pragma unroll
+                    for (int cl = 0; cl < CB; cl++)
+                        if (c0 + cl < C) v[cl] = load16(raw + p + (int64_t)(c0 + cl) * stride);
+#pragma unroll
+                    for (int cl = 0; cl < CB; cl++) {
+                        if (c0 + cl < C) {
+                            const int ph = line_phase(out + (int64_t)(c0 + cl) * ostride, m_before);
+                            stage_put(s_stage + cl * RS, ph + th_m, mm, v[cl]);
+                        }
+                    }
+                }
+                __syncthreads();
+                stage_flush<NT, CB>(s_stage, RS, out, ostride, c0, C, m_before, len);
+                __syncthreads();
+            }
         }
     }
 
@@ -345,16 +444,9 @@ __device__ __forceinline__ void chop_tile(const KArgs &a, const FillDev &fd, int
     }
 }
 
-template <int NT>
-struct ChopLds {
-    static constexpr int kGroups = 2 * kMaxHaloGroups + NT;
-    static constexpr int kWords = (kGroups + 7) / 8 + 1;
-};
-
 template <int NT, bool RESIDENT>
 __global__ void __launch_bounds__(NT) k_chop(KArgs a) {
-    __shared__ __align__(16) uint8_t s_bits[ChopLds<NT>::kWords * 8];
-    __shared__ uint32_t s_pc[ChopLds<NT>::kWords + 1];
+    __shared__ __align__(16) uint8_t s_lds[ChopLds<NT>::kBytes];
     __shared__ uint32_t s_wsum[NT / 64];
     __shared__ uint64_t s_excl;
     __shared__ int64_t s_tile;
@@ -375,39 +467,55 @@ __global__ void __launch_bounds__(NT) k_chop(KArgs a) {
         }
         const FillDev fd = fill_at(a, lo);
         if (RESIDENT && fd.C == kResidentChannels)
-            chop_tile<NT, RESIDENT>(a, fd, lo, tile, s_bits, s_pc, s_wsum, &s_excl);
+            chop_tile<NT, RESIDENT>(a, fd, lo, tile, s_lds, s_wsum, &s_excl);
         else
-            chop_tile<NT, false>(a, fd, lo, tile, s_bits, s_pc, s_wsum, &s_excl);
+            chop_tile<NT, false>(a, fd, lo, tile, s_lds, s_wsum, &s_excl);
         __syncthreads();
     }
 }
 
+// Pedestals (Table 2 pedestal row), effective thresholds, cleared look-back
+// words and counts. A block handles whole fills; its threads take
+// (channel, 8-sample chunk) pairs of the pedestal window with 16-byte loads.
 __global__ void __launch_bounds__(256) k_prepare(KArgs a) {
-    __shared__ unsigned long long s_ped;
+    constexpr int kChan = 512;  // channels accumulated per round
+    __shared__ long long s_acc[kChan];
+    __shared__ long long s_ped;
     const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
     const int64_t total = a.hdr ? a.hdr->total_tiles : a.total_tiles;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256)
         a.tile_state[i] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.ticket = 0;
-    const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
     for (int f = blockIdx.x; f < nf; f += gridDim.x) {
         const FillDev fd = fill_at(a, f);
-        if (threadIdx.x == 0) s_ped = 0;
-        __syncthreads();
         const int64_t n = fd.n < (int64_t)fd.np ? fd.n : (int64_t)fd.np;
-        for (int c = wid; c < fd.C; c += 4) {
-            const int16_t *row = fd.raw + (int64_t)c * fd.stride;
-            int64_t P = 0;
-            for (int64_t t = lane; t < n; t += 64) P += row[t];
-            P = wave_sum_i64(P);
-            if (lane == 0) {
-                const int32_t ped = n > 0 ? (int32_t)floor_div(2 * P + n, 2 * n) : 0;
-                if (fd.ped) fd.ped[c] = ped;
-                atomicAdd(&s_ped, (unsigned long long)(int64_t)ped);
+        const int64_t nch = (n + kVec - 1) / kVec;
+        if (threadIdx.x == 0) s_ped = 0;
+        for (int c0 = 0; c0 < fd.C; c0 += kChan) {
+            const int cn = fd.C - c0 < kChan ? fd.C - c0 : kChan;
+            for (int i = threadIdx.x; i < cn; i += 256) s_acc[i] = 0;
+            __syncthreads();
+            const int64_t items = (int64_t)cn * nch;
+            for (int64_t i = threadIdx.x; i < items; i += 256) {
+                const int cl = (int)(i / nch);
+                const int64_t t = (i - (int64_t)cl * nch) * kVec;
+                const uint4 v = load16(fd.raw + (int64_t)(c0 + cl) * fd.stride + t);
+                int32_t s[kVec] = {0, 0, 0, 0, 0, 0, 0, 0};
+                add8(s, v);
+                int32_t part = 0;
+#pragma unroll
+                for (int k = 0; k < kVec; k++) part += (t + k < n) ? s[k] : 0;
+                atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[cl]),
+                          (unsigned long long)(long long)part);
             }
+            __syncthreads();
+            for (int i = threadIdx.x; i < cn; i += 256) {
+                const int32_t ped = n > 0 ? (int32_t)floor_div(2 * (int64_t)s_acc[i] + n, 2 * n) : 0;
+                if (fd.ped) fd.ped[c0 + i] = ped;
+                atomicAdd(reinterpret_cast<unsigned long long *>(&s_ped), (unsigned long long)(long long)ped);
+            }
+            __syncthreads();
         }
-        __syncthreads();
         if (threadIdx.x == 0) {
             a.thr_eff[f] = (int64_t)fd.thr + (int64_t)s_ped;
             if (fd.counts) {

@@ -41,7 +41,7 @@ int hip_fail(hipError_t e) {
     } while (0)
 
 constexpr int kRing = 4;          // pinned staging slots per stream
-constexpr int kPrepareBlocks = 64;
+constexpr int kPrepareBlocks = 1024;
 
 struct GraphKey {
     int threads = 0, wgs = 0, resident = 0;
@@ -225,12 +225,13 @@ int check_out(const daq_fill_out *o) {
     return DAQ_OK;
 }
 
-int64_t tiles_of(int64_t n, int threads) {
-    const int64_t T = (int64_t)threads * daqk::kVec;
-    return (n + T - 1) / T;
+int64_t tiles_of(const daq_fill &f, int threads) {
+    const int64_t T = daqk::tile_shape(f.pre, f.post, threads).tout;
+    return (f.n_samples + T - 1) / T;
 }
 
 FillDev make_desc(const daq_fill &f, const daq_fill_out &o, int64_t tile_base, int threads) {
+    const daqk::TileShape ts = daqk::tile_shape(f.pre, f.post, threads);
     FillDev d{};
     d.raw = f.raw;
     d.n = f.n_samples;
@@ -240,8 +241,12 @@ FillDev make_desc(const daq_fill &f, const daq_fill_out &o, int64_t tile_base, i
     d.thr = f.threshold;
     d.pre = f.pre;
     d.post = f.post;
+    d.gl = ts.gl;
+    d.gr = ts.gr;
+    d.wide = ts.wide;
+    d.tout = ts.tout;
     d.tile_base = tile_base;
-    d.n_tiles = tiles_of(f.n_samples, threads);
+    d.n_tiles = tiles_of(f, threads);
     d.isl = o.islands;
     d.cap = o.capacity;
     d.counts = o.counts;
@@ -268,6 +273,7 @@ int launch_pair(daq_ctx *ctx, const KArgs &a, int64_t total_tiles, hipStream_t s
     const daq_schedule &s = ctx->sched;
     int prep_blocks = (int)std::min<int64_t>(kPrepareBlocks, std::max<int64_t>(1, (total_tiles + 2047) / 2048));
     prep_blocks = std::max(prep_blocks, std::min(a.n_fills, kPrepareBlocks));
+    prep_blocks = std::min(prep_blocks, std::max(a.n_fills, 64));
     HIP_TRY(daqk::launch_prepare(a, prep_blocks, stream));
     if (total_tiles == 0) return DAQ_OK;
     size_t slot = 0;
@@ -338,7 +344,7 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     std::vector<int64_t> base((size_t)n);
     for (int32_t i = 0; i < n; i++) {
         base[(size_t)i] = total;
-        total += tiles_of(fills[i].n_samples, sc.threads);
+        total += tiles_of(fills[i], sc.threads);
     }
     Scratch *s = scratch_for(ctx, stream);
     int rc = ensure_scratch(s, total, n);
