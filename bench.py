@@ -84,11 +84,11 @@ def main():
     if not args.no_tune:
         log("autotuning the fused kernel schedule")
         best = ctx.daq_autotune(fills, outs)
-        sched = (best.threads, best.wgs_per_cu, best.resident)
+        sched = (best.threads, best.wgs_per_cu, best.variant)
     else:
         s = ctx.get_schedule()
-        sched = (s.threads, s.wgs_per_cu, s.resident)
-    log("schedule threads=%d wgs_per_cu=%d resident=%d" % sched)
+        sched = (s.threads, s.wgs_per_cu, s.variant)
+    log("schedule threads=%d wgs_per_cu=%d variant=%d" % sched)
     ctx.set_graphs(True)
 
     # ---- batched: warm-up then the timed region --------------------------------
@@ -218,7 +218,7 @@ def main():
                                "thr -200, pre 8, post 24; batched persistent launch (graph)",
                    "fills": len(specs), "channels": C, "samples": N, "rate": 3.0,
                    "threshold": -200, "pre": 8, "post": 24, "ped_samples": 100,
-                   "schedule": {"threads": sched[0], "wgs_per_cu": sched[1], "resident": sched[2]}},
+                   "schedule": {"threads": sched[0], "wgs_per_cu": sched[1], "variant": sched[2]}},
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "batched": {"gbs": round(value, 1), "p50_fill_ms": round(pct(step_ms, 50), 4),
                     "p99_fill_ms": round(pct(step_ms, 99), 4)},

@@ -113,12 +113,23 @@ typedef struct daq_fill_out {
 } daq_fill_out;
 
 /* Launch schedule of the fused kernel (chosen by daq_autotune or set). */
+#define DAQ_VARIANT_RELOAD 0   /* rows read into registers, read again for the
+                                  write-out                                   */
+#define DAQ_VARIANT_REGISTERS 1 /* 54-channel tiles kept in registers; a call
+                                   with any other channel count runs
+                                   DAQ_VARIANT_RELOAD instead                 */
+#define DAQ_VARIANT_LDS 2      /* 54-channel tiles loaded straight into LDS,
+                                  two work-groups per CU (threads = 256)      */
+#define DAQ_VARIANT_RELOAD18 3 /* as RELOAD with 18 rows in flight (6 there) */
+#define DAQ_VARIANT_RELOAD27 4 /* as RELOAD with 27 rows in flight          */
 typedef struct daq_schedule {
-    int32_t threads;     /* work-group size: 256 or 512                        */
-    int32_t wgs_per_cu;  /* persistent grid = wgs_per_cu x CUs; 0 = one
-                            work-group per tile                                */
-    int32_t resident;    /* 1 = keep a 54-channel tile in registers between
-                            the scan and the write-out; 0 = re-read it       */
+    int32_t threads;     /* work-group size: 128, 256 or 512                    */
+    int32_t wgs_per_cu;  /* persistent grid = wgs_per_cu x CUs (1..16); 0 =
+                            one work-group per tile                            */
+    int32_t variant;     /* DAQ_VARIANT_*; under DAQ_VARIANT_LDS, fills it
+                            cannot take (other channel counts, halos wider
+                            than a quarter of its tile) use the re-read path
+                            inside the same launch                             */
     int32_t reserved;
 } daq_schedule;
 

@@ -33,6 +33,9 @@ DAQ_EMISMATCH = -7
 DAQ_STATUS_CAPACITY = 1
 DAQ_STATUS_OUT_STRIDE = 2
 DAQ_MAX_WINDOW = 32768
+DAQ_VARIANT_RELOAD = 0
+DAQ_VARIANT_REGISTERS = 1
+DAQ_VARIANT_LDS = 2
 
 
 class daq_fill(ctypes.Structure):
@@ -50,7 +53,7 @@ class daq_fill_out(ctypes.Structure):
 
 class daq_schedule(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
-                ("resident", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("variant", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class DaqError(RuntimeError):
@@ -268,8 +271,8 @@ class Context:
         return best
 
     # -- settings ----------------------------------------------------------
-    def set_schedule(self, threads: int = 256, wgs_per_cu: int = 4, resident: int = 0):
-        s = daq_schedule(threads, wgs_per_cu, resident, 0)
+    def set_schedule(self, threads: int = 256, wgs_per_cu: int = 2, variant: int = 2):
+        s = daq_schedule(threads, wgs_per_cu, variant, 0)
         _check(self._lib.daq_ctx_set_schedule(self.handle, ctypes.byref(s)), "daq_ctx_set_schedule")
 
     def get_schedule(self) -> daq_schedule:

@@ -14,8 +14,21 @@ constexpr int kVec = 8;
 // Halo groups on one side for the largest window (post + 1 or pre + 1).
 constexpr int kMaxHaloGroups = (DAQ_MAX_WINDOW + 1 + kVec - 1) / kVec;
 // Channel count of one calorimeter (a 6 x 9 crystal grid, Section 3): the
-// count for which the fused kernel can keep a whole tile in registers.
+// count for which the fused kernel can keep a whole tile in registers or LDS.
 constexpr int kResidentChannels = 54;
+// Kernel variants (daq_schedule.variant).
+constexpr int kVariantReload = 0;    // rows read into registers, read again to write out
+constexpr int kVariantResident = 1;  // rows kept in registers until written out
+constexpr int kVariantStream = 2;    // rows DMA'd into LDS; two work-groups per CU
+constexpr int kVariantReload18 = 3;  // as kVariantReload, 18 rows in flight per round (6 there)
+constexpr int kVariantReload27 = 4;  // as kVariantReload, 27 rows in flight per round
+constexpr int kVariantLast = 4;
+// Tile of the LDS variant: groups of 8 samples per row buffer, work-group size.
+constexpr int kStreamGroups = 80;
+constexpr int kStreamThreads = 256;
+// Per-fill tile modes.
+constexpr int kModeChop = 0;
+constexpr int kModeStream = 1;
 
 // Device-side view of one fill and where its results go.
 struct FillDev {
@@ -31,6 +44,8 @@ struct FillDev {
     int32_t gr;         // halo groups right of a tile: ceil((pre + 1) / 8)
     int32_t wide;       // 0: halo groups are ordinary thread groups of the tile;
                         // 1: extra groups loaded by a separate loop (wide windows)
+    int32_t mode;       // kModeChop or kModeStream
+    int32_t pad1;
     int64_t tout;       // samples a tile owns (decides and writes)
     int64_t tile_base;  // global index of the fill's first tile in the launch
     int64_t n_tiles;
@@ -40,7 +55,9 @@ struct FillDev {
     int32_t *ped;       // may be null
     int16_t *out;       // may be null (find only)
     int64_t out_stride;
+    int64_t pad2;       // size: a whole number of 16-byte words
 };
+static_assert(sizeof(FillDev) % 16 == 0, "descriptors are read as 16-byte words");
 
 // Per-launch sizes kept in device memory so that a captured graph can be
 // replayed for any batch that fits the scratch it was captured with.
@@ -74,26 +91,32 @@ struct GatherArgs {
     int64_t out_stride;
 };
 
-// Tile geometry of one fill for a work-group of `threads`: halo groups, mode
-// and the samples each tile owns. Windows up to a quarter of the work-group
-// keep the halo inside the work-group's own groups.
+// Tile geometry of one fill: halo groups, mode and the samples each tile
+// owns. Halos up to a quarter of the tile's groups are ordinary groups of the
+// tile; wider ones are loaded apart. The LDS variant takes 54-channel fills
+// with such halos; every other fill uses the register path.
 struct TileShape {
-    int32_t gl, gr, wide;
+    int32_t gl, gr, wide, mode;
     int64_t tout;
 };
-inline TileShape tile_shape(int32_t pre, int32_t post, int threads) {
+inline TileShape tile_shape(int32_t pre, int32_t post, int32_t channels, int threads, int variant) {
     TileShape t;
     t.gl = (post + 1 + kVec - 1) / kVec;
     t.gr = (pre + 1 + kVec - 1) / kVec;
+    if (variant == kVariantStream && channels == kResidentChannels && (t.gl + t.gr) * 4 <= kStreamGroups) {
+        t.mode = kModeStream;
+        t.wide = 0;
+        t.tout = (int64_t)(kStreamGroups - t.gl - t.gr) * kVec;
+        return t;
+    }
+    t.mode = kModeChop;
     t.wide = (t.gl + t.gr) * 4 > threads ? 1 : 0;
     t.tout = (int64_t)(t.wide ? threads : threads - t.gl - t.gr) * kVec;
     return t;
 }
 
 hipError_t launch_prepare(const KArgs &a, int blocks, hipStream_t s);
-hipError_t launch_chop(const KArgs &a, int threads, bool resident, int grid, hipStream_t s);
+hipError_t launch_chop(const KArgs &a, int threads, int variant, int grid, hipStream_t s);
 hipError_t launch_gather(const GatherArgs &g, int grid, hipStream_t s);
-// Resource use of each chop variant (for the autotuner's candidate list).
-int chop_max_threads(int threads, bool resident);
 
 }  // namespace daqk

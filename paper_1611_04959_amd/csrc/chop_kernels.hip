@@ -61,16 +61,44 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
     return v;
 }
 
+// Work-group barrier for LDS traffic only. Global stores stay in flight: no
+// wave of a tile reads what another wave wrote to global memory (tiles talk
+// through the look-back atomics), so waiting for them would only add latency.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Global-memory views of generic pointers: descriptors arrive from memory, so
+// without these the compiler would address fill data with flat instructions.
+#define DAQ_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ DAQ_GLOBAL T *gbl(T *p) {
+    return (DAQ_GLOBAL T *)p;
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 // Descriptor of fill f: from the device table, or the single fill passed in
 // the kernel arguments. Returned by value so that no pointer to the kernel
 // arguments is formed.
 __device__ __forceinline__ FillDev fill_at(const KArgs &a, int f) {
-    if (a.table) return a.table[f];
+    if (a.table) {
+        union {
+            FillDev d;
+            u32x4 v[sizeof(FillDev) / 16];
+        } u;
+        const DAQ_GLOBAL u32x4 *src = (const DAQ_GLOBAL u32x4 *)(a.table + f);
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(FillDev) / 16); i++) u.v[i] = src[i];
+        return u.d;
+    }
     return a.one;
 }
 
 __device__ __forceinline__ int64_t tile_base_at(const KArgs &a, int f) {
-    return a.table ? a.table[f].tile_base : a.one.tile_base;
+    return a.table ? gbl(a.table + f)->tile_base : a.one.tile_base;
 }
 
 // Adds the eight int16 samples of one 16-byte row chunk to eight sums.
@@ -92,20 +120,31 @@ __device__ __forceinline__ uint32_t flags8(const int32_t (&s)[kVec], int32_t thr
 }
 
 __device__ __forceinline__ uint4 load16(const int16_t *p) {
-    return *reinterpret_cast<const uint4 *>(p);
+    const u32x4 v = *(const DAQ_GLOBAL u32x4 *)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
 }
 
-// Flags of 8 samples starting at p (all C rows read, nothing kept).
-__device__ uint32_t group_flags(const int16_t *p, int64_t stride, int C, int32_t thr_eff,
-                                int64_t valid) {
+__device__ __forceinline__ void store16(int16_t *p, const uint4 v) {
+    u32x4 w;
+    w.x = v.x;
+    w.y = v.y;
+    w.z = v.z;
+    w.w = v.w;
+    *(DAQ_GLOBAL u32x4 *)p = w;
+}
+
+// Flags of 8 samples starting at p (all C rows read, nothing kept); R rows
+// are in flight per round.
+template <int R>
+__device__ uint32_t group_flags(const int16_t *p, int64_t stride, int C, int32_t thr_eff, int64_t valid) {
     int32_t s[kVec] = {0, 0, 0, 0, 0, 0, 0, 0};
     int c = 0;
-    for (; c + 6 <= C; c += 6) {
-        uint4 v[6];
+    for (; c + R <= C; c += R) {
+        uint4 v[R];
 #pragma unroll
-        for (int u = 0; u < 6; u++) v[u] = load16(p + (int64_t)(c + u) * stride);
+        for (int u = 0; u < R; u++) v[u] = load16(p + (int64_t)(c + u) * stride);
 #pragma unroll
-        for (int u = 0; u < 6; u++) add8(s, v[u]);
+        for (int u = 0; u < R; u++) add8(s, v[u]);
     }
     for (; c < C; c++) add8(s, load16(p + (int64_t)c * stride));
     return flags8(s, thr_eff, valid);
@@ -139,7 +178,7 @@ __device__ uint64_t look_back(uint64_t *st, int64_t lt, int lane) {
     for (;;) {
         const int64_t j = hi - lane;
         uint64_t s = kFlagIncl;  // before the fill's first tile: empty prefix
-        if (j >= 0) s = __hip_atomic_load(st + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (j >= 0) s = __hip_atomic_load(gbl(st + j), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t flag = s & ~kValMask;
         const uint64_t b_incl = __ballot(flag == kFlagIncl);
         const uint64_t b_none = __ballot(flag == 0);
@@ -211,90 +250,74 @@ __device__ __forceinline__ void stage_flush(const int16_t *stage, int rs, int16_
         const int16_t *src = stage + cl * rs + q * 8;
         const int64_t g0 = m0 + j0;
         if (j0 >= 0 && j0 + 8 <= len && g0 + 8 <= ostride) {
-            *reinterpret_cast<uint4 *>(row + g0) = *reinterpret_cast<const uint4 *>(src);
+            store16(row + g0, *reinterpret_cast<const uint4 *>(src));
         } else {
 #pragma unroll
             for (int e = 0; e < 8; e++) {
                 const int j = j0 + e;
-                if (j >= 0 && j < len && m0 + j < ostride) row[m0 + j] = src[e];
+                if (j >= 0 && j < len && m0 + j < ostride) *gbl(row + m0 + j) = src[e];
             }
         }
     }
 }
 
-template <int NT>
-struct ChopLds {
-    static constexpr int kGroups = 2 * kMaxHaloGroups + NT;  // widest bitmap
-    static constexpr int kWords = (kGroups + 7) / 8 + 1;
-    static constexpr int kBitsBytes = kWords * 8 + (kWords + 1) * 4;
-    static constexpr int kCB = NT == 256 ? 8 : 4;            // channels staged per round
-    static constexpr int kRowStride = NT * kVec + 16;        // elements per staged row
-    static constexpr int kStageBytes = kCB * kRowStride * 2;
-    static constexpr int kBytes = kBitsBytes > kStageBytes ? kBitsBytes : kStageBytes;
+// Last run whose packed start is <= j, or -1 (j lies in the run open at the
+// tile's first sample).
+__device__ __forceinline__ int find_run(const int32_t *seg_dst, int nrun, int j) {
+    int lo = 0, hi = nrun - 1, ans = -1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        if (seg_dst[mid] <= j) {
+            ans = mid;
+            lo = mid + 1;
+        } else {
+            hi = mid - 1;
+        }
+    }
+    return ans;
+}
+
+// Samples shift .. shift + 7 of the 16 samples held by A (0..7) and B (8..15).
+__device__ __forceinline__ uint4 realign8(const uint4 A, const uint4 B, int shift) {
+    const uint32_t d[8] = {A.x, A.y, A.z, A.w, B.x, B.y, B.z, B.w};
+    const int h = shift >> 1;
+    uint32_t e[5];
+#pragma unroll
+    for (int k = 0; k < 5; k++) {
+        const uint32_t a0 = d[k], a1 = d[k + 1 < 8 ? k + 1 : 7], a2 = d[k + 2 < 8 ? k + 2 : 7],
+                       a3 = d[k + 3 < 8 ? k + 3 : 7];
+        e[k] = h == 0 ? a0 : (h == 1 ? a1 : (h == 2 ? a2 : a3));
+    }
+    if (shift & 1)
+        return make_uint4(__builtin_amdgcn_alignbyte(e[1], e[0], 2), __builtin_amdgcn_alignbyte(e[2], e[1], 2),
+                          __builtin_amdgcn_alignbyte(e[3], e[2], 2), __builtin_amdgcn_alignbyte(e[4], e[3], 2));
+    return make_uint4(e[0], e[1], e[2], e[3]);
+}
+
+// ---- steps shared by every tile variant ---------------------------------------
+
+struct TileScan {
+    uint32_t mm, rise, fall;     // this thread's island mask and island edges
+    int th_m, th_i;              // island samples / islands of lower threads in the tile
+    int tile_m, tile_i;          // tile totals
+    int64_t m_before, i_before;  // totals of the fill's earlier tiles
 };
 
-template <int NT, bool RESIDENT>
-__device__ __forceinline__ void chop_tile(const KArgs &a, const FillDev &fd, int f, int64_t tile, uint8_t *lds,
-                                          uint32_t *s_wsum, uint64_t *s_excl) {
+// Step 2 of a tile whose flag bitmap (G groups of 8 bits, zero padding up to
+// word Wn included) is in s_bits: popcount prefix, dilation of the calling
+// thread's group g (owners only; its first sample is p) and work-group scan.
+// Ends by publishing the tile's total (its inclusive prefix for a fill's
+// first tile); never waits for another tile.
+template <int NT>
+__device__ __forceinline__ TileScan scan_front(const KArgs &a, const FillDev &fd, int64_t lt, int G, int g,
+                                               bool owner, int64_t p, const uint8_t *s_bits, uint32_t *s_pc,
+                                               uint32_t *s_wsum) {
     constexpr int NW = NT / 64;
-    constexpr int CR = RESIDENT ? kResidentChannels : 1;
-    constexpr int CB = ChopLds<NT>::kCB;
-    constexpr int RS = ChopLds<NT>::kRowStride;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
-
-    const int64_t lt = tile - fd.tile_base;
     const int64_t N = fd.n;
-    const int C = RESIDENT ? kResidentChannels : fd.C;
-    const int64_t stride = fd.stride;
-    const int16_t *raw = fd.raw;
-    const int gl = fd.gl;
-    const int gr = fd.gr;
-    const bool wide = fd.wide != 0;
-    const int G = wide ? gl + NT + gr : NT;           // bitmap groups
-    const int64_t t0 = lt * fd.tout;                  // first sample the tile owns
-    const int64_t base = t0 - (int64_t)gl * kVec;     // sample at bitmap bit 0
-    const int g = wide ? gl + tid : tid;              // this thread's group
-    const bool owner = wide || (tid >= gl && tid < NT - gr);
-    const int64_t p = base + (int64_t)g * kVec;       // its first sample
-    int64_t te = a.thr_eff[f];
-    te = te > 2147483647LL ? 2147483647LL : (te < -2147483648LL ? -2147483648LL : te);
-    const int32_t thr_eff = (int32_t)te;
-
-    uint8_t *s_bits = lds;
-    uint32_t *s_pc = reinterpret_cast<uint32_t *>(lds + ChopLds<NT>::kWords * 8);
-    int16_t *s_stage = reinterpret_cast<int16_t *>(lds);
-
-    // 1. flags of this thread's 8 samples from all channel rows (Table 2
-    //    waveform-sum and threshold rows); halo groups of wide windows apart
-    uint4 xr[CR];
-    uint32_t fb = 0;
-    if (p >= 0 && p < N) {
-        if constexpr (RESIDENT) {
-#pragma unroll
-            for (int c = 0; c < kResidentChannels; c++) xr[c] = load16(raw + p + (int64_t)c * stride);
-            int32_t s[kVec] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-            for (int c = 0; c < kResidentChannels; c++) add8(s, xr[c]);
-            fb = flags8(s, thr_eff, N - p);
-        } else {
-            fb = group_flags(raw + p, stride, C, thr_eff, N - p);
-        }
-    }
-    s_bits[g] = (uint8_t)fb;
-    if (wide) {
-        for (int h = tid; h < gl + gr; h += NT) {
-            const int hg = (h < gl) ? h : (NT + h);
-            const int64_t q = base + (int64_t)hg * kVec;
-            uint32_t hb = 0;
-            if (q >= 0 && q < N) hb = group_flags(raw + q, stride, C, thr_eff, N - q);
-            s_bits[hg] = (uint8_t)hb;
-        }
-    }
-    const int Wn = (G + 7) >> 3;  // bitmap words; word Wn stays zero
-    for (int z = G + tid; z < (Wn + 1) * 8; z += NT) s_bits[z] = 0;
-    __syncthreads();
+    const int Wn = (G + 7) >> 3;
 
     // 2a. exclusive popcount prefix over the bitmap words (wave 0)
     const uint64_t *words = reinterpret_cast<const uint64_t *>(s_bits);
@@ -308,7 +331,7 @@ __device__ __forceinline__ void chop_tile(const KArgs &a, const FillDev &fd, int
             carry += __shfl(inc, 63, 64);
         }
     }
-    __syncthreads();
+    lds_barrier();
 
     // 2b. dilation (Table 2 pre/post row): sample t is inside an island when
     //     a flag lies in [t - post, t + pre]; masks for p-1 .. p+8
@@ -325,15 +348,16 @@ __device__ __forceinline__ void chop_tile(const KArgs &a, const FillDev &fd, int
             m10 |= (in ? 1u : 0u) << j;
         }
     }
-    const uint32_t mm = (m10 >> 1) & 0xFFu;
-    const uint32_t rise = mm & ~(((mm << 1) | (m10 & 1u)) & 0xFFu);
-    const uint32_t fall = mm & ~((mm >> 1) | (((m10 >> 9) & 1u) << 7));
+    TileScan r;
+    r.mm = (m10 >> 1) & 0xFFu;
+    r.rise = r.mm & ~(((r.mm << 1) | (m10 & 1u)) & 0xFFu);
+    r.fall = r.mm & ~((r.mm >> 1) | (((m10 >> 9) & 1u) << 7));
 
     // 2c. work-group exclusive scan of (island samples << 16 | islands)
-    const uint32_t mine = ((uint32_t)__popc(mm) << 16) | (uint32_t)__popc(rise);
+    const uint32_t mine = ((uint32_t)__popc(r.mm) << 16) | (uint32_t)__popc(r.rise);
     const uint32_t inc = wave_incl_scan_u32(mine, lane);
     if (lane == 63) s_wsum[wid] = inc;
-    __syncthreads();
+    lds_barrier();
     uint32_t before = 0, total = 0;
 #pragma unroll
     for (int w = 0; w < NW; w++) {
@@ -342,135 +366,536 @@ __device__ __forceinline__ void chop_tile(const KArgs &a, const FillDev &fd, int
         total += v;
     }
     const uint32_t excl = before + inc - mine;
-    const int th_m = (int)(excl >> 16), th_i = (int)(excl & 0xFFFFu);
-    const uint64_t tile_m = total >> 16, tile_i = total & 0xFFFFu;
+    r.th_m = (int)(excl >> 16);
+    r.th_i = (int)(excl & 0xFFFFu);
+    r.tile_m = (int)(total >> 16);
+    r.tile_i = (int)(total & 0xFFFFu);
+    r.m_before = 0;
+    r.i_before = 0;
 
-    // 3. decoupled look-back over the fill's earlier tiles (wave 0)
-    if (wid == 0) {
+    // 3a. publish the tile's total at once: later tiles of the fill wait for it
+    if (tid == 0) {
         uint64_t *st = a.tile_state + fd.tile_base;
-        const uint64_t agg = (tile_m << 31) | tile_i;
+        const uint64_t agg = ((uint64_t)r.tile_m << 31) | (uint64_t)r.tile_i;
+        __hip_atomic_store(gbl(st + lt), (lt == 0 ? kFlagIncl : kFlagAgg) | agg, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return r;
+}
+
+// Step 3b: decoupled look-back over the fill's earlier tiles (wave 0), the
+// tile's inclusive prefix, and the prefix broadcast to the work-group.
+__device__ __forceinline__ void scan_back(const KArgs &a, const FillDev &fd, int64_t lt, TileScan &r,
+                                          uint64_t *s_excl) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    if ((tid >> 6) == 0) {
         uint64_t ex = 0;
-        if (lt == 0) {
-            if (lane == 0) __hip_atomic_store(st, kFlagIncl | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            if (lane == 0) __hip_atomic_store(st + lt, kFlagAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lt > 0) {
+            uint64_t *st = a.tile_state + fd.tile_base;
+            const uint64_t agg = ((uint64_t)r.tile_m << 31) | (uint64_t)r.tile_i;
             ex = look_back(st, lt, lane);
             if (lane == 0)
-                __hip_atomic_store(st + lt, kFlagIncl | (ex + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(gbl(st + lt), kFlagIncl | (ex + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (lane == 0) *s_excl = ex;
     }
-    __syncthreads();
+    lds_barrier();
     const uint64_t ex = *s_excl;
-    const int64_t m_before = (int64_t)((ex >> 31) & kField);
-    const int64_t i_before = (int64_t)(ex & kField);
-    const int64_t mbase = m_before + th_m;  // packed position of this thread's first island sample
-    const int64_t ibase = i_before + th_i;  // islands starting before this thread's samples
+    r.m_before = (int64_t)((ex >> 31) & kField);
+    r.i_before = (int64_t)(ex & kField);
+}
 
-    // 4a. island records (Table 2 island-array row)
-    if (rise | fall) {
-        daq_island *isl = fd.isl;
-        const int64_t cap = fd.cap;
+// Steps 2-3 back to back.
+template <int NT>
+__device__ __forceinline__ TileScan scan_tile(const KArgs &a, const FillDev &fd, int64_t lt, int G, int g,
+                                              bool owner, int64_t p, const uint8_t *s_bits, uint32_t *s_pc,
+                                              uint32_t *s_wsum, uint64_t *s_excl) {
+    TileScan r = scan_front<NT>(a, fd, lt, G, g, owner, p, s_bits, s_pc, s_wsum);
+    scan_back(a, fd, lt, r, s_excl);
+    return r;
+}
+
+// Step 4a (Table 2 island-array row): the record fields this thread owns.
+__device__ __forceinline__ void write_records(const FillDev &fd, const TileScan &r, int64_t p) {
+    if (!(r.rise | r.fall)) return;
+    DAQ_GLOBAL daq_island *isl = gbl(fd.isl);
+    const int64_t cap = fd.cap;
+    const int64_t mbase = r.m_before + r.th_m;
+    const int64_t ibase = r.i_before + r.th_i;
 #pragma unroll
-        for (int k = 0; k < kVec; k++) {
-            if ((rise >> k) & 1u) {
-                const int64_t idx = ibase + __popc(rise & ((1u << k) - 1u));
-                if (idx < cap) {
-                    isl[idx].start = p + k;
-                    isl[idx].offset = mbase + __popc(mm & ((1u << k) - 1u));
-                }
-            }
-            if ((fall >> k) & 1u) {
-                const int64_t idx = ibase + __popc(rise & ((2u << k) - 1u)) - 1;
-                if (idx >= 0 && idx < cap) isl[idx].stop = p + k + 1;
+    for (int k = 0; k < kVec; k++) {
+        if ((r.rise >> k) & 1u) {
+            const int64_t idx = ibase + __popc(r.rise & ((1u << k) - 1u));
+            if (idx < cap) {
+                isl[idx].start = p + k;
+                isl[idx].offset = mbase + __popc(r.mm & ((1u << k) - 1u));
             }
         }
+        if ((r.fall >> k) & 1u) {
+            const int64_t idx = ibase + __popc(r.rise & ((2u << k) - 1u)) - 1;
+            if (idx >= 0 && idx < cap) isl[idx].stop = p + k + 1;
+        }
     }
+}
 
-    // 4b. chopped islands: the packed raw samples of every channel, staged in
-    //     LDS per CB channels so that global stores are aligned 16-byte lines
-    if (fd.out != nullptr && tile_m > 0) {
-        int16_t *out = fd.out;
-        const int64_t ostride = fd.out_stride;
-        const int len = (int)tile_m;
-        if constexpr (RESIDENT) {
+// Step 5: totals, written by the fill's last tile (right after its scan).
+__device__ __forceinline__ void write_counts(const FillDev &fd, int64_t lt, const TileScan &r) {
+    if (threadIdx.x != 0 || lt != fd.n_tiles - 1 || fd.counts == nullptr) return;
+    const int64_t n_isl = r.i_before + r.tile_i;
+    const int64_t tl = r.m_before + r.tile_m;
+    int32_t status = (n_isl > fd.cap) ? DAQ_STATUS_CAPACITY : 0;
+    if (fd.out != nullptr && tl > fd.out_stride) status |= DAQ_STATUS_OUT_STRIDE;
+    DAQ_GLOBAL daq_counts *cnt = gbl(fd.counts);
+    cnt->n_islands = n_isl;
+    cnt->total_len = tl;
+    cnt->status = status;
+    cnt->reserved = 0;
+}
+
+__device__ __forceinline__ int32_t clamp_thr(int64_t te) {
+    return (int32_t)(te > 2147483647LL ? 2147483647LL : (te < -2147483648LL ? -2147483648LL : te));
+}
+
+// ---- variant 0 / 1: rows read into registers ------------------------------------
+
+template <int NT>
+struct ChopLds {
+    static constexpr int kGroups = 2 * kMaxHaloGroups + NT;  // widest bitmap
+    static constexpr int kWords = (kGroups + 7) / 8 + 1;
+    static constexpr int kBitsBytes = kWords * 8 + (kWords + 1) * 4;
+    static constexpr int kCB = NT <= 256 ? 8 : 4;            // channels staged per round
+    static constexpr int kRowStride = NT * kVec + 16;        // elements per staged row
+    static constexpr int kStageBytes = kCB * kRowStride * 2;
+    static constexpr int kBytes = kBitsBytes > kStageBytes ? kBitsBytes : kStageBytes;
+};
+
+// Geometry of a tile of NT groups of 8 samples (the halo groups included, or
+// loaded apart for wide windows) as seen by one thread.
+template <int NT>
+struct ChopGeom {
+    int64_t lt, t0, base, p;
+    int G, g;
+    bool owner;
+    __device__ __forceinline__ ChopGeom(const FillDev &fd, int64_t tile) {
+        const bool wide = fd.wide != 0;
+        lt = tile - fd.tile_base;
+        G = wide ? fd.gl + NT + fd.gr : NT;            // bitmap groups
+        t0 = lt * fd.tout;                             // first sample the tile owns
+        base = t0 - (int64_t)fd.gl * kVec;             // sample at bitmap bit 0
+        g = wide ? fd.gl + (int)threadIdx.x : (int)threadIdx.x;
+        owner = wide || ((int)threadIdx.x >= fd.gl && (int)threadIdx.x < NT - fd.gr);
+        p = base + (int64_t)g * kVec;                  // this thread's first sample
+    }
+};
+
+// Step 1 for a tile of NT groups: flags of this thread's 8 samples from all
+// channel rows (Table 2 waveform-sum and threshold rows), R rows in flight,
+// halo groups of wide windows loaded apart; bitmap zero padding; barrier.
+template <int NT, int R>
+__device__ __forceinline__ void chop_flags(const FillDev &fd, const ChopGeom<NT> &q, int32_t thr_eff,
+                                           uint8_t *s_bits) {
+    const int tid = threadIdx.x;
+    const int64_t N = fd.n;
+    uint32_t fb = 0;
+    if (q.p >= 0 && q.p < N) fb = group_flags<R>(fd.raw + q.p, fd.stride, fd.C, thr_eff, N - q.p);
+    s_bits[q.g] = (uint8_t)fb;
+    if (fd.wide) {
+        for (int h = tid; h < fd.gl + fd.gr; h += NT) {
+            const int hg = (h < fd.gl) ? h : (NT + h);
+            const int64_t s0 = q.base + (int64_t)hg * kVec;
+            uint32_t hb = 0;
+            if (s0 >= 0 && s0 < N) hb = group_flags<6>(fd.raw + s0, fd.stride, fd.C, thr_eff, N - s0);
+            s_bits[hg] = (uint8_t)hb;
+        }
+    }
+    const int Wn = (q.G + 7) >> 3;  // bitmap words; word Wn stays zero
+    for (int z = q.G + tid; z < (Wn + 1) * 8; z += NT) s_bits[z] = 0;
+    lds_barrier();
+}
+
+// What a re-read tile keeps between its front half (flags, scan, total
+// published) and its back half (look-back, records, packed samples).
+struct ReloadTile {
+    TileScan r;
+    int64_t lt;
+    int64_t p;
+};
+
+template <int NT, int R>
+__device__ __forceinline__ ReloadTile reload_front(const KArgs &a, const FillDev &fd, int32_t thr_eff, int64_t tile,
+                                                   uint8_t *lds, uint32_t *s_wsum) {
+    const ChopGeom<NT> q(fd, tile);
+    uint8_t *s_bits = lds;
+    uint32_t *s_pc = reinterpret_cast<uint32_t *>(lds + ChopLds<NT>::kWords * 8);
+    chop_flags<NT, R>(fd, q, thr_eff, s_bits);
+    ReloadTile t;
+    t.r = scan_front<NT>(a, fd, q.lt, q.G, q.g, q.owner, q.p, s_bits, s_pc, s_wsum);
+    t.lt = q.lt;
+    t.p = q.p;
+    return t;
+}
+
+// Back half: prefix, records, totals and the chopped islands, whose raw
+// samples are read again and staged in LDS per CB channels so that global
+// stores are aligned 16-byte lines.
+template <int NT>
+__device__ __forceinline__ void reload_back(const KArgs &a, const FillDev &fd, ReloadTile &t, uint8_t *lds,
+                                            uint64_t *s_excl) {
+    constexpr int CB = ChopLds<NT>::kCB;
+    constexpr int RS = ChopLds<NT>::kRowStride;
+    scan_back(a, fd, t.lt, t.r, s_excl);
+    const TileScan &r = t.r;
+    write_records(fd, r, t.p);
+    write_counts(fd, t.lt, r);
+    if (fd.out == nullptr || r.tile_m == 0) return;
+    int16_t *s_stage = reinterpret_cast<int16_t *>(lds);
+    int16_t *out = fd.out;
+    const int64_t ostride = fd.out_stride;
+    const int64_t m0 = r.m_before;
+    const uint32_t mm = r.mm;
+    const int C = fd.C;
+    for (int c0 = 0; c0 < C; c0 += CB) {
+        if (mm) {
+            uint4 v[CB];
+#pragma unroll
+            for (int cl = 0; cl < CB; cl++)
+                if (c0 + cl < C) v[cl] = load16(fd.raw + t.p + (int64_t)(c0 + cl) * fd.stride);
+#pragma unroll
+            for (int cl = 0; cl < CB; cl++) {
+                if (c0 + cl < C) {
+                    const int ph = line_phase(out + (int64_t)(c0 + cl) * ostride, m0);
+                    stage_put(s_stage + cl * RS, ph + r.th_m, mm, v[cl]);
+                }
+            }
+        }
+        lds_barrier();
+        stage_flush<NT, CB>(s_stage, RS, out, ostride, c0, C, m0, r.tile_m);
+        lds_barrier();
+    }
+}
+
+// A whole tile at once. RESIDENT keeps each thread's 54 channel chunks in
+// registers for the write-out; otherwise the two halves run back to back.
+template <int NT, bool RESIDENT, int kRowsInFlight>
+__device__ __forceinline__ void chop_tile(const KArgs &a, const FillDev &fd, int32_t thr_eff, int64_t tile, uint8_t *lds,
+                                          uint32_t *s_wsum, uint64_t *s_excl) {
+    if constexpr (!RESIDENT) {
+        ReloadTile t = reload_front<NT, kRowsInFlight>(a, fd, thr_eff, tile, lds, s_wsum);
+        reload_back<NT>(a, fd, t, lds, s_excl);
+    } else {
+        constexpr int CB = ChopLds<NT>::kCB;
+        constexpr int RS = ChopLds<NT>::kRowStride;
+        const ChopGeom<NT> q(fd, tile);
+        const int64_t N = fd.n;
+        const int64_t stride = fd.stride;
+        const int16_t *raw = fd.raw;
+        uint8_t *s_bits = lds;
+        uint32_t *s_pc = reinterpret_cast<uint32_t *>(lds + ChopLds<NT>::kWords * 8);
+        int16_t *s_stage = reinterpret_cast<int16_t *>(lds);
+
+        // 1. flags of this thread's 8 samples from all 54 rows, kept
+        uint4 xr[kResidentChannels];
+        uint32_t fb = 0;
+        if (q.p >= 0 && q.p < N) {
+#pragma unroll
+            for (int c = 0; c < kResidentChannels; c++) xr[c] = load16(raw + q.p + (int64_t)c * stride);
+            int32_t s[kVec] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int c = 0; c < kResidentChannels; c++) add8(s, xr[c]);
+            fb = flags8(s, thr_eff, N - q.p);
+        }
+        s_bits[q.g] = (uint8_t)fb;
+        if (fd.wide) {
+            for (int h = threadIdx.x; h < fd.gl + fd.gr; h += NT) {
+                const int hg = (h < fd.gl) ? h : (NT + h);
+                const int64_t s0 = q.base + (int64_t)hg * kVec;
+                uint32_t hb = 0;
+                if (s0 >= 0 && s0 < N) hb = group_flags<6>(raw + s0, stride, kResidentChannels, thr_eff, N - s0);
+                s_bits[hg] = (uint8_t)hb;
+            }
+        }
+        const int Wn = (q.G + 7) >> 3;
+        for (int z = q.G + threadIdx.x; z < (Wn + 1) * 8; z += NT) s_bits[z] = 0;
+        lds_barrier();
+
+        const TileScan r = scan_tile<NT>(a, fd, q.lt, q.G, q.g, q.owner, q.p, s_bits, s_pc, s_wsum, s_excl);
+        write_records(fd, r, q.p);
+        write_counts(fd, q.lt, r);
+
+        // 4b. chopped islands from the registers, staged in LDS per CB channels
+        if (fd.out != nullptr && r.tile_m > 0) {
+            int16_t *out = fd.out;
+            const int64_t ostride = fd.out_stride;
+            const int64_t m0 = r.m_before;
+            const uint32_t mm = r.mm;
 #pragma unroll
             for (int c0 = 0; c0 < kResidentChannels; c0 += CB) {
                 if (mm) {
 #pragma unroll
                     for (int cl = 0; cl < CB; cl++) {
                         if (c0 + cl < kResidentChannels) {
-                            const int ph = line_phase(out + (int64_t)(c0 + cl) * ostride, m_before);
-                            stage_put(s_stage + cl * RS, ph + th_m, mm, xr[c0 + cl]);
+                            const int ph = line_phase(out + (int64_t)(c0 + cl) * ostride, m0);
+                            stage_put(s_stage + cl * RS, ph + r.th_m, mm, xr[c0 + cl]);
                         }
                     }
                 }
-                __syncthreads();
-                stage_flush<NT, CB>(s_stage, RS, out, ostride, c0, kResidentChannels, m_before, len);
-                __syncthreads();
-            }
-        } else {
-            for (int c0 = 0; c0 < C; c0 += CB) {
-                if (mm) {
-                    uint4 v[CB];
-#pragma unroll
-                    for (int cl = 0; cl < CB; cl++)
-                        if (c0 + cl < C) v[cl] = load16(raw + p + (int64_t)(c0 + cl) * stride);
-#pragma unroll
-                    for (int cl = 0; cl < CB; cl++) {
-                        if (c0 + cl < C) {
-                            const int ph = line_phase(out + (int64_t)(c0 + cl) * ostride, m_before);
-                            stage_put(s_stage + cl * RS, ph + th_m, mm, v[cl]);
-                        }
-                    }
-                }
-                __syncthreads();
-                stage_flush<NT, CB>(s_stage, RS, out, ostride, c0, C, m_before, len);
-                __syncthreads();
+                lds_barrier();
+                stage_flush<NT, CB>(s_stage, RS, out, ostride, c0, kResidentChannels, m0, r.tile_m);
+                lds_barrier();
             }
         }
-    }
-
-    // 5. totals, written by the fill's last tile
-    if (tid == 0 && lt == fd.n_tiles - 1 && fd.counts != nullptr) {
-        const int64_t n_isl = i_before + (int64_t)tile_i;
-        const int64_t tl = m_before + (int64_t)tile_m;
-        int32_t status = (n_isl > fd.cap) ? DAQ_STATUS_CAPACITY : 0;
-        if (fd.out != nullptr && tl > fd.out_stride) status |= DAQ_STATUS_OUT_STRIDE;
-        fd.counts->n_islands = n_isl;
-        fd.counts->total_len = tl;
-        fd.counts->status = status;
-        fd.counts->reserved = 0;
     }
 }
 
-template <int NT, bool RESIDENT>
+// ---- variant 2: the tile lives in LDS ---------------------------------------------
+
+// Tile rows are DMA'd straight from HBM into LDS (no registers hold them), so
+// two work-groups share a CU and overlap one another's load and compute
+// phases; the write-out reads LDS.
+struct StreamLds {
+    static constexpr int kGroups = kStreamGroups;                       // groups per tile buffer
+    static constexpr int kRow = kGroups * kVec;                         // samples per row
+    static constexpr int kChunks = kResidentChannels * kGroups;         // 16-byte chunks
+    static constexpr int kIters = (kChunks + kStreamThreads - 1) / kStreamThreads;
+    static constexpr int kBufBytes = kIters * kStreamThreads * 16;      // last round lands in padding
+    static constexpr int kWords = (kGroups + 7) / 8 + 1;
+    static constexpr int kBitsOff = kBufBytes;
+    static constexpr int kPcOff = kBitsOff + kWords * 8;
+    static constexpr int kMaxRuns = kRow / 2 + 2;
+    static constexpr int kRunOff = kPcOff + (kWords + 1) * 4;
+    static constexpr int kBytes = kRunOff + 2 * kMaxRuns * 4;
+};
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Chopped islands of one tile straight from the LDS rows: work items are
+// (channel, aligned 16-byte chunk of the packed row); a chunk whose 8 samples
+// come from one run reads two aligned LDS words and realigns them, the others
+// go element by element.
+template <int NT>
+__device__ __forceinline__ void gather_from_lds(const int16_t *buf, const int32_t *seg_src, const int32_t *seg_dst,
+                                                int nrun, int own0, int16_t *out, int64_t ostride, int64_t m0,
+                                                int len) {
+    constexpr int C = kResidentChannels;
+    constexpr int ROW = StreamLds::kRow;
+    const int nch = (len + 7 + 7) >> 3;
+    const int items = C * nch;
+    for (int i = threadIdx.x; i < items; i += NT) {
+        const int c = i / nch;
+        const int q = i - c * nch;
+        int16_t *orow = out + (int64_t)c * ostride;
+        const int j0 = q * 8 - line_phase(orow, m0);
+        if (j0 >= len) continue;
+        const int16_t *brow = buf + c * ROW;
+        const int jlo = j0 < 0 ? 0 : j0;
+        int r = find_run(seg_dst, nrun, jlo);
+        int next = (r + 1 < nrun) ? seg_dst[r + 1] : len;
+        const bool full = j0 >= 0 && j0 + 8 <= len && m0 + j0 + 8 <= ostride;
+        if (full && j0 + 7 < next) {  // one run: two aligned LDS words, realigned
+            const int s0 = (r < 0) ? own0 + j0 : seg_src[r] + (j0 - seg_dst[r]);
+            const int a0 = s0 & ~7;
+            const uint4 A = *reinterpret_cast<const uint4 *>(brow + a0);
+            const uint4 B = (s0 & 7) ? *reinterpret_cast<const uint4 *>(brow + a0 + 8) : make_uint4(0, 0, 0, 0);
+            store16(orow + m0 + j0, realign8(A, B, s0 & 7));
+            continue;
+        }
+        // run edges and row ends: walk the runs forward from the chunk's first
+        // element, gather the values, then store them
+        uint32_t v[8];
+        uint32_t valid = 0;
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int j = j0 + e;
+            v[e] = 0;
+            if (j < 0 || j >= len || m0 + j >= ostride) continue;
+            while (j >= next) {
+                r++;
+                next = (r + 1 < nrun) ? seg_dst[r + 1] : len;
+            }
+            const int sj = (r < 0) ? own0 + j : seg_src[r] + (j - seg_dst[r]);
+            v[e] = (uint16_t)brow[sj];
+            valid |= 1u << e;
+        }
+        if (valid == 0xFFu) {
+            store16(orow + m0 + j0, make_uint4(v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16),
+                                               v[6] | (v[7] << 16)));
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; e++)
+                if ((valid >> e) & 1u) *gbl(orow + m0 + j0 + e) = (int16_t)v[e];
+        }
+    }
+}
+
+__device__ __forceinline__ void stream_tile(const KArgs &a, const FillDev &fd, int32_t thr_eff, int64_t tile, uint8_t *lds,
+                                            uint32_t *s_wsum, uint64_t *s_excl) {
+    constexpr int NT = kStreamThreads;
+    constexpr int G = StreamLds::kGroups;
+    constexpr int C = kResidentChannels;
+    constexpr int ROW = StreamLds::kRow;
+    const int tid = threadIdx.x;
+    const int wid = tid >> 6;
+
+    const int64_t lt = tile - fd.tile_base;
+    const int64_t N = fd.n;
+    const int gl = fd.gl;
+    const int gr = fd.gr;
+    const int64_t t0 = lt * fd.tout;
+    const int64_t base = t0 - (int64_t)gl * kVec;
+    const int16_t *raw = fd.raw;
+    const int64_t stride = fd.stride;
+    int16_t *buf = reinterpret_cast<int16_t *>(lds);
+    uint8_t *s_bits = lds + StreamLds::kBitsOff;
+    uint32_t *s_pc = reinterpret_cast<uint32_t *>(lds + StreamLds::kPcOff);
+    int32_t *seg_src = reinterpret_cast<int32_t *>(lds + StreamLds::kRunOff);
+    int32_t *seg_dst = seg_src + StreamLds::kMaxRuns;
+
+    // 1. every (channel, group) chunk of the tile into LDS; chunks outside
+    //    the fill read the fill's first chunk instead and are never used
+#pragma unroll
+    for (int it = 0; it < StreamLds::kIters; it++) {
+        const int k = it * NT + tid;
+        const int c = k / G;
+        const int g = k - c * G;
+        const int64_t q = base + (int64_t)g * kVec;
+        const int16_t *src = (k < StreamLds::kChunks && q >= 0 && q < N) ? raw + (int64_t)c * stride + q : raw;
+        __builtin_amdgcn_global_load_lds(src, (lds_void *)(buf + (it * NT + wid * 64) * kVec), 16, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's chunks are in LDS
+    lds_barrier();
+
+    // 2. flags of the tile's groups from the LDS rows (Table 2 waveform-sum and
+    //    threshold rows)
+    if (tid < G) {
+        const int64_t q = base + (int64_t)tid * kVec;
+        uint32_t fb = 0;
+        if (q >= 0 && q < N) {
+            int32_t s[kVec] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 6
+            for (int c = 0; c < C; c++) add8(s, *reinterpret_cast<const uint4 *>(buf + c * ROW + tid * kVec));
+            fb = flags8(s, thr_eff, N - q);
+        }
+        s_bits[tid] = (uint8_t)fb;
+    }
+    constexpr int Wn = (G + 7) >> 3;
+    for (int z = G + tid; z < (Wn + 1) * 8; z += NT) s_bits[z] = 0;
+    lds_barrier();
+
+    const bool owner = tid >= gl && tid < G - gr;
+    const int64_t p = base + (int64_t)tid * kVec;
+    const TileScan r = scan_tile<NT>(a, fd, lt, G, tid, owner, p, s_bits, s_pc, s_wsum, s_excl);
+    write_records(fd, r, p);
+    write_counts(fd, lt, r);
+
+    // 4b. chopped islands from the LDS rows
+    if (fd.out != nullptr && r.tile_m > 0) {
+        if (r.rise) {
+#pragma unroll
+            for (int k = 0; k < kVec; k++) {
+                if ((r.rise >> k) & 1u) {
+                    const int j = r.th_i + __popc(r.rise & ((1u << k) - 1u));
+                    seg_src[j] = tid * kVec + k;
+                    seg_dst[j] = r.th_m + __popc(r.mm & ((1u << k) - 1u));
+                }
+            }
+        }
+        lds_barrier();
+        gather_from_lds<NT>(buf, seg_src, seg_dst, r.tile_i, gl * kVec, fd.out, fd.out_stride, r.m_before,
+                            r.tile_m);
+    }
+}
+
+// ---- the persistent kernel ------------------------------------------------------------
+
+template <int NT, int VARIANT>
+struct KernelLds {
+    static constexpr int kChop = ChopLds<NT>::kBytes;
+    static constexpr int kBytes = (VARIANT == kVariantStream && StreamLds::kBytes > kChop) ? StreamLds::kBytes : kChop;
+};
+
+// Fills whose first-tile indices a work-group keeps in LDS for the lookup.
+constexpr int kLdsFills = 256;
+
+template <int NT, int VARIANT>
 __global__ void __launch_bounds__(NT) k_chop(KArgs a) {
-    __shared__ __align__(16) uint8_t s_lds[ChopLds<NT>::kBytes];
+    __shared__ __align__(16) uint8_t s_lds[KernelLds<NT, VARIANT>::kBytes];
     __shared__ uint32_t s_wsum[NT / 64];
     __shared__ uint64_t s_excl;
     __shared__ int64_t s_tile;
+    __shared__ int64_t s_base[kLdsFills];
 
     const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
     const int64_t total = a.hdr ? a.hdr->total_tiles : a.total_tiles;
-    for (;;) {
-        if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(a.ticket, 1u);
-        __syncthreads();
-        const int64_t tile = s_tile;
-        if (tile >= total) break;
-        // the fill owning this tile: the last one whose first tile is <= tile
+    const bool lds_fills = nf <= kLdsFills;
+    if (lds_fills)
+        for (int i = threadIdx.x; i < nf; i += NT) s_base[i] = tile_base_at(a, i);
+    if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(a.ticket, 1u);
+    lds_barrier();
+    int64_t tile = s_tile;
+    // the fill of the previous tile stays cached: consecutive tiles of a
+    // work-group usually belong to the same fill
+    FillDev fd{};
+    int cur = -1;
+    int32_t thr_eff = 0;
+    // the fill owning a tile: the last one whose first tile is <= tile; the
+    // previous tile's fill stays cached
+    auto lookup = [&](int64_t t) {
+        if (cur >= 0 && t >= fd.tile_base && t < fd.tile_base + fd.n_tiles) return;
         int lo = 0, hi = nf - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (tile_base_at(a, mid) <= tile) lo = mid;
+            if ((lds_fills ? s_base[mid] : tile_base_at(a, mid)) <= t) lo = mid;
             else hi = mid - 1;
         }
-        const FillDev fd = fill_at(a, lo);
-        if (RESIDENT && fd.C == kResidentChannels)
-            chop_tile<NT, RESIDENT>(a, fd, lo, tile, s_lds, s_wsum, &s_excl);
-        else
-            chop_tile<NT, false>(a, fd, lo, tile, s_lds, s_wsum, &s_excl);
-        __syncthreads();
+        fd = fill_at(a, lo);
+        thr_eff = clamp_thr(*gbl(a.thr_eff + lo));
+        cur = lo;
+    };
+    constexpr bool kDeferred =
+        VARIANT == kVariantReload || VARIANT == kVariantReload18 || VARIANT == kVariantReload27;
+    if constexpr (kDeferred) {
+        // Each tile's back half runs one tile later: by then every earlier
+        // tile of its fill has published its total, so the look-back does not
+        // wait, and the next tile's loads are already done.
+        constexpr int R = VARIANT == kVariantReload18 ? 18 : (VARIANT == kVariantReload27 ? 27 : 6);
+        FillDev fd_prev{};
+        ReloadTile prev{};
+        bool have_prev = false;
+        while (tile < total || have_prev) {
+            const bool have_cur = tile < total;
+            ReloadTile now{};
+            if (have_cur) {
+                lookup(tile);
+                now = reload_front<NT, R>(a, fd, thr_eff, tile, s_lds, s_wsum);
+            }
+            if (have_prev) reload_back<NT>(a, fd_prev, prev, s_lds, &s_excl);
+            lds_barrier();
+            // the next tile is taken only now: a dispensed tile must start at
+            // once, because later tiles of its fill wait for its total
+            if (threadIdx.x == 0) s_tile = have_cur ? (int64_t)atomicAdd(a.ticket, 1u) : total;
+            lds_barrier();
+            tile = s_tile;
+            fd_prev = fd;
+            prev = now;
+            have_prev = have_cur;
+        }
+    } else {
+        while (tile < total) {
+            lookup(tile);
+            if constexpr (VARIANT == kVariantStream && NT == kStreamThreads) {
+                if (fd.mode == kModeStream) stream_tile(a, fd, thr_eff, tile, s_lds, s_wsum, &s_excl);
+                else chop_tile<NT, false, 6>(a, fd, thr_eff, tile, s_lds, s_wsum, &s_excl);
+            } else {
+                chop_tile<NT, true, 6>(a, fd, thr_eff, tile, s_lds, s_wsum, &s_excl);  // 54-channel fills only
+            }
+            lds_barrier();
+            // the next tile is taken only now: a dispensed tile must start at
+            // once, because later tiles of its fill wait for its total
+            if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(a.ticket, 1u);
+            lds_barrier();
+            tile = s_tile;
+        }
     }
 }
 
@@ -576,27 +1001,34 @@ hipError_t launch_prepare(const KArgs &a, int blocks, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_chop(const KArgs &a, int threads, bool resident, int grid, hipStream_t s) {
-    if (threads == 256) {
-        if (resident) hipLaunchKernelGGL((k_chop<256, true>), dim3(grid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_chop<256, false>), dim3(grid), dim3(256), 0, s, a);
-    } else if (threads == 512) {
-        if (resident) hipLaunchKernelGGL((k_chop<512, true>), dim3(grid), dim3(512), 0, s, a);
-        else hipLaunchKernelGGL((k_chop<512, false>), dim3(grid), dim3(512), 0, s, a);
-    } else {
-        return hipErrorInvalidValue;
+hipError_t launch_chop(const KArgs &a, int threads, int variant, int grid, hipStream_t s) {
+#define DAQ_LAUNCH(NT_, V_) hipLaunchKernelGGL((k_chop<NT_, V_>), dim3(grid), dim3(NT_), 0, s, a)
+#define DAQ_THREADS(V_)                      \
+    do {                                     \
+        if (threads == 128) DAQ_LAUNCH(128, V_); \
+        else if (threads == 256) DAQ_LAUNCH(256, V_); \
+        else if (threads == 512) DAQ_LAUNCH(512, V_); \
+        else return hipErrorInvalidValue;    \
+    } while (0)
+    switch (variant) {
+        case kVariantStream:
+            if (threads != kStreamThreads) return hipErrorInvalidValue;
+            DAQ_LAUNCH(256, kVariantStream);
+            break;
+        case kVariantReload: DAQ_THREADS(kVariantReload); break;
+        case kVariantResident: DAQ_THREADS(kVariantResident); break;
+        case kVariantReload18: DAQ_THREADS(kVariantReload18); break;
+        case kVariantReload27: DAQ_THREADS(kVariantReload27); break;
+        default: return hipErrorInvalidValue;
     }
+#undef DAQ_THREADS
+#undef DAQ_LAUNCH
     return hipGetLastError();
 }
 
 hipError_t launch_gather(const GatherArgs &g, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_gather, dim3(grid), dim3(256), 0, s, g);
     return hipGetLastError();
-}
-
-int chop_max_threads(int threads, bool resident) {
-    (void)resident;
-    return threads;
 }
 
 }  // namespace daqk

@@ -44,11 +44,11 @@ constexpr int kRing = 4;          // pinned staging slots per stream
 constexpr int kPrepareBlocks = 1024;
 
 struct GraphKey {
-    int threads = 0, wgs = 0, resident = 0;
+    int threads = 0, wgs = 0, variant = 0;
     const void *table = nullptr;
     const void *state = nullptr;
     bool operator==(const GraphKey &o) const {
-        return threads == o.threads && wgs == o.wgs && resident == o.resident && table == o.table &&
+        return threads == o.threads && wgs == o.wgs && variant == o.variant && table == o.table &&
                state == o.state;
     }
 };
@@ -79,7 +79,7 @@ struct daq_ctx {
     int n_cu = 0;
     std::string name;
     std::vector<Scratch *> scratch;
-    daq_schedule sched{256, 4, 0, 0};
+    daq_schedule sched{daqk::kStreamThreads, 2, daqk::kVariantStream, 0};
     bool graphs = true;
     bool timing = false;
     // event pairs bracketing fused-kernel launches while timing is on;
@@ -225,13 +225,13 @@ int check_out(const daq_fill_out *o) {
     return DAQ_OK;
 }
 
-int64_t tiles_of(const daq_fill &f, int threads) {
-    const int64_t T = daqk::tile_shape(f.pre, f.post, threads).tout;
+int64_t tiles_of(const daq_fill &f, const daq_schedule &sc) {
+    const int64_t T = daqk::tile_shape(f.pre, f.post, f.n_channels, sc.threads, sc.variant).tout;
     return (f.n_samples + T - 1) / T;
 }
 
-FillDev make_desc(const daq_fill &f, const daq_fill_out &o, int64_t tile_base, int threads) {
-    const daqk::TileShape ts = daqk::tile_shape(f.pre, f.post, threads);
+FillDev make_desc(const daq_fill &f, const daq_fill_out &o, int64_t tile_base, const daq_schedule &sc) {
+    const daqk::TileShape ts = daqk::tile_shape(f.pre, f.post, f.n_channels, sc.threads, sc.variant);
     FillDev d{};
     d.raw = f.raw;
     d.n = f.n_samples;
@@ -244,9 +244,10 @@ FillDev make_desc(const daq_fill &f, const daq_fill_out &o, int64_t tile_base, i
     d.gl = ts.gl;
     d.gr = ts.gr;
     d.wide = ts.wide;
+    d.mode = ts.mode;
     d.tout = ts.tout;
     d.tile_base = tile_base;
-    d.n_tiles = tiles_of(f, threads);
+    d.n_tiles = tiles_of(f, sc);
     d.isl = o.islands;
     d.cap = o.capacity;
     d.counts = o.counts;
@@ -262,15 +263,13 @@ int chop_grid(const daq_ctx *ctx, const daq_schedule &s, int64_t total_tiles) {
     return (int)std::min<int64_t>(g, 1 << 30);
 }
 
-bool all_resident(const daq_fill *fills, int32_t n) {
+bool all_calorimeters(const daq_fill *fills, int32_t n) {
     for (int32_t i = 0; i < n; i++)
         if (fills[i].n_channels != daqk::kResidentChannels) return false;
     return true;
 }
 
-int launch_pair(daq_ctx *ctx, const KArgs &a, int64_t total_tiles, hipStream_t stream,
-                bool resident) {
-    const daq_schedule &s = ctx->sched;
+int launch_pair(daq_ctx *ctx, const KArgs &a, int64_t total_tiles, hipStream_t stream, const daq_schedule &s) {
     int prep_blocks = (int)std::min<int64_t>(kPrepareBlocks, std::max<int64_t>(1, (total_tiles + 2047) / 2048));
     prep_blocks = std::max(prep_blocks, std::min(a.n_fills, kPrepareBlocks));
     prep_blocks = std::min(prep_blocks, std::max(a.n_fills, 64));
@@ -281,14 +280,14 @@ int launch_pair(daq_ctx *ctx, const KArgs &a, int64_t total_tiles, hipStream_t s
         int rc = timing_begin(ctx, stream, &slot);
         if (rc) return rc;
     }
-    HIP_TRY(daqk::launch_chop(a, s.threads, resident, chop_grid(ctx, s, total_tiles), stream));
+    HIP_TRY(daqk::launch_chop(a, s.threads, s.variant, chop_grid(ctx, s, total_tiles), stream));
     if (ctx->timing) return timing_end(ctx, stream, slot);
     return DAQ_OK;
 }
 
 // Captures the two kernels of a table-driven launch (sizes read from the
 // device header) into two graph execs bound to this scratch.
-int capture_graphs(daq_ctx *ctx, Scratch *s, bool resident) {
+int capture_graphs(daq_ctx *ctx, Scratch *s, const daq_schedule &sc) {
     free_graphs(s);
     if (!ctx->capture) HIP_TRY(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
     KArgs a{};
@@ -307,9 +306,8 @@ int capture_graphs(daq_ctx *ctx, Scratch *s, bool resident) {
     e = hipGraphInstantiate(&s->g_prep, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(e);
-    const daq_schedule &sc = ctx->sched;
     HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
-    e = daqk::launch_chop(a, sc.threads, resident, sc.wgs_per_cu * ctx->n_cu, ctx->capture);
+    e = daqk::launch_chop(a, sc.threads, sc.variant, sc.wgs_per_cu * ctx->n_cu, ctx->capture);
     e2 = hipStreamEndCapture(ctx->capture, &g);
     if (e != hipSuccess) return hip_fail(e);
     if (e2 != hipSuccess) return hip_fail(e2);
@@ -318,7 +316,7 @@ int capture_graphs(daq_ctx *ctx, Scratch *s, bool resident) {
     if (e != hipSuccess) return hip_fail(e);
     s->key.threads = sc.threads;
     s->key.wgs = sc.wgs_per_cu;
-    s->key.resident = resident;
+    s->key.variant = sc.variant;
     s->key.table = s->table;
     s->key.state = s->tile_state;
     return DAQ_OK;
@@ -338,13 +336,15 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     }
     if (n == 0) return DAQ_OK;
     DeviceGuard guard(ctx->device);
-    const daq_schedule sc = ctx->sched;
-    const bool resident = sc.resident && all_resident(fills, n);
+    daq_schedule sc = ctx->sched;
+    // the register variant keeps exactly 54 rows per thread: calls with other
+    // channel counts run the re-read variant
+    if (sc.variant == daqk::kVariantResident && !all_calorimeters(fills, n)) sc.variant = daqk::kVariantReload;
     int64_t total = 0;
     std::vector<int64_t> base((size_t)n);
     for (int32_t i = 0; i < n; i++) {
         base[(size_t)i] = total;
-        total += tiles_of(fills[i], sc.threads);
+        total += tiles_of(fills[i], sc);
     }
     Scratch *s = scratch_for(ctx, stream);
     int rc = ensure_scratch(s, total, n);
@@ -356,8 +356,8 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     a.n_fills = n;
     a.total_tiles = total;
     if (n == 1 && !force_table) {
-        a.one = make_desc(fills[0], outs[0], 0, sc.threads);
-        return launch_pair(ctx, a, total, stream, resident);
+        a.one = make_desc(fills[0], outs[0], 0, sc);
+        return launch_pair(ctx, a, total, stream, sc);
     }
     // stage the descriptors
     const int rs = s->ring_pos;
@@ -368,7 +368,7 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     h->n_fills = n;
     h->pad = 0;
     h->total_tiles = total;
-    for (int32_t i = 0; i < n; i++) tab[i] = make_desc(fills[i], outs[i], base[(size_t)i], sc.threads);
+    for (int32_t i = 0; i < n; i++) tab[i] = make_desc(fills[i], outs[i], base[(size_t)i], sc);
     HIP_TRY(hipMemcpyAsync(s->hdr, h, sizeof(BatchHdr), hipMemcpyHostToDevice, stream));
     HIP_TRY(hipMemcpyAsync(s->table, tab, (size_t)n * sizeof(FillDev), hipMemcpyHostToDevice, stream));
     HIP_TRY(hipEventRecord(s->ring_ev[rs], stream));
@@ -376,15 +376,15 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     a.table = s->table;
     a.hdr = s->hdr;
     const bool use_graph = ctx->graphs && sc.wgs_per_cu > 0;
-    if (!use_graph) return launch_pair(ctx, a, total, stream, resident);
+    if (!use_graph) return launch_pair(ctx, a, total, stream, sc);
     GraphKey want;
     want.threads = sc.threads;
     want.wgs = sc.wgs_per_cu;
-    want.resident = resident;
+    want.variant = sc.variant;
     want.table = s->table;
     want.state = s->tile_state;
     if (!s->g_chop || !(s->key == want)) {
-        rc = capture_graphs(ctx, s, resident);
+        rc = capture_graphs(ctx, s, sc);
         if (rc) return rc;
     }
     HIP_TRY(hipGraphLaunch(s->g_prep, stream));
@@ -578,9 +578,10 @@ int daq_process_batch(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *o
 
 int daq_ctx_set_schedule(daq_ctx *ctx, const daq_schedule *s) {
     if (!ctx || !s) return DAQ_EINVAL;
-    if ((s->threads != 256 && s->threads != 512) || s->wgs_per_cu < 0 || s->wgs_per_cu > 16 ||
-        (s->resident != 0 && s->resident != 1) || s->reserved != 0)
+    if ((s->threads != 128 && s->threads != 256 && s->threads != 512) || s->wgs_per_cu < 0 || s->wgs_per_cu > 16 ||
+        s->variant < daqk::kVariantReload || s->variant > daqk::kVariantLast || s->reserved != 0)
         return DAQ_EINVAL;
+    if (s->variant == daqk::kVariantStream && s->threads != daqk::kStreamThreads) return DAQ_EINVAL;
     ctx->sched = *s;
     return DAQ_OK;
 }
@@ -641,7 +642,7 @@ int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, 
             const size_t bar = line.find('|');
             if (bar == std::string::npos || line.substr(0, bar) != key) continue;
             daq_schedule s{};
-            if (sscanf(line.c_str() + bar + 1, "%d %d %d", &s.threads, &s.wgs_per_cu, &s.resident) == 3 &&
+            if (sscanf(line.c_str() + bar + 1, "%d %d %d", &s.threads, &s.wgs_per_cu, &s.variant) == 3 &&
                 daq_ctx_set_schedule(ctx, &s) == DAQ_OK) {
                 if (best) *best = s;
                 return DAQ_OK;
@@ -649,14 +650,14 @@ int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, 
         }
     }
     std::vector<daq_schedule> cand;
-    const bool res_ok = all_resident(fills, n);
-    for (int threads : {256, 512})
-        for (int wgs : {1, 2, 4, 8})
-            for (int res : {0, 1}) {
-                if (res && !res_ok) continue;
-                if (threads * wgs > 2048) continue;  // a CU holds at most 32 waves
-                cand.push_back(daq_schedule{threads, wgs, res, 0});
-            }
+    const bool calo = all_calorimeters(fills, n);
+    const int V0 = daqk::kVariantReload, V1 = daqk::kVariantResident, V2 = daqk::kVariantStream;
+    const int V3 = daqk::kVariantReload18, V4 = daqk::kVariantReload27;
+    const daq_schedule menu[] = {{256, 4, V0, 0}, {256, 2, V2, 0}, {256, 8, V0, 0}, {512, 2, V0, 0},
+                                 {256, 4, V3, 0}, {256, 3, V3, 0}, {512, 2, V3, 0}, {256, 3, V4, 0},
+                                 {256, 2, V4, 0}, {128, 8, V0, 0}, {256, 1, V1, 0}, {128, 2, V1, 0}};
+    for (const daq_schedule &m : menu)
+        if ((m.variant != V1 && m.variant != V2) || calo) cand.push_back(m);
     const daq_schedule saved = ctx->sched;
     const bool saved_timing = ctx->timing;
     ctx->timing = true;
@@ -700,7 +701,7 @@ int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, 
     if (best) *best = best_s;
     if (cache_path) {
         std::ofstream o(cache_path, std::ios::app);
-        o << key << "|" << best_s.threads << " " << best_s.wgs_per_cu << " " << best_s.resident << " "
+        o << key << "|" << best_s.threads << " " << best_s.wgs_per_cu << " " << best_s.variant << " "
           << best_ms << "\n";
     }
     return DAQ_OK;

@@ -22,7 +22,8 @@ import paper_1611_04959_amd as daq  # noqa: E402
 from gpu_util import (assert_same, dev, log, make_fill, oracle_many, oracle_result, pad_stride,  # noqa: E402
                       run)
 
-SCHEDULES = [(256, 4, 0), (256, 1, 1), (512, 2, 0), (512, 1, 1), (256, 0, 0), (512, 0, 1)]
+SCHEDULES = [(256, 2, 2), (256, 1, 2), (256, 0, 2), (256, 4, 0), (256, 1, 1), (512, 2, 0), (512, 1, 1),
+             (128, 8, 0), (128, 2, 1), (256, 0, 0), (512, 0, 1), (256, 4, 3), (512, 2, 3), (256, 3, 4)]
 MODES = ["chop", "twopass", "batch"]
 
 
@@ -89,7 +90,7 @@ def test_random_fills_all_schedules_and_modes(ctx, sched):
                 o = daq.alloc_out(f)
                 run(ctx, mode, [f], [o])
                 assert_same(o, ref, ctx="C=%d N=%d pre=%d post=%d %s %s" % (C, N, pre, post, sched, mode))
-    ctx.set_schedule(256, 4, 0)
+    ctx.set_schedule(256, 2, 2)
 
 
 def test_batch_of_uneven_random_fills(ctx):
@@ -111,13 +112,13 @@ def test_batch_of_uneven_random_fills(ctx):
         run(ctx, "batch", fills, outs)
         for i, (o, r) in enumerate(zip(outs, refs)):
             assert_same(o, r, ctx="fill %d sched %s" % (i, sched))
-    ctx.set_schedule(256, 4, 0)
+    ctx.set_schedule(256, 2, 2)
 
 
 def test_graph_replays_match_eager(ctx):
     """Replays of the captured graphs, with eager work and syncs between them."""
     rng = np.random.default_rng(17)
-    ctx.set_schedule(256, 4, 0)
+    ctx.set_schedule(256, 2, 2)
     for rep in range(4):
         n = int(rng.integers(2, 9))
         xs = [_random_fill(rng, 54, int(rng.integers(1000, 20_000))) for _ in range(n)]
@@ -264,7 +265,7 @@ def test_workload_plain_single_fill(ctx):
 
 
 def test_workload_16_fills_batched(ctx):
-    ctx.set_schedule(256, 4, 0)
+    ctx.set_schedule(256, 2, 2)
     refs = _workload(synth.config_c1(), "batch", ctx)
     assert sum(r.n_islands for r in refs) > 10_000
 
@@ -298,5 +299,5 @@ def test_autotune_candidates_agree(ctx, tmp_path):
         assert_same(o, r, ctx="after autotune")
     # the cached choice is reused
     best2 = ctx.daq_autotune(fills, outs, cache_path=str(tmp_path / "tune.txt"))
-    assert (best2.threads, best2.wgs_per_cu, best2.resident) == (best.threads, best.wgs_per_cu, best.resident)
-    ctx.set_schedule(256, 4, 0)
+    assert (best2.threads, best2.wgs_per_cu, best2.variant) == (best.threads, best.wgs_per_cu, best.variant)
+    ctx.set_schedule(256, 2, 2)
