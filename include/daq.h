@@ -122,6 +122,10 @@ typedef struct daq_fill_out {
                                   two work-groups per CU (threads = 256)      */
 #define DAQ_VARIANT_RELOAD18 3 /* as RELOAD with 18 rows in flight (6 there) */
 #define DAQ_VARIANT_RELOAD27 4 /* as RELOAD with 27 rows in flight          */
+#define DAQ_VARIANT_SPLIT 5    /* three passes: a streaming scan that writes
+                                  island-mask bits and tile totals, a prefix
+                                  pass, and an emit pass that copies only the
+                                  island samples (threads = 256 or 512)       */
 typedef struct daq_schedule {
     int32_t threads;     /* work-group size: 128, 256 or 512                    */
     int32_t wgs_per_cu;  /* persistent grid = wgs_per_cu x CUs (1..16); 0 =

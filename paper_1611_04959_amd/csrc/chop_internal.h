@@ -22,7 +22,10 @@ constexpr int kVariantResident = 1;  // rows kept in registers until written out
 constexpr int kVariantStream = 2;    // rows DMA'd into LDS; two work-groups per CU
 constexpr int kVariantReload18 = 3;  // as kVariantReload, 18 rows in flight per round (6 there)
 constexpr int kVariantReload27 = 4;  // as kVariantReload, 27 rows in flight per round
-constexpr int kVariantLast = 4;
+constexpr int kVariantSplit = 5;     // scan pass (mask bits, tile totals), prefix pass, emit pass
+constexpr int kVariantLast = 5;
+// Guard bytes around each fill's island-mask bits (read as zero past the ends).
+constexpr int kMaskGuard = 16;
 // Tile of the LDS variant: groups of 8 samples per row buffer, work-group size.
 constexpr int kStreamGroups = 80;
 constexpr int kStreamThreads = 256;
@@ -55,7 +58,8 @@ struct FillDev {
     int32_t *ped;       // may be null
     int16_t *out;       // may be null (find only)
     int64_t out_stride;
-    int64_t pad2;       // size: a whole number of 16-byte words
+    uint8_t *mbits;     // split variant: island-mask bits of the fill (bit t of
+                        // byte t / 8), kMaskGuard zero bytes on either side
 };
 static_assert(sizeof(FillDev) % 16 == 0, "descriptors are read as 16-byte words");
 
@@ -73,9 +77,10 @@ struct KArgs {
     int32_t n_fills;
     int32_t pad;
     int64_t total_tiles;
-    uint64_t *tile_state;  // one look-back word per tile
+    uint64_t *tile_state;  // one look-back word per tile (split variant: tile totals)
     uint32_t *ticket;      // tile dispenser
     int64_t *thr_eff;      // per fill: threshold + sum of pedestals
+    uint64_t *tile_pref;   // split variant: exclusive prefix of each tile
     FillDev one;
 };
 
@@ -117,6 +122,8 @@ inline TileShape tile_shape(int32_t pre, int32_t post, int32_t channels, int thr
 
 hipError_t launch_prepare(const KArgs &a, int blocks, hipStream_t s);
 hipError_t launch_chop(const KArgs &a, int threads, int variant, int grid, hipStream_t s);
+// Split variant: scan pass, per-fill prefix pass, emit pass.
+hipError_t launch_split(const KArgs &a, int threads, int grid, int prefix_blocks, hipStream_t s);
 hipError_t launch_gather(const GatherArgs &g, int grid, hipStream_t s);
 
 }  // namespace daqk

@@ -101,13 +101,19 @@ __device__ __forceinline__ int64_t tile_base_at(const KArgs &a, int f) {
     return a.table ? gbl(a.table + f)->tile_base : a.one.tile_base;
 }
 
-// Adds the eight int16 samples of one 16-byte row chunk to eight sums.
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+// Adds the eight int16 samples of one 16-byte row chunk to eight sums: one
+// 2-way int16 dot product per sample (with weights (1, 0) or (0, 1)), exact.
 __device__ __forceinline__ void add8(int32_t (&s)[kVec], const uint4 v) {
     const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    const s16x2 lo = {1, 0};
+    const s16x2 hi = {0, 1};
 #pragma unroll
     for (int i = 0; i < 4; i++) {
-        s[2 * i] += (int32_t)(int16_t)(w[i] & 0xFFFFu);
-        s[2 * i + 1] += ((int32_t)w[i]) >> 16;
+        const s16x2 x = __builtin_bit_cast(s16x2, w[i]);
+        s[2 * i] = __builtin_amdgcn_sdot2(x, lo, s[2 * i], false);
+        s[2 * i + 1] = __builtin_amdgcn_sdot2(x, hi, s[2 * i + 1], false);
     }
 }
 
@@ -899,6 +905,346 @@ __global__ void __launch_bounds__(NT) k_chop(KArgs a) {
     }
 }
 
+// ---- variant 5: scan pass, prefix pass, emit pass -----------------------------------
+//
+// The scan pass streams the raw rows once and keeps nothing: per tile it
+// writes the island-mask bits of the samples it owns and the tile's totals.
+// A prefix pass turns the totals into each tile's exclusive prefix (and the
+// fill's counts); the emit pass writes the island records and copies only the
+// island samples. No tile waits for another, so the streaming pass keeps as
+// many loads in flight as the CU holds.
+
+// Scan pass, one tile: flags, dilation, mask bits, totals.
+template <int NT, int R>
+__device__ __forceinline__ void scan_pass_tile(const KArgs &a, const FillDev &fd, int32_t thr_eff, int64_t tile,
+                                               uint8_t *lds, uint32_t *s_wsum) {
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    const ChopGeom<NT> q(fd, tile);
+    const int64_t N = fd.n;
+    uint8_t *s_bits = lds;
+    uint32_t *s_pc = reinterpret_cast<uint32_t *>(lds + ChopLds<NT>::kWords * 8);
+    chop_flags<NT, R>(fd, q, thr_eff, s_bits);
+    const int Wn = (q.G + 7) >> 3;
+    const uint64_t *words = reinterpret_cast<const uint64_t *>(s_bits);
+    if (wid == 0) {
+        uint32_t carry = 0;
+        for (int w0 = 0; w0 <= Wn; w0 += 64) {
+            const int w = w0 + lane;
+            const uint32_t c = (w <= Wn) ? (uint32_t)__popcll(words[w]) : 0u;
+            const uint32_t inc = wave_incl_scan_u32(c, lane);
+            if (w <= Wn) s_pc[w] = carry + inc - c;
+            carry += __shfl(inc, 63, 64);
+        }
+    }
+    lds_barrier();
+    // dilation (Table 2 pre/post row) of the owned samples p-1 .. p+8
+    uint32_t m10 = 0;
+    if (q.owner) {
+        const int r0 = q.g * kVec;
+        uint32_t lo[10], hi[10];
+        prefix_bits10(words, s_pc, r0 - 1 - fd.post, lo);
+        prefix_bits10(words, s_pc, r0 + fd.pre, hi);
+#pragma unroll
+        for (int j = 0; j < 10; j++) {
+            const int64_t t = q.p + j - 1;
+            const bool in = (hi[j] != lo[j]) && t >= 0 && t < N;
+            m10 |= (in ? 1u : 0u) << j;
+        }
+        // the owned samples' mask byte: t0 is a multiple of 8
+        const int64_t byte = (q.t0 >> 3) + (q.g - fd.gl);
+        *gbl(fd.mbits + byte) = (uint8_t)((m10 >> 1) & 0xFFu);
+    }
+    const uint32_t mm = (m10 >> 1) & 0xFFu;
+    const uint32_t rise = mm & ~(((mm << 1) | (m10 & 1u)) & 0xFFu);
+    // tile totals (island samples, islands begun in the tile)
+    uint32_t mine = ((uint32_t)__popc(mm) << 16) | (uint32_t)__popc(rise);
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) mine += __shfl_xor(mine, d, 64);
+    if (lane == 0) s_wsum[wid] = mine;
+    lds_barrier();
+    if (tid == 0) {
+        uint32_t total = 0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) total += s_wsum[w];
+        *gbl(a.tile_state + tile) = ((uint64_t)(total >> 16) << 31) | (uint64_t)(total & 0xFFFFu);
+    }
+}
+
+template <int NT, int R>
+__global__ void __launch_bounds__(NT) k_scan_pass(KArgs a) {
+    __shared__ __align__(16) uint8_t s_lds[ChopLds<NT>::kBitsBytes];
+    __shared__ uint32_t s_wsum[NT / 64];
+    __shared__ int64_t s_base[kLdsFills];
+    const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
+    const int64_t total = a.hdr ? a.hdr->total_tiles : a.total_tiles;
+    const bool lds_fills = nf <= kLdsFills;
+    if (lds_fills)
+        for (int i = threadIdx.x; i < nf; i += NT) s_base[i] = tile_base_at(a, i);
+    lds_barrier();
+    FillDev fd{};
+    int cur = -1;
+    int32_t thr_eff = 0;
+    for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        if (cur < 0 || tile < fd.tile_base || tile >= fd.tile_base + fd.n_tiles) {
+            int lo = 0, hi = nf - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if ((lds_fills ? s_base[mid] : tile_base_at(a, mid)) <= tile) lo = mid;
+                else hi = mid - 1;
+            }
+            fd = fill_at(a, lo);
+            thr_eff = clamp_thr(*gbl(a.thr_eff + lo));
+            cur = lo;
+        }
+        scan_pass_tile<NT, R>(a, fd, thr_eff, tile, s_lds, s_wsum);
+        lds_barrier();
+    }
+}
+
+// Prefix pass: a block per fill scans the fill's tile totals into exclusive
+// prefixes and writes the fill's counts.
+__global__ void __launch_bounds__(256) k_prefix_pass(KArgs a) {
+    __shared__ uint64_t s_w[4];
+    const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    for (int f = blockIdx.x; f < nf; f += gridDim.x) {
+        const FillDev fd = fill_at(a, f);
+        uint64_t carry = 0;
+        for (int64_t i0 = 0; i0 < fd.n_tiles; i0 += 256) {
+            const int64_t i = i0 + threadIdx.x;
+            const uint64_t v = i < fd.n_tiles ? *gbl(a.tile_state + fd.tile_base + i) : 0ull;
+            uint64_t inc = v;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint64_t u = __shfl_up(inc, d, 64);
+                if (lane >= d) inc += u;
+            }
+            if (lane == 63) s_w[wid] = inc;
+            lds_barrier();
+            uint64_t before = carry, all = carry;
+#pragma unroll
+            for (int w = 0; w < 4; w++) {
+                before += (w < wid) ? s_w[w] : 0ull;
+                all += s_w[w];
+            }
+            if (i < fd.n_tiles) *gbl(a.tile_pref + fd.tile_base + i) = before + inc - v;
+            carry = all;
+            lds_barrier();
+        }
+        if (threadIdx.x == 0 && fd.counts != nullptr) {
+            const int64_t n_isl = (int64_t)(carry & kField);
+            const int64_t tl = (int64_t)((carry >> 31) & kField);
+            int32_t status = (n_isl > fd.cap) ? DAQ_STATUS_CAPACITY : 0;
+            if (fd.out != nullptr && tl > fd.out_stride) status |= DAQ_STATUS_OUT_STRIDE;
+            DAQ_GLOBAL daq_counts *cnt = gbl(fd.counts);
+            cnt->n_islands = n_isl;
+            cnt->total_len = tl;
+            cnt->status = status;
+            cnt->reserved = 0;
+        }
+    }
+}
+
+// Sample e (0..7) of an 8-sample vector.
+__device__ __forceinline__ int16_t sample_of(const uint4 v, int e) {
+    const uint32_t w = (e < 2) ? v.x : (e < 4) ? v.y : (e < 6) ? v.z : v.w;
+    return (int16_t)((e & 1) ? (w >> 16) : (w & 0xFFFFu));
+}
+
+// Chopped islands of one tile copied from the raw rows (emit pass). Run r
+// moves tile samples [src_r, src_r + len_r) to packed positions [dst_r,
+// dst_r + len_r) (tile-relative); kpref[r] counts the 16-byte destination
+// lines reserved for the runs before r. A work item is (channel, run, line):
+// its source is contiguous, read as two aligned 16-byte words and realigned;
+// a line wholly inside the run is one 16-byte store, the run's edge lines
+// store their own samples only. Loads of U items are issued before stores.
+template <int NT>
+__device__ __forceinline__ void emit_runs(const int32_t *seg_src, const int32_t *seg_dst, const int32_t *kpref,
+                                          int nrun, int tile_m, const int16_t *raw, int64_t stride, int64_t t0,
+                                          int16_t *out, int64_t ostride, int C, int64_t m0) {
+    constexpr int U = 4;
+    const int ktot = kpref[nrun];
+    const int items = C * ktot;
+    for (int i0 = threadIdx.x; i0 < items; i0 += NT * U) {
+        uint4 A[U], B[U];
+        int cs[U], e0s[U], e1s[U], sh[U];
+        int64_t first[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int i = i0 + u * NT;
+            A[u] = make_uint4(0, 0, 0, 0);
+            B[u] = make_uint4(0, 0, 0, 0);
+            e0s[u] = 0;
+            e1s[u] = 0;  // empty
+            cs[u] = 0;
+            sh[u] = 0;
+            first[u] = 0;
+            if (i >= items) continue;
+            const int c = i / ktot;
+            const int rem = i - c * ktot;
+            int lo = 0, hi = nrun - 1;  // last run with kpref[r] <= rem
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (kpref[mid] <= rem) lo = mid;
+                else hi = mid - 1;
+            }
+            const int r = lo;
+            const int k = rem - kpref[r];
+            const int len = ((r + 1 < nrun) ? seg_dst[r + 1] : tile_m) - seg_dst[r];
+            const int16_t *orow_c = out + (int64_t)c * ostride;
+            const int64_t D = m0 + seg_dst[r];
+            const int64_t f0 = D - line_phase(orow_c, D) + 8 * k;  // packed position of the line's sample 0
+            int64_t lo_p = f0 > D ? f0 : D;
+            int64_t hi_p = f0 + 8;
+            if (hi_p > D + len) hi_p = D + len;
+            if (hi_p > ostride) hi_p = ostride;
+            if (lo_p >= hi_p) continue;
+            const int e0 = (int)(lo_p - f0), e1 = (int)(hi_p - f0);
+            const int sv = seg_src[r] + (int)(lo_p - D);  // tile-relative source of sample e0
+            const int16_t *row = raw + (int64_t)c * stride + t0;  // t0 is a multiple of 8
+            const int a0 = sv & ~7;
+            A[u] = load16(row + a0);
+            if ((sv & 7) + (e1 - e0) > 8) B[u] = load16(row + a0 + 8);
+            cs[u] = c;
+            e0s[u] = e0;
+            e1s[u] = e1;
+            sh[u] = sv & 7;
+            first[u] = f0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (e1s[u] <= e0s[u]) continue;
+            int16_t *orow = out + (int64_t)cs[u] * ostride + first[u];
+            const uint4 v = realign8(A[u], B[u], sh[u]);
+            if (e0s[u] == 0 && e1s[u] == 8) {
+                store16(orow, v);
+            } else {
+                for (int e = e0s[u]; e < e1s[u]; e++) *gbl(orow + e) = sample_of(v, e - e0s[u]);
+            }
+        }
+    }
+}
+
+// Emit pass, one tile: island edges from the mask bits, records, packed
+// samples. Thread j takes the tile's owned samples t0 + 8j .. t0 + 8j + 7.
+// Run 0 of the run table is the island open at the tile's first sample (it
+// may be empty); the others start at the tile's rising edges.
+template <int NT>
+__device__ __forceinline__ void emit_pass_tile(const KArgs &a, const FillDev &fd, int64_t tile, int32_t *seg_src,
+                                               int32_t *seg_dst, int32_t *kpref, uint32_t *s_wsum) {
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    const int64_t lt = tile - fd.tile_base;
+    const int64_t t0 = lt * fd.tout;
+    const int own = (int)(fd.tout / kVec);  // owned groups
+    const int64_t p = t0 + (int64_t)tid * kVec;
+    const uint8_t *mb = fd.mbits + (t0 >> 3);
+    uint32_t mm = 0, prv = 0, nxt = 0;
+    if (tid < own) {
+        mm = *gbl(mb + tid);
+        prv = (*gbl(mb + tid - 1) >> 7) & 1u;  // a zero guard byte before the fill
+        nxt = *gbl(mb + tid + 1) & 1u;         // a zero guard byte after the fill
+    }
+    TileScan r;
+    r.mm = mm;
+    r.rise = mm & ~(((mm << 1) | prv) & 0xFFu);
+    r.fall = mm & ~((mm >> 1) | (nxt << 7));
+    const uint32_t mine = ((uint32_t)__popc(r.mm) << 16) | (uint32_t)__popc(r.rise);
+    const uint32_t inc = wave_incl_scan_u32(mine, lane);
+    if (lane == 63) s_wsum[wid] = inc;
+    lds_barrier();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < NW; w++) {
+        const uint32_t v = s_wsum[w];
+        before += (w < wid) ? v : 0u;
+        total += v;
+    }
+    const uint32_t excl = before + inc - mine;
+    r.th_m = (int)(excl >> 16);
+    r.th_i = (int)(excl & 0xFFFFu);
+    r.tile_m = (int)(total >> 16);
+    r.tile_i = (int)(total & 0xFFFFu);
+    const uint64_t pref = *gbl(a.tile_pref + tile);
+    r.m_before = (int64_t)((pref >> 31) & kField);
+    r.i_before = (int64_t)(pref & kField);
+    write_records(fd, r, p);
+    if (fd.out == nullptr || r.tile_m == 0) return;
+    if (tid == 0) {
+        seg_src[0] = 0;
+        seg_dst[0] = 0;
+    }
+    if (r.rise) {
+#pragma unroll
+        for (int k = 0; k < kVec; k++) {
+            if ((r.rise >> k) & 1u) {
+                const int j = 1 + r.th_i + __popc(r.rise & ((1u << k) - 1u));
+                seg_src[j] = tid * kVec + k;
+                seg_dst[j] = r.th_m + __popc(r.mm & ((1u << k) - 1u));
+            }
+        }
+    }
+    lds_barrier();
+    // lines reserved per run: enough for any phase of the destination line
+    const int nrun = r.tile_i + 1;
+    if (wid == 0) {
+        int carry = 0;
+        for (int r0 = 0; r0 < nrun; r0 += 64) {
+            const int rr = r0 + lane;
+            int kcount = 0;
+            if (rr < nrun) {
+                const int len = ((rr + 1 < nrun) ? seg_dst[rr + 1] : r.tile_m) - seg_dst[rr];
+                kcount = len > 0 ? (len + 14) >> 3 : 0;
+            }
+            const uint32_t incl = wave_incl_scan_u32((uint32_t)kcount, lane);
+            if (rr < nrun) kpref[rr] = carry + (int)incl - kcount;
+            carry += (int)__shfl(incl, 63, 64);
+        }
+        if (lane == 0) kpref[nrun] = carry;
+    }
+    lds_barrier();
+    emit_runs<NT>(seg_src, seg_dst, kpref, nrun, r.tile_m, fd.raw, fd.stride, t0, fd.out, fd.out_stride, fd.C,
+                  r.m_before);
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_emit_pass(KArgs a) {
+    constexpr int kMaxRuns = NT * kVec / 2 + 3;  // the open run, the rises, a sentinel
+    __shared__ int32_t s_src[kMaxRuns];
+    __shared__ int32_t s_dst[kMaxRuns];
+    __shared__ int32_t s_kpref[kMaxRuns];
+    __shared__ uint32_t s_wsum[NT / 64];
+    __shared__ int64_t s_base[kLdsFills];
+    const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
+    const int64_t total = a.hdr ? a.hdr->total_tiles : a.total_tiles;
+    const bool lds_fills = nf <= kLdsFills;
+    if (lds_fills)
+        for (int i = threadIdx.x; i < nf; i += NT) s_base[i] = tile_base_at(a, i);
+    lds_barrier();
+    FillDev fd{};
+    int cur = -1;
+    for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        if (cur < 0 || tile < fd.tile_base || tile >= fd.tile_base + fd.n_tiles) {
+            int lo = 0, hi = nf - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if ((lds_fills ? s_base[mid] : tile_base_at(a, mid)) <= tile) lo = mid;
+                else hi = mid - 1;
+            }
+            fd = fill_at(a, lo);
+            cur = lo;
+        }
+        emit_pass_tile<NT>(a, fd, tile, s_src, s_dst, s_kpref, s_wsum);
+        lds_barrier();
+    }
+}
+
 // Pedestals (Table 2 pedestal row), effective thresholds, cleared look-back
 // words and counts. A block handles whole fills; its threads take
 // (channel, 8-sample chunk) pairs of the pedestal window with 16-byte loads.
@@ -940,6 +1286,11 @@ __global__ void __launch_bounds__(256) k_prepare(KArgs a) {
                 atomicAdd(reinterpret_cast<unsigned long long *>(&s_ped), (unsigned long long)(long long)ped);
             }
             __syncthreads();
+        }
+        if (fd.mbits != nullptr && threadIdx.x < 2 * kMaskGuard) {
+            const int64_t nbytes = fd.n_tiles * fd.tout / kVec;
+            const int i = threadIdx.x;
+            fd.mbits[i < kMaskGuard ? i - kMaskGuard : nbytes + (i - kMaskGuard)] = 0;
         }
         if (threadIdx.x == 0) {
             a.thr_eff[f] = (int64_t)fd.thr + (int64_t)s_ped;
@@ -1023,6 +1374,21 @@ hipError_t launch_chop(const KArgs &a, int threads, int variant, int grid, hipSt
     }
 #undef DAQ_THREADS
 #undef DAQ_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_split(const KArgs &a, int threads, int grid, int prefix_blocks, hipStream_t s) {
+    if (threads == 256) {
+        hipLaunchKernelGGL((k_scan_pass<256, 6>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_prefix_pass, dim3(prefix_blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_emit_pass<256>), dim3(grid), dim3(256), 0, s, a);
+    } else if (threads == 512) {
+        hipLaunchKernelGGL((k_scan_pass<512, 6>), dim3(grid), dim3(512), 0, s, a);
+        hipLaunchKernelGGL(k_prefix_pass, dim3(prefix_blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_emit_pass<512>), dim3(grid), dim3(512), 0, s, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

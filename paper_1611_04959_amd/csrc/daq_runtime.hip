@@ -42,6 +42,7 @@ int hip_fail(hipError_t e) {
 
 constexpr int kRing = 4;          // pinned staging slots per stream
 constexpr int kPrepareBlocks = 1024;
+constexpr int kPrefixBlocks = 256;
 
 struct GraphKey {
     int threads = 0, wgs = 0, variant = 0;
@@ -70,6 +71,9 @@ struct Scratch {
     GraphKey key;
     uint64_t *digest = nullptr;  // autotune digests
     int32_t digest_cap = 0;
+    uint64_t *tile_pref = nullptr;  // split variant: tile prefixes (tile_cap)
+    uint8_t *mask = nullptr;        // split variant: island-mask bits of all fills
+    int64_t mask_cap = 0;
 };
 
 }  // namespace
@@ -145,6 +149,8 @@ void free_scratch(Scratch *s) {
     (void)hipFree(s->table);
     (void)hipFree(s->hdr);
     (void)hipFree(s->digest);
+    (void)hipFree(s->tile_pref);
+    (void)hipFree(s->mask);
     for (int i = 0; i < kRing; i++) {
         if (s->ring_ev[i]) (void)hipEventDestroy(s->ring_ev[i]);
         if (s->ring_host[i]) (void)hipHostFree(s->ring_host[i]);
@@ -163,18 +169,30 @@ Scratch *scratch_for(daq_ctx *ctx, hipStream_t stream) {
 
 // Grows the scratch of one stream; waits for that stream first because the
 // old buffers may still be in use by queued work or captured graphs.
-int ensure_scratch(Scratch *s, int64_t tiles, int32_t fills) {
+int ensure_scratch(Scratch *s, int64_t tiles, int32_t fills, int64_t mask_bytes) {
     if (!s->ticket) HIP_TRY(hipMalloc(&s->ticket, 64));
-    if (tiles <= s->tile_cap && fills <= s->fill_cap && s->ring_host[0]) return DAQ_OK;
+    if (tiles <= s->tile_cap && fills <= s->fill_cap && s->ring_host[0] && mask_bytes <= s->mask_cap)
+        return DAQ_OK;
     HIP_TRY(hipStreamSynchronize(s->stream));
     free_graphs(s);
     if (tiles > s->tile_cap) {
         int64_t cap = std::max<int64_t>(tiles + tiles / 2, 4096);
         (void)hipFree(s->tile_state);
+        (void)hipFree(s->tile_pref);
         s->tile_state = nullptr;
+        s->tile_pref = nullptr;
         s->tile_cap = 0;
         HIP_TRY(hipMalloc(&s->tile_state, (size_t)cap * sizeof(uint64_t)));
+        HIP_TRY(hipMalloc(&s->tile_pref, (size_t)cap * sizeof(uint64_t)));
         s->tile_cap = cap;
+    }
+    if (mask_bytes > s->mask_cap) {
+        const int64_t cap = std::max<int64_t>(mask_bytes + mask_bytes / 2, 1 << 20);
+        (void)hipFree(s->mask);
+        s->mask = nullptr;
+        s->mask_cap = 0;
+        HIP_TRY(hipMalloc(&s->mask, (size_t)cap));
+        s->mask_cap = cap;
     }
     if (fills > s->fill_cap || !s->ring_host[0]) {
         int32_t cap = std::max<int32_t>(fills + fills / 2, 64);
@@ -230,6 +248,13 @@ int64_t tiles_of(const daq_fill &f, const daq_schedule &sc) {
     return (f.n_samples + T - 1) / T;
 }
 
+// Bytes of island-mask bits (with guards) the split variant needs for a fill.
+int64_t mask_bytes_of(const daq_fill &f, const daq_schedule &sc) {
+    const int64_t tout = daqk::tile_shape(f.pre, f.post, f.n_channels, sc.threads, sc.variant).tout;
+    const int64_t data = tiles_of(f, sc) * tout / daqk::kVec;
+    return (data + 2 * daqk::kMaskGuard + 15) / 16 * 16;
+}
+
 FillDev make_desc(const daq_fill &f, const daq_fill_out &o, int64_t tile_base, const daq_schedule &sc) {
     const daqk::TileShape ts = daqk::tile_shape(f.pre, f.post, f.n_channels, sc.threads, sc.variant);
     FillDev d{};
@@ -269,6 +294,17 @@ bool all_calorimeters(const daq_fill *fills, int32_t n) {
     return true;
 }
 
+int launch_main(const daq_ctx *ctx, const KArgs &a, const daq_schedule &s, int grid, hipStream_t stream) {
+    if (s.variant == daqk::kVariantSplit) {
+        const int pb = std::max(1, std::min(a.hdr ? kPrefixBlocks : a.n_fills, kPrefixBlocks));
+        HIP_TRY(daqk::launch_split(a, s.threads, grid, pb, stream));
+        return DAQ_OK;
+    }
+    (void)ctx;
+    HIP_TRY(daqk::launch_chop(a, s.threads, s.variant, grid, stream));
+    return DAQ_OK;
+}
+
 int launch_pair(daq_ctx *ctx, const KArgs &a, int64_t total_tiles, hipStream_t stream, const daq_schedule &s) {
     int prep_blocks = (int)std::min<int64_t>(kPrepareBlocks, std::max<int64_t>(1, (total_tiles + 2047) / 2048));
     prep_blocks = std::max(prep_blocks, std::min(a.n_fills, kPrepareBlocks));
@@ -280,7 +316,8 @@ int launch_pair(daq_ctx *ctx, const KArgs &a, int64_t total_tiles, hipStream_t s
         int rc = timing_begin(ctx, stream, &slot);
         if (rc) return rc;
     }
-    HIP_TRY(daqk::launch_chop(a, s.threads, s.variant, chop_grid(ctx, s, total_tiles), stream));
+    int rc = launch_main(ctx, a, s, chop_grid(ctx, s, total_tiles), stream);
+    if (rc) return rc;
     if (ctx->timing) return timing_end(ctx, stream, slot);
     return DAQ_OK;
 }
@@ -296,6 +333,7 @@ int capture_graphs(daq_ctx *ctx, Scratch *s, const daq_schedule &sc) {
     a.tile_state = s->tile_state;
     a.ticket = s->ticket;
     a.thr_eff = s->thr_eff;
+    a.tile_pref = s->tile_pref;
     hipGraph_t g = nullptr;
     // prepare: grid covers the largest table this scratch holds
     HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
@@ -307,9 +345,9 @@ int capture_graphs(daq_ctx *ctx, Scratch *s, const daq_schedule &sc) {
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(e);
     HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
-    e = daqk::launch_chop(a, sc.threads, sc.variant, sc.wgs_per_cu * ctx->n_cu, ctx->capture);
+    const int rc0 = launch_main(ctx, a, sc, sc.wgs_per_cu * ctx->n_cu, ctx->capture);
     e2 = hipStreamEndCapture(ctx->capture, &g);
-    if (e != hipSuccess) return hip_fail(e);
+    if (rc0) return rc0;
     if (e2 != hipSuccess) return hip_fail(e2);
     e = hipGraphInstantiate(&s->g_chop, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -340,23 +378,34 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     // the register variant keeps exactly 54 rows per thread: calls with other
     // channel counts run the re-read variant
     if (sc.variant == daqk::kVariantResident && !all_calorimeters(fills, n)) sc.variant = daqk::kVariantReload;
-    int64_t total = 0;
-    std::vector<int64_t> base((size_t)n);
+    int64_t total = 0, mask_total = 0;
+    std::vector<int64_t> base((size_t)n), moff((size_t)n, -1);
+    const bool split = sc.variant == daqk::kVariantSplit;
     for (int32_t i = 0; i < n; i++) {
         base[(size_t)i] = total;
         total += tiles_of(fills[i], sc);
+        if (split) {
+            moff[(size_t)i] = mask_total;
+            mask_total += mask_bytes_of(fills[i], sc);
+        }
     }
     Scratch *s = scratch_for(ctx, stream);
-    int rc = ensure_scratch(s, total, n);
+    int rc = ensure_scratch(s, total, n, mask_total);
     if (rc) return rc;
+    auto desc = [&](int32_t i) {
+        FillDev d = make_desc(fills[i], outs[i], base[(size_t)i], sc);
+        d.mbits = split ? s->mask + moff[(size_t)i] + daqk::kMaskGuard : nullptr;
+        return d;
+    };
     KArgs a{};
     a.tile_state = s->tile_state;
     a.ticket = s->ticket;
     a.thr_eff = s->thr_eff;
+    a.tile_pref = s->tile_pref;
     a.n_fills = n;
     a.total_tiles = total;
     if (n == 1 && !force_table) {
-        a.one = make_desc(fills[0], outs[0], 0, sc);
+        a.one = desc(0);
         return launch_pair(ctx, a, total, stream, sc);
     }
     // stage the descriptors
@@ -368,7 +417,7 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     h->n_fills = n;
     h->pad = 0;
     h->total_tiles = total;
-    for (int32_t i = 0; i < n; i++) tab[i] = make_desc(fills[i], outs[i], base[(size_t)i], sc);
+    for (int32_t i = 0; i < n; i++) tab[i] = desc(i);
     HIP_TRY(hipMemcpyAsync(s->hdr, h, sizeof(BatchHdr), hipMemcpyHostToDevice, stream));
     HIP_TRY(hipMemcpyAsync(s->table, tab, (size_t)n * sizeof(FillDev), hipMemcpyHostToDevice, stream));
     HIP_TRY(hipEventRecord(s->ring_ev[rs], stream));
@@ -582,6 +631,7 @@ int daq_ctx_set_schedule(daq_ctx *ctx, const daq_schedule *s) {
         s->variant < daqk::kVariantReload || s->variant > daqk::kVariantLast || s->reserved != 0)
         return DAQ_EINVAL;
     if (s->variant == daqk::kVariantStream && s->threads != daqk::kStreamThreads) return DAQ_EINVAL;
+    if (s->variant == daqk::kVariantSplit && s->threads == 128) return DAQ_EINVAL;
     ctx->sched = *s;
     return DAQ_OK;
 }
@@ -652,8 +702,9 @@ int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, 
     std::vector<daq_schedule> cand;
     const bool calo = all_calorimeters(fills, n);
     const int V0 = daqk::kVariantReload, V1 = daqk::kVariantResident, V2 = daqk::kVariantStream;
-    const int V3 = daqk::kVariantReload18, V4 = daqk::kVariantReload27;
-    const daq_schedule menu[] = {{256, 4, V0, 0}, {256, 2, V2, 0}, {256, 8, V0, 0}, {512, 2, V0, 0},
+    const int V3 = daqk::kVariantReload18, V4 = daqk::kVariantReload27, V5 = daqk::kVariantSplit;
+    const daq_schedule menu[] = {{256, 8, V5, 0}, {256, 4, V5, 0}, {512, 2, V5, 0}, {512, 4, V5, 0},
+                                 {256, 4, V0, 0}, {256, 2, V2, 0}, {256, 8, V0, 0}, {512, 2, V0, 0},
                                  {256, 4, V3, 0}, {256, 3, V3, 0}, {512, 2, V3, 0}, {256, 3, V4, 0},
                                  {256, 2, V4, 0}, {128, 8, V0, 0}, {256, 1, V1, 0}, {128, 2, V1, 0}};
     for (const daq_schedule &m : menu)

@@ -23,7 +23,8 @@ from gpu_util import (assert_same, dev, log, make_fill, oracle_many, oracle_resu
                       run)
 
 SCHEDULES = [(256, 2, 2), (256, 1, 2), (256, 0, 2), (256, 4, 0), (256, 1, 1), (512, 2, 0), (512, 1, 1),
-             (128, 8, 0), (128, 2, 1), (256, 0, 0), (512, 0, 1), (256, 4, 3), (512, 2, 3), (256, 3, 4)]
+             (128, 8, 0), (128, 2, 1), (256, 0, 0), (512, 0, 1), (256, 4, 3), (512, 2, 3), (256, 3, 4),
+             (256, 8, 5), (512, 2, 5), (256, 0, 5)]
 MODES = ["chop", "twopass", "batch"]
 
 
