@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "raw ADC GB/s island-chopped & % HBM peak; p99 fill latency, batched vs plain"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "chop_fused_16fills_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "chop_16fills_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1611_04959_amd", "csrc", "chop_kernels.hip")
 
 
@@ -144,7 +144,9 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                "traffic": traffic, "kernel": "k_chop (fused find + gather)",
+                "traffic": traffic,
+                "kernel": ("chop pass = k_scan_pass + k_prefix_pass + k_emit_pass" if sched[2] == 5
+                           else "k_chop (fused find + gather)"),
                 "kernel_ms_mean": round(kmean, 4) if kmean else None,
                 "kernel_launches_timed": len(kern_ms),
                 "algorithmic_bytes_per_launch": alg_bytes}

@@ -157,6 +157,8 @@ int64_t daq_max_islands(int64_t n_samples, int32_t pre, int32_t post);
 int daq_ctx_create(daq_ctx **out, int device);
 /* Waits for the context's streams, frees its scratch and graphs. NULL ok. */
 void daq_ctx_destroy(daq_ctx *ctx);
+/* HIP device of the context. */
+int daq_ctx_get_device(daq_ctx *ctx, int *device);
 
 /* Pedestals, sum, threshold, dilation, merge and island array for one fill
  * (Table 2 rows 1-6). Writes capacity records at most to d_islands (in
@@ -223,6 +225,99 @@ int daq_ctx_kernel_times(daq_ctx *ctx, float *ms, int32_t max);
 int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs,
                  int32_t n, void *stream, const char *cache_path,
                  daq_schedule *best);
+
+/* ---- serving loop ----------------------------------------------------------
+ * Fills arrive in bursts, eight fills 10 ms apart (Section 3), and records
+ * must be deadtime-free (abstract): a fill has to be taken while earlier
+ * ones are still being processed. A
+ * server admits each submitted fill only if its results fit in the device
+ * arena it was given (the HBM budget) and keeps them resident there until
+ * the caller releases them. Worker threads, one per HIP stream, take every
+ * admitted fill not yet running (up to max_batch, oldest first) and launch
+ * them as one batch (daq_process_batch); fills that arrive while a batch
+ * runs go out with the next free worker on its own stream, so batches
+ * overlap on the device. Each fill's results are the same as those of
+ * daq_chop_fill on that fill alone.
+ *
+ * Slot of one fill in the arena, in this order, each part aligned to 256
+ * bytes: counts (one daq_counts), ped (C int32), islands (capacity =
+ * daq_max_islands(N, pre, post) records), out (C rows of out_stride = N
+ * rounded up to a multiple of 8), and for DAQ_SUBMIT_HOST_RAW the raw rows
+ * (C x row_stride int16).
+ *
+ * daq_submit_fill, daq_poll, daq_release and daq_server_get_stats may be
+ * called from any host thread. */
+typedef struct daq_server daq_server;
+
+#define DAQ_SUBMIT_HOST_RAW 1 /* fill->raw is host memory (pinned for speed):
+                                 the server copies it into the fill's slot on
+                                 the worker's stream before the launch; the
+                                 host buffer may be reused once the fill's
+                                 completion is returned by daq_poll          */
+
+/* One finished fill, as returned by daq_poll. */
+typedef struct daq_completion {
+    uint64_t tag;        /* as given to daq_submit_fill                       */
+    uint64_t ticket;     /* as returned by daq_submit_fill                    */
+    daq_counts counts;   /* host copy of the fill's device counts            */
+    daq_fill_out out;    /* device pointers into the arena, valid until
+                            daq_release(ticket)                               */
+    const int16_t *raw;  /* device raw rows the fill was chopped from        */
+    int32_t status;      /* DAQ_OK, or the error of the batch launch          */
+    int32_t batch_fills; /* fills in the launch that carried this one        */
+    int64_t t_submit_ns; /* steady clock (ns): submit accepted                */
+    int64_t t_launch_ns; /* its batch handed to the device                    */
+    int64_t t_ready_ns;  /* results complete in device memory                 */
+} daq_completion;
+
+typedef struct daq_server_stats {
+    uint64_t submitted;   /* fills admitted                                  */
+    uint64_t rejected;    /* submits refused with DAQ_EAGAIN                 */
+    uint64_t completed;   /* fills whose results are ready                   */
+    uint64_t released;    /* slots returned by daq_release                   */
+    uint64_t batches;     /* launches                                        */
+    uint64_t arena_bytes; /* usable budget                                   */
+    uint64_t arena_in_use;
+    uint64_t arena_peak;
+    int32_t pending;      /* admitted, not yet launched                      */
+    int32_t running;      /* launched, not yet complete                      */
+} daq_server_stats;
+
+/* Bytes of arena one fill takes (its slot, above). EINVAL as
+ * daq_find_islands for a bad fill, or a NULL `bytes`; host-only. */
+int daq_server_slot_bytes(const daq_fill *fill, int32_t flags, uint64_t *bytes);
+
+/* Starts a server on ctx's device with ctx's current schedule (ctx is not
+ * used afterwards). d_arena: caller-owned device memory of arena_bytes,
+ * 256-byte aligned, that the server sub-allocates (never frees).
+ * n_streams: 1..8 workers; max_batch: 1..256 fills per launch. */
+int daq_server_create(daq_server **out, daq_ctx *ctx, void *d_arena,
+                      size_t arena_bytes, int32_t n_streams, int32_t max_batch);
+
+/* Admits one fill: reserves its slot and queues it; *ticket (not NULL)
+ * receives its number (increasing from 1). fill->raw must stay valid and
+ * unchanged until the fill's completion is returned. DAQ_EAGAIN when the
+ * slot does not fit in the free arena now (retry after releasing),
+ * DAQ_ERANGE when it can never fit, EINVAL/EALIGN as daq_find_islands
+ * (a host raw needs no alignment). */
+int daq_submit_fill(daq_server *srv, const daq_fill *fill, int32_t flags,
+                    uint64_t tag, uint64_t *ticket);
+
+/* Copies up to max finished fills (oldest completion first) to out and
+ * returns how many; waits up to timeout_us for the first one (0 = do not
+ * wait). Negative on error. */
+int daq_poll(daq_server *srv, daq_completion *out, int32_t max,
+             int32_t timeout_us);
+
+/* Frees the slot of a finished fill. DAQ_EAGAIN while the fill is queued or
+ * running, EINVAL for an unknown or already released ticket. */
+int daq_release(daq_server *srv, uint64_t ticket);
+
+int daq_server_get_stats(daq_server *srv, daq_server_stats *st);
+
+/* Stops the workers after their current launches (queued fills are dropped)
+ * and frees the server's host and scratch memory. NULL ok. */
+void daq_server_destroy(daq_server *srv);
 
 #ifdef __cplusplus
 }

@@ -36,6 +36,9 @@ DAQ_MAX_WINDOW = 32768
 DAQ_VARIANT_RELOAD = 0
 DAQ_VARIANT_REGISTERS = 1
 DAQ_VARIANT_LDS = 2
+DAQ_VARIANT_RELOAD18 = 3
+DAQ_VARIANT_RELOAD27 = 4
+DAQ_VARIANT_SPLIT = 5
 
 
 class daq_fill(ctypes.Structure):
@@ -54,6 +57,29 @@ class daq_fill_out(ctypes.Structure):
 class daq_schedule(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class daq_counts(ctypes.Structure):
+    _fields_ = [("n_islands", ctypes.c_int64), ("total_len", ctypes.c_int64),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class daq_completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("ticket", ctypes.c_uint64), ("counts", daq_counts),
+                ("out", daq_fill_out), ("raw", ctypes.c_void_p), ("status", ctypes.c_int32),
+                ("batch_fills", ctypes.c_int32), ("t_submit_ns", ctypes.c_int64),
+                ("t_launch_ns", ctypes.c_int64), ("t_ready_ns", ctypes.c_int64)]
+
+
+class daq_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("released", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
+                ("arena_in_use", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64),
+                ("pending", ctypes.c_int32), ("running", ctypes.c_int32)]
+
+
+DAQ_SUBMIT_HOST_RAW = 1
 
 
 class DaqError(RuntimeError):
@@ -104,6 +130,16 @@ def load_library():
         "daq_ctx_kernel_times": ([vp, ctypes.POINTER(ctypes.c_float), i32], ctypes.c_int),
         "daq_autotune": ([vp, ctypes.POINTER(daq_fill), ctypes.POINTER(daq_fill_out), i32, vp,
                           ctypes.c_char_p, ctypes.POINTER(daq_schedule)], ctypes.c_int),
+        "daq_ctx_get_device": ([vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "daq_server_slot_bytes": ([ctypes.POINTER(daq_fill), i32, ctypes.POINTER(ctypes.c_uint64)],
+                                  ctypes.c_int),
+        "daq_server_create": ([ctypes.POINTER(vp), vp, vp, ctypes.c_size_t, i32, i32], ctypes.c_int),
+        "daq_submit_fill": ([vp, ctypes.POINTER(daq_fill), i32, ctypes.c_uint64,
+                             ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "daq_poll": ([vp, ctypes.POINTER(daq_completion), i32, i32], ctypes.c_int),
+        "daq_release": ([vp, ctypes.c_uint64], ctypes.c_int),
+        "daq_server_get_stats": ([vp, ctypes.POINTER(daq_server_stats)], ctypes.c_int),
+        "daq_server_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -271,7 +307,7 @@ class Context:
         return best
 
     # -- settings ----------------------------------------------------------
-    def set_schedule(self, threads: int = 256, wgs_per_cu: int = 2, variant: int = 2):
+    def set_schedule(self, threads: int = 256, wgs_per_cu: int = 16, variant: int = 5):
         s = daq_schedule(threads, wgs_per_cu, variant, 0)
         _check(self._lib.daq_ctx_set_schedule(self.handle, ctypes.byref(s)), "daq_ctx_set_schedule")
 
@@ -305,3 +341,141 @@ def version() -> str:
 
 __all__: List[str] = ["Context", "Fill", "FillOut", "alloc_out", "daq_max_islands", "load_library",
                       "version", "DaqError", "padded", "daq_schedule"]
+
+
+def slot_bytes(fill: Fill, host_raw: bool = False) -> int:
+    """Arena bytes one fill's slot takes in a Server (daq_server_slot_bytes)."""
+    lib = load_library()
+    b = ctypes.c_uint64(0)
+    f = fill.c_struct()
+    _check(lib.daq_server_slot_bytes(ctypes.byref(f), DAQ_SUBMIT_HOST_RAW if host_raw else 0,
+                                     ctypes.byref(b)), "daq_server_slot_bytes")
+    return int(b.value)
+
+
+@dataclasses.dataclass
+class Completion:
+    """A finished fill (daq_completion) and where its results sit in the arena."""
+    tag: int
+    ticket: int
+    n_islands: int
+    total_len: int
+    status: int
+    error: int
+    batch_fills: int
+    t_submit_ns: int
+    t_launch_ns: int
+    t_ready_ns: int
+    islands_ptr: int
+    capacity: int
+    ped_ptr: int
+    out_ptr: int
+    out_stride: int
+
+    @property
+    def latency_ms(self) -> float:
+        return (self.t_ready_ns - self.t_submit_ns) * 1e-6
+
+
+class Server:
+    """daq_server: admission by HBM budget and continuous batching.
+
+    ``arena`` is a device ``torch.uint8`` tensor (the budget); it must outlive
+    the server. ``Context`` supplies the device and the kernel schedule.
+    """
+
+    def __init__(self, ctx: Context, arena, n_streams: int = 2, max_batch: int = 16):
+        self._lib = load_library()
+        self.arena = arena
+        self._base = int(arena.data_ptr())
+        h = ctypes.c_void_p()
+        _check(self._lib.daq_server_create(ctypes.byref(h), ctx.handle, self._base, int(arena.numel()),
+                                           int(n_streams), int(max_batch)), "daq_server_create")
+        self._h = h
+        self._buf = (daq_completion * 256)()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.daq_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, fill: Fill, tag: int = 0, host_raw=None) -> Optional[int]:
+        """Admits a fill; returns its ticket, or None when the budget is full now.
+
+        With ``host_raw`` (a CPU int16 [C, row_stride] tensor, pinned for
+        speed) the samples are copied into the arena by the server and
+        ``fill.raw`` is only used for its shape."""
+        f = fill.c_struct()
+        flags = 0
+        if host_raw is not None:
+            if host_raw.dim() != 2 or host_raw.stride(1) != 1 or host_raw.is_cuda:
+                raise ValueError("host_raw must be a 2-D CPU tensor with contiguous rows")
+            f.raw = host_raw.data_ptr()
+            f.row_stride = int(host_raw.stride(0))
+            f.n_channels = int(host_raw.shape[0])
+            flags = DAQ_SUBMIT_HOST_RAW
+        t = ctypes.c_uint64(0)
+        rc = self._lib.daq_submit_fill(self._h, ctypes.byref(f), flags, int(tag), ctypes.byref(t))
+        if rc == DAQ_EAGAIN:
+            return None
+        _check(rc, "daq_submit_fill")
+        return int(t.value)
+
+    def poll(self, max_n: int = 256, timeout_us: int = 0) -> List[Completion]:
+        n = self._lib.daq_poll(self._h, self._buf, min(int(max_n), 256), int(timeout_us))
+        if n < 0:
+            _check(n, "daq_poll")
+        res = []
+        for i in range(n):
+            c = self._buf[i]
+            res.append(Completion(int(c.tag), int(c.ticket), int(c.counts.n_islands),
+                                  int(c.counts.total_len), int(c.counts.status) & 0xFFFFFFFF,
+                                  int(c.status), int(c.batch_fills), int(c.t_submit_ns),
+                                  int(c.t_launch_ns), int(c.t_ready_ns), int(c.out.islands or 0),
+                                  int(c.out.capacity), int(c.out.ped or 0), int(c.out.out or 0),
+                                  int(c.out.out_stride)))
+        return res
+
+    def release(self, ticket: int):
+        _check(self._lib.daq_release(self._h, int(ticket)), "daq_release")
+
+    def try_release(self, ticket: int) -> int:
+        return int(self._lib.daq_release(self._h, int(ticket)))
+
+    def stats(self) -> daq_server_stats:
+        st = daq_server_stats()
+        _check(self._lib.daq_server_get_stats(self._h, ctypes.byref(st)), "daq_server_get_stats")
+        return st
+
+    # the C names
+    daq_submit_fill = submit
+    daq_poll = poll
+    daq_release = release
+
+    def results(self, c: Completion, n_channels: int):
+        """Host copies of a completion's results: (islands[n], ped, out[:, :total_len])."""
+        import torch
+        a = self.arena
+
+        def view(ptr, nbytes, dtype):
+            off = ptr - self._base
+            return a[off:off + nbytes].view(dtype)
+
+        n = min(c.n_islands, c.capacity)
+        isl = view(c.islands_ptr, n * 24, torch.int64).reshape(n, 3).cpu().numpy()
+        ped = view(c.ped_ptr, 4 * n_channels, torch.int32).cpu().numpy()
+        rows = view(c.out_ptr, 2 * n_channels * c.out_stride, torch.int16).reshape(n_channels, c.out_stride)
+        out = rows[:, :min(c.total_len, c.out_stride)].cpu().numpy()
+        return isl, ped, out

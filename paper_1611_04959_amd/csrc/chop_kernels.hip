@@ -82,16 +82,24 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // Descriptor of fill f: from the device table, or the single fill passed in
 // the kernel arguments. Returned by value so that no pointer to the kernel
-// arguments is formed.
+// arguments is formed. f must be the same in every lane of the wave; the
+// descriptor is then made wave-uniform (scalar registers).
 __device__ __forceinline__ FillDev fill_at(const KArgs &a, int f) {
     if (a.table) {
+        f = __builtin_amdgcn_readfirstlane(f);
         union {
             FillDev d;
             u32x4 v[sizeof(FillDev) / 16];
         } u;
         const DAQ_GLOBAL u32x4 *src = (const DAQ_GLOBAL u32x4 *)(a.table + f);
 #pragma unroll
-        for (int i = 0; i < (int)(sizeof(FillDev) / 16); i++) u.v[i] = src[i];
+        for (int i = 0; i < (int)(sizeof(FillDev) / 16); i++) {
+            const u32x4 w = src[i];
+            u.v[i] = u32x4{(unsigned)__builtin_amdgcn_readfirstlane((int)w.x),
+                           (unsigned)__builtin_amdgcn_readfirstlane((int)w.y),
+                           (unsigned)__builtin_amdgcn_readfirstlane((int)w.z),
+                           (unsigned)__builtin_amdgcn_readfirstlane((int)w.w)};
+        }
         return u.d;
     }
     return a.one;
@@ -1049,85 +1057,158 @@ __global__ void __launch_bounds__(256) k_prefix_pass(KArgs a) {
     }
 }
 
-// Sample e (0..7) of an 8-sample vector.
-__device__ __forceinline__ int16_t sample_of(const uint4 v, int e) {
-    const uint32_t w = (e < 2) ? v.x : (e < 4) ? v.y : (e < 6) ? v.z : v.w;
-    return (int16_t)((e & 1) ? (w >> 16) : (w & 0xFFFFu));
+// Last run whose packed start is <= q (runs with equal starts: the later,
+// non-empty one).
+__device__ __forceinline__ int run_at(const int32_t *seg_dst, int nrun, int q) {
+    int lo = 0, hi = nrun - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg_dst[mid] <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Elements [0, split) of a, [split, 8) of b.
+__device__ __forceinline__ uint4 blend8(const uint4 a, const uint4 b, int split) {
+    auto m = [split](int k) -> uint32_t {
+        return (2 * k + 1 < split) ? 0xFFFFFFFFu : (2 * k < split ? 0x0000FFFFu : 0u);
+    };
+    const uint32_t m0 = m(0), m1 = m(1), m2 = m(2), m3 = m(3);
+    return make_uint4((a.x & m0) | (b.x & ~m0), (a.y & m1) | (b.y & ~m1), (a.z & m2) | (b.z & ~m2),
+                      (a.w & m3) | (b.w & ~m3));
 }
 
 // Chopped islands of one tile copied from the raw rows (emit pass). Run r
-// moves tile samples [src_r, src_r + len_r) to packed positions [dst_r,
-// dst_r + len_r) (tile-relative); kpref[r] counts the 16-byte destination
-// lines reserved for the runs before r. A work item is (channel, run, line):
-// its source is contiguous, read as two aligned 16-byte words and realigned;
-// a line wholly inside the run is one 16-byte store, the run's edge lines
-// store their own samples only. Loads of U items are issued before stores.
-template <int NT>
-__device__ __forceinline__ void emit_runs(const int32_t *seg_src, const int32_t *seg_dst, const int32_t *kpref,
-                                          int nrun, int tile_m, const int16_t *raw, int64_t stride, int64_t t0,
-                                          int16_t *out, int64_t ostride, int C, int64_t m0) {
-    constexpr int U = 4;
-    const int ktot = kpref[nrun];
-    const int items = C * ktot;
-    for (int i0 = threadIdx.x; i0 < items; i0 += NT * U) {
-        uint4 A[U], B[U];
-        int cs[U], e0s[U], e1s[U], sh[U];
-        int64_t first[U];
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int i = i0 + u * NT;
-            A[u] = make_uint4(0, 0, 0, 0);
-            B[u] = make_uint4(0, 0, 0, 0);
-            e0s[u] = 0;
-            e1s[u] = 0;  // empty
-            cs[u] = 0;
-            sh[u] = 0;
-            first[u] = 0;
-            if (i >= items) continue;
-            const int c = i / ktot;
-            const int rem = i - c * ktot;
-            int lo = 0, hi = nrun - 1;  // last run with kpref[r] <= rem
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (kpref[mid] <= rem) lo = mid;
-                else hi = mid - 1;
-            }
-            const int r = lo;
-            const int k = rem - kpref[r];
-            const int len = ((r + 1 < nrun) ? seg_dst[r + 1] : tile_m) - seg_dst[r];
-            const int16_t *orow_c = out + (int64_t)c * ostride;
-            const int64_t D = m0 + seg_dst[r];
-            const int64_t f0 = D - line_phase(orow_c, D) + 8 * k;  // packed position of the line's sample 0
-            int64_t lo_p = f0 > D ? f0 : D;
-            int64_t hi_p = f0 + 8;
-            if (hi_p > D + len) hi_p = D + len;
-            if (hi_p > ostride) hi_p = ostride;
-            if (lo_p >= hi_p) continue;
-            const int e0 = (int)(lo_p - f0), e1 = (int)(hi_p - f0);
-            const int sv = seg_src[r] + (int)(lo_p - D);  // tile-relative source of sample e0
-            const int16_t *row = raw + (int64_t)c * stride + t0;  // t0 is a multiple of 8
-            const int a0 = sv & ~7;
-            A[u] = load16(row + a0);
-            if ((sv & 7) + (e1 - e0) > 8) B[u] = load16(row + a0 + 8);
-            cs[u] = c;
-            e0s[u] = e0;
-            e1s[u] = e1;
-            sh[u] = sv & 7;
-            first[u] = f0;
+// moves tile samples [src_r, ...) to packed positions [dst_r, dst_{r+1})
+// (tile-relative; the last run ends at tile_m). A work item is one 16-byte
+// line of one channel's packed row. A line inside one run, or across the
+// boundary of two runs, is read as aligned 16-byte words, realigned (and
+// blended) and written with one 16-byte store; lines at the tile's ends
+// (shared with the neighbouring tiles) or across three or more runs go
+// sample by sample. When every row has the same line phase (out_stride a
+// multiple of 8), line_run[j] holds the run of line j's first sample.
+template <int NT, int U>
+__device__ __forceinline__ void emit_lines(const int32_t *seg_src, const int32_t *seg_dst, const int32_t *line_run,
+                                           bool uniform, int ph_all, int lines, int nrun, int tile_m,
+                                           const int16_t *raw, int64_t stride, int64_t t0, int16_t *out,
+                                           int64_t ostride, int C, int64_t m0) {
+    const int items = C * lines;
+    const int dq = NT / lines, dr = NT - dq * lines;
+    int c = (int)threadIdx.x / lines, j = (int)threadIdx.x - c * lines;
+    auto step = [&]() {
+        j += dr;
+        c += dq;
+        if (j >= lines) {
+            j -= lines;
+            c++;
         }
+    };
+    // the line's tile-relative packed range [lo, hi) and its position q0
+    auto span = [&](int cc, int jj, int &q0, int &lo, int &hi) {
+        const int ph = uniform ? ph_all : line_phase(out + (int64_t)cc * ostride, m0);
+        q0 = 8 * jj - ph;
+        lo = q0 > 0 ? q0 : 0;
+        hi = q0 + 8 < tile_m ? q0 + 8 : tile_m;
+        if (m0 + hi > ostride) hi = (int)(ostride - m0);
+    };
+    for (int i0 = threadIdx.x; i0 < items; i0 += NT * U) {
+        const int c_first = c, j_first = j;
+        uint4 A0[U], B0[U], A1[U], B1[U];
+        int meta[U];  // kind (0 none, 1 one run, 2 two runs, 3 sample by sample) | split << 2 | shifts
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            if (e1s[u] <= e0s[u]) continue;
-            int16_t *orow = out + (int64_t)cs[u] * ostride + first[u];
-            const uint4 v = realign8(A[u], B[u], sh[u]);
-            if (e0s[u] == 0 && e1s[u] == 8) {
-                store16(orow, v);
-            } else {
-                for (int e = e0s[u]; e < e1s[u]; e++) *gbl(orow + e) = sample_of(v, e - e0s[u]);
+            meta[u] = 0;
+            A0[u] = B0[u] = A1[u] = B1[u] = make_uint4(0, 0, 0, 0);
+            if (i0 + u * NT < items) {
+                int q0, lo, hi;
+                span(c, j, q0, lo, hi);
+                if (lo < hi) {
+                    // the samples go to packed positions lo .. hi - 1; v[e] below is position lo + e
+                    const int r0 = uniform ? line_run[j] : run_at(seg_dst, nrun, lo);
+                    const int end0 = (r0 + 1 < nrun) ? seg_dst[r0 + 1] : tile_m;
+                    const int16_t *row = raw + (int64_t)c * stride + t0;  // t0 is a multiple of 8
+                    const int s0 = seg_src[r0] + lo - seg_dst[r0];
+                    meta[u] = 3;
+                    if (end0 >= hi) {
+                        meta[u] = 1 | ((s0 & 7) << 6);
+                        A0[u] = load16(row + (s0 & ~7));
+                        if ((s0 & 7) + (hi - lo) > 8) B0[u] = load16(row + (s0 & ~7) + 8);
+                    } else {
+                        const int end1 = (r0 + 2 < nrun) ? seg_dst[r0 + 2] : tile_m;
+                        if (end1 >= hi) {
+                            // runs are separated by at least one sample: s1 >= s0 + 1 >= 1
+                            const int sp = end0 - lo;
+                            const int s1 = seg_src[r0 + 1] - sp;
+                            meta[u] = 2 | (sp << 2) | ((s0 & 7) << 6) | ((s1 & 7) << 9);
+                            A0[u] = load16(row + (s0 & ~7));
+                            if ((s0 & 7) + sp > 8) B0[u] = load16(row + (s0 & ~7) + 8);
+                            A1[u] = load16(row + (s1 & ~7));
+                            if ((s1 & 7) + (hi - lo) > 8) B1[u] = load16(row + (s1 & ~7) + 8);
+                        }
+                    }
+                }
             }
+            step();
+        }
+        c = c_first;
+        j = j_first;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int kind = meta[u] & 3;
+            if (kind != 0) {
+                int q0, lo, hi;
+                span(c, j, q0, lo, hi);
+                int16_t *orow = out + (int64_t)c * ostride + m0;
+                if (kind == 3) {
+                    const int16_t *row = raw + (int64_t)c * stride + t0;
+                    int r = run_at(seg_dst, nrun, lo);
+                    for (int q = lo; q < hi; q++) {
+                        while (r + 1 < nrun && seg_dst[r + 1] <= q) r++;
+                        *gbl(orow + q) = *gbl(row + seg_src[r] + (q - seg_dst[r]));
+                    }
+                } else {
+                    uint4 v = realign8(A0[u], B0[u], (meta[u] >> 6) & 7);
+                    if (kind == 2) v = blend8(v, realign8(A1[u], B1[u], (meta[u] >> 9) & 7), (meta[u] >> 2) & 15);
+                    if (lo == q0 && hi == q0 + 8) {
+                        store16(orow + q0, v);
+                    } else {
+                        // a line shared with a neighbouring tile: this tile's samples only
+                        uint32_t w[4] = {v.x, v.y, v.z, v.w};
+                        for (int e = 0; e < hi - lo; e++)
+                            *gbl(orow + lo + e) = (int16_t)((w[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu);
+                    }
+                }
+            }
+            step();
         }
     }
 }
+
+// Tiles of one work-group. Work-groups are handed to the 8 XCDs in turn;
+// giving each XCD one contiguous chunk of tiles keeps neighbouring tiles,
+// which share the 16-byte lines at the ends of their packed ranges, in the
+// same L2.
+struct TileRange {
+    int64_t first, end, stride;
+};
+__device__ __forceinline__ TileRange xcd_tiles(int64_t total) {
+    const int G = (int)gridDim.x;
+    const int X = G < 8 ? G : 8;
+    const int x = (int)blockIdx.x % X;
+    const int64_t per = (total + X - 1) / X;
+    const int64_t first = x * per + (int64_t)blockIdx.x / X;
+    const int64_t end = (x + 1) * per < total ? (x + 1) * per : total;
+    return TileRange{first, end, (G - x + X - 1) / X};
+}
+
+#ifndef DAQ_EMIT_XCD
+#define DAQ_EMIT_XCD 1
+#endif
+
+#ifndef DAQ_EMIT_U
+#define DAQ_EMIT_U 4  // lines per thread with loads in flight
+#endif
 
 // Emit pass, one tile: island edges from the mask bits, records, packed
 // samples. Thread j takes the tile's owned samples t0 + 8j .. t0 + 8j + 7.
@@ -1135,7 +1216,7 @@ __device__ __forceinline__ void emit_runs(const int32_t *seg_src, const int32_t 
 // may be empty); the others start at the tile's rising edges.
 template <int NT>
 __device__ __forceinline__ void emit_pass_tile(const KArgs &a, const FillDev &fd, int64_t tile, int32_t *seg_src,
-                                               int32_t *seg_dst, int32_t *kpref, uint32_t *s_wsum) {
+                                               int32_t *seg_dst, int32_t *line_run, uint32_t *s_wsum) {
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -1191,34 +1272,29 @@ __device__ __forceinline__ void emit_pass_tile(const KArgs &a, const FillDev &fd
         }
     }
     lds_barrier();
-    // lines reserved per run: enough for any phase of the destination line
+    // packed lines of this tile; with one line phase for every row, the run
+    // of each line's first sample
     const int nrun = r.tile_i + 1;
-    if (wid == 0) {
-        int carry = 0;
-        for (int r0 = 0; r0 < nrun; r0 += 64) {
-            const int rr = r0 + lane;
-            int kcount = 0;
-            if (rr < nrun) {
-                const int len = ((rr + 1 < nrun) ? seg_dst[rr + 1] : r.tile_m) - seg_dst[rr];
-                kcount = len > 0 ? (len + 14) >> 3 : 0;
-            }
-            const uint32_t incl = wave_incl_scan_u32((uint32_t)kcount, lane);
-            if (rr < nrun) kpref[rr] = carry + (int)incl - kcount;
-            carry += (int)__shfl(incl, 63, 64);
+    const bool uniform = (fd.out_stride & 7) == 0;
+    const int ph_all = line_phase(fd.out, r.m_before);
+    const int lines = uniform ? (ph_all + r.tile_m + 7) >> 3 : (r.tile_m + 14) >> 3;
+    if (uniform) {
+        for (int jj = tid; jj < lines; jj += NT) {
+            const int q = 8 * jj - ph_all;
+            line_run[jj] = run_at(seg_dst, nrun, q > 0 ? q : 0);
         }
-        if (lane == 0) kpref[nrun] = carry;
+        lds_barrier();
     }
-    lds_barrier();
-    emit_runs<NT>(seg_src, seg_dst, kpref, nrun, r.tile_m, fd.raw, fd.stride, t0, fd.out, fd.out_stride, fd.C,
-                  r.m_before);
+    emit_lines<NT, DAQ_EMIT_U>(seg_src, seg_dst, line_run, uniform, ph_all, lines, nrun, r.tile_m, fd.raw, fd.stride, t0,
+                   fd.out, fd.out_stride, fd.C, r.m_before);
 }
 
 template <int NT>
 __global__ void __launch_bounds__(NT) k_emit_pass(KArgs a) {
-    constexpr int kMaxRuns = NT * kVec / 2 + 3;  // the open run, the rises, a sentinel
+    constexpr int kMaxRuns = NT * kVec / 2 + 2;  // the open run and the rises
     __shared__ int32_t s_src[kMaxRuns];
     __shared__ int32_t s_dst[kMaxRuns];
-    __shared__ int32_t s_kpref[kMaxRuns];
+    __shared__ int32_t s_line_run[NT + 2];
     __shared__ uint32_t s_wsum[NT / 64];
     __shared__ int64_t s_base[kLdsFills];
     const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
@@ -1229,7 +1305,8 @@ __global__ void __launch_bounds__(NT) k_emit_pass(KArgs a) {
     lds_barrier();
     FillDev fd{};
     int cur = -1;
-    for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const TileRange tr = DAQ_EMIT_XCD ? xcd_tiles(total) : TileRange{blockIdx.x, total, gridDim.x};
+    for (int64_t tile = tr.first; tile < tr.end; tile += tr.stride) {
         if (cur < 0 || tile < fd.tile_base || tile >= fd.tile_base + fd.n_tiles) {
             int lo = 0, hi = nf - 1;
             while (lo < hi) {
@@ -1240,7 +1317,7 @@ __global__ void __launch_bounds__(NT) k_emit_pass(KArgs a) {
             fd = fill_at(a, lo);
             cur = lo;
         }
-        emit_pass_tile<NT>(a, fd, tile, s_src, s_dst, s_kpref, s_wsum);
+        emit_pass_tile<NT>(a, fd, tile, s_src, s_dst, s_line_run, s_wsum);
         lds_barrier();
     }
 }
@@ -1377,15 +1454,22 @@ hipError_t launch_chop(const KArgs &a, int threads, int variant, int grid, hipSt
     return hipGetLastError();
 }
 
+#ifndef DAQ_EMIT_GRID_MULT
+#define DAQ_EMIT_GRID_MULT 1
+#endif
+
 hipError_t launch_split(const KArgs &a, int threads, int grid, int prefix_blocks, hipStream_t s) {
+    int64_t eg = (int64_t)grid * DAQ_EMIT_GRID_MULT;
+    if (!a.hdr && eg > a.total_tiles) eg = a.total_tiles > grid ? a.total_tiles : grid;
+    const int egrid = (int)(eg < (1 << 30) ? eg : (1 << 30));
     if (threads == 256) {
         hipLaunchKernelGGL((k_scan_pass<256, 6>), dim3(grid), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_prefix_pass, dim3(prefix_blocks), dim3(256), 0, s, a);
-        hipLaunchKernelGGL((k_emit_pass<256>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_emit_pass<256>), dim3(egrid), dim3(256), 0, s, a);
     } else if (threads == 512) {
         hipLaunchKernelGGL((k_scan_pass<512, 6>), dim3(grid), dim3(512), 0, s, a);
         hipLaunchKernelGGL(k_prefix_pass, dim3(prefix_blocks), dim3(256), 0, s, a);
-        hipLaunchKernelGGL((k_emit_pass<512>), dim3(grid), dim3(512), 0, s, a);
+        hipLaunchKernelGGL((k_emit_pass<512>), dim3(egrid), dim3(512), 0, s, a);
     } else {
         return hipErrorInvalidValue;
     }

@@ -83,7 +83,7 @@ struct daq_ctx {
     int n_cu = 0;
     std::string name;
     std::vector<Scratch *> scratch;
-    daq_schedule sched{daqk::kStreamThreads, 2, daqk::kVariantStream, 0};
+    daq_schedule sched{256, 16, daqk::kVariantSplit, 0};
     bool graphs = true;
     bool timing = false;
     // event pairs bracketing fused-kernel launches while timing is on;
@@ -580,6 +580,12 @@ void daq_ctx_destroy(daq_ctx *ctx) {
     delete ctx;
 }
 
+int daq_ctx_get_device(daq_ctx *ctx, int *device) {
+    if (!ctx || !device) return DAQ_EINVAL;
+    *device = ctx->device;
+    return DAQ_OK;
+}
+
 int daq_find_islands(daq_ctx *ctx, const daq_fill *fill, daq_island *d_islands, int64_t capacity,
                      daq_counts *d_counts, int32_t *d_ped, void *stream) {
     daq_fill_out o{};
@@ -703,10 +709,9 @@ int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, 
     const bool calo = all_calorimeters(fills, n);
     const int V0 = daqk::kVariantReload, V1 = daqk::kVariantResident, V2 = daqk::kVariantStream;
     const int V3 = daqk::kVariantReload18, V4 = daqk::kVariantReload27, V5 = daqk::kVariantSplit;
-    const daq_schedule menu[] = {{256, 8, V5, 0}, {256, 4, V5, 0}, {512, 2, V5, 0}, {512, 4, V5, 0},
-                                 {256, 4, V0, 0}, {256, 2, V2, 0}, {256, 8, V0, 0}, {512, 2, V0, 0},
-                                 {256, 4, V3, 0}, {256, 3, V3, 0}, {512, 2, V3, 0}, {256, 3, V4, 0},
-                                 {256, 2, V4, 0}, {128, 8, V0, 0}, {256, 1, V1, 0}, {128, 2, V1, 0}};
+    const daq_schedule menu[] = {{256, 16, V5, 0}, {256, 8, V5, 0}, {512, 4, V5, 0}, {256, 4, V0, 0},
+                                 {256, 8, V0, 0},  {512, 2, V0, 0}, {256, 2, V2, 0}, {256, 4, V3, 0},
+                                 {256, 3, V4, 0},  {128, 8, V0, 0}, {256, 1, V1, 0}};
     for (const daq_schedule &m : menu)
         if ((m.variant != V1 && m.variant != V2) || calo) cand.push_back(m);
     const daq_schedule saved = ctx->sched;

@@ -1,0 +1,122 @@
+"""HBM traffic of the chop pass from rocprofv3 counters.
+
+Two counter runs of the benchmark (``FETCH_SIZE``, then ``WRITE_SIZE``, in
+KiB per dispatch) give the bytes each kernel moved between L2 and memory.
+The counters are scaled by what they read for a plain copy of known size
+(``python -m paper_1611_04959_amd.traffic copy``, torch's copy kernel), so
+the reported figures are bytes.
+
+  python -m paper_1611_04959_amd.traffic copy [MiB]
+  python -m paper_1611_04959_amd.traffic summarize FETCH_DIR WRITE_DIR \
+         COPY_FETCH_DIR COPY_WRITE_DIR OUT_JSON [fills]
+
+``summarize`` writes OUT_JSON (read by bench.py) and prints a text summary.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SRC = os.path.join(HERE, "csrc", "chop_kernels.hip")
+PASS_KERNELS = ("k_prepare", "k_scan_pass", "k_prefix_pass", "k_emit_pass", "k_chop")
+
+
+def kernel_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def copy_run(mib: int = 1024, reps: int = 3):
+    import torch
+    n = mib * (1 << 20) // 2
+    src = torch.ones(n, dtype=torch.int16, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print("copied %d x %d MiB" % (reps, mib), flush=True)
+
+
+def _rows(d):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError("no counter_collection.csv under " + d)
+    for f in files:
+        with open(f, newline="") as fh:
+            yield from csv.DictReader(fh)
+
+
+def per_kernel(d, counter):
+    """kernel short name -> list of per-dispatch counter values (KiB)."""
+    acc = defaultdict(lambda: defaultdict(float))  # kernel -> dispatch -> value
+    for r in _rows(d):
+        if r.get("Counter_Name") != counter:
+            continue
+        name = r.get("Kernel_Name", "")
+        acc[name][r.get("Dispatch_Id")] += float(r.get("Counter_Value", 0) or 0)
+    return {k: list(v.values()) for k, v in acc.items()}
+
+
+def short(name):
+    for k in PASS_KERNELS:
+        if k in name:
+            return k
+    return None
+
+
+def copy_factor(d, counter, mib):
+    vals = [v for k, vs in per_kernel(d, counter).items() if "copy" in k.lower() or "elementwise" in k
+            for v in vs]
+    vals = [v for v in vals if v > mib * 1024 * 0.5]  # the big copies only
+    if not vals:
+        raise RuntimeError("copy kernel not found in " + d)
+    kib = sum(vals) / len(vals)
+    return mib * (1 << 20) / (kib * 1024), kib
+
+
+def summarize(fetch_dir, write_dir, cf_dir, cw_dir, out_json, fills=16, mib=1024):
+    f_fac, f_kib = copy_factor(cf_dir, "FETCH_SIZE", mib)
+    w_fac, w_kib = copy_factor(cw_dir, "WRITE_SIZE", mib)
+    fetch = per_kernel(fetch_dir, "FETCH_SIZE")
+    write = per_kernel(write_dir, "WRITE_SIZE")
+    kern = {}
+    for name, vs in fetch.items():
+        k = short(name)
+        if k is None or not vs:
+            continue
+        ws = write.get(name, [0.0])
+        # every dispatch of these kernels is one 16-fill launch: take the median
+        fk, wk = sorted(vs)[len(vs) // 2], sorted(ws)[len(ws) // 2]
+        kern[k] = {"fetch_bytes": fk * 1024 * f_fac, "write_bytes": wk * 1024 * w_fac,
+                   "dispatches": len(vs), "fetch_kib_raw": fk, "write_kib_raw": wk}
+    # the timed launch: every kernel but k_prepare (which runs before it)
+    total = sum(v["fetch_bytes"] + v["write_bytes"] for k, v in kern.items() if k != "k_prepare")
+    res = {"kernel_sha": kernel_sha(), "fills": fills, "bytes_per_launch": round(total),
+           "copy_factor_fetch": f_fac, "copy_factor_write": w_fac,
+           "copy_fetch_kib": f_kib, "copy_write_kib": w_kib, "copy_mib": mib, "kernels": kern}
+    with open(out_json, "w") as fh:
+        json.dump(res, fh, indent=1)
+    print("copy calibration: %d MiB copy reads FETCH_SIZE %.0f KiB (x%.3f), WRITE_SIZE %.0f KiB (x%.3f)"
+          % (mib, f_kib, f_fac, w_kib, w_fac))
+    for k, v in sorted(kern.items()):
+        print("%-14s fetch %10.1f MB  write %9.1f MB  (raw %.0f / %.0f KiB, %d dispatches)"
+              % (k, v["fetch_bytes"] / 1e6, v["write_bytes"] / 1e6, v["fetch_kib_raw"], v["write_kib_raw"],
+                 v["dispatches"]))
+    print("per timed launch (without k_prepare): %.1f MB" % (total / 1e6))
+    return res
+
+
+if __name__ == "__main__":
+    if len(sys.argv) >= 2 and sys.argv[1] == "copy":
+        copy_run(int(sys.argv[2]) if len(sys.argv) > 2 else 1024)
+    elif len(sys.argv) >= 7 and sys.argv[1] == "summarize":
+        summarize(*sys.argv[2:7], fills=int(sys.argv[7]) if len(sys.argv) > 7 else 16)
+    else:
+        print(__doc__)
+        sys.exit(2)

@@ -72,3 +72,48 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(daq.daq_fill) == 48
     assert ctypes.sizeof(daq.daq_fill_out) == 48
     assert ctypes.sizeof(daq.daq_schedule) == 16
+
+
+def test_server_slot_bytes_layout():
+    lib = daq.load_library()
+    up = lambda n: (n + 255) // 256 * 256
+    b = ctypes.c_uint64(0)
+    for C, N, stride, pre, post, flags in ((54, 560_000, 560_000, 8, 24, 0), (54, 560_000, 560_000, 8, 24, 1),
+                                           (3, 1001, 1008, 0, 0, 0), (1, 0, 0, 4, 4, 0)):
+        f = daq.daq_fill(0x1000 if N else 0, N, stride, C, 100, -200, pre, post, 0)
+        assert lib.daq_server_slot_bytes(ctypes.byref(f), flags, ctypes.byref(b)) == daq.DAQ_OK
+        cap = 0 if N == 0 else (N - 1) // (pre + post + 2) + 1
+        expect = (up(32) + up(4 * C) + up(24 * cap) + up(2 * C * ((N + 7) // 8 * 8))
+                  + (up(2 * C * stride) if flags else 0))
+        assert b.value == expect
+    f = daq.daq_fill(0x1000, 10, 12, 1, 100, -200, 8, 24, 0)  # stride not a multiple of 8
+    assert lib.daq_server_slot_bytes(ctypes.byref(f), 0, ctypes.byref(b)) == daq.DAQ_EALIGN
+    f = daq.daq_fill(0x1000, 10, 16, 0, 100, -200, 8, 24, 0)  # no channels
+    assert lib.daq_server_slot_bytes(ctypes.byref(f), 0, ctypes.byref(b)) == daq.DAQ_EINVAL
+    f = daq.daq_fill(0x1000, 10, 16, 1, 100, -200, 8, 24, 0)
+    assert lib.daq_server_slot_bytes(ctypes.byref(f), 4, ctypes.byref(b)) == daq.DAQ_EINVAL  # unknown flag
+    assert lib.daq_server_slot_bytes(ctypes.byref(f), 0, None) == daq.DAQ_EINVAL
+
+
+def test_server_calls_reject_null_handles_without_touching_a_gpu():
+    lib = daq.load_library()
+    h = ctypes.c_void_p()
+    assert lib.daq_server_create(ctypes.byref(h), None, 0x1000, 1 << 20, 1, 1) == daq.DAQ_EINVAL
+    assert lib.daq_server_create(None, None, 0x1000, 1 << 20, 1, 1) == daq.DAQ_EINVAL
+    f = daq.daq_fill(0x1000, 10, 16, 1, 100, -200, 8, 24, 0)
+    t = ctypes.c_uint64(0)
+    assert lib.daq_submit_fill(None, ctypes.byref(f), 0, 0, ctypes.byref(t)) == daq.DAQ_EINVAL
+    buf = (daq.daq_completion * 4)()
+    assert lib.daq_poll(None, buf, 4, 0) == daq.DAQ_EINVAL
+    assert lib.daq_release(None, 1) == daq.DAQ_EINVAL
+    st = daq.daq_server_stats()
+    assert lib.daq_server_get_stats(None, ctypes.byref(st)) == daq.DAQ_EINVAL
+    lib.daq_server_destroy(None)
+    d = ctypes.c_int(0)
+    assert lib.daq_ctx_get_device(None, ctypes.byref(d)) == daq.DAQ_EINVAL
+
+
+def test_server_struct_layouts():
+    assert ctypes.sizeof(daq.daq_counts) == 24
+    assert ctypes.sizeof(daq.daq_completion) == 8 + 8 + 24 + 48 + 8 + 4 + 4 + 24
+    assert ctypes.sizeof(daq.daq_server_stats) == 8 * 8 + 8

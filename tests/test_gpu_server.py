@@ -1,0 +1,182 @@
+"""GPU tests of the serving loop (daq_server_* through the C ABI).
+
+Each fill's results must be the same whether it is served alone or in a mix
+of other fills arriving while batches run, and equal to the CPU oracle
+(bit-exact: all integers). Admission follows the arena budget.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU machines
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1611_04959_amd as daq  # noqa: E402
+from gpu_util import log, oracle_many  # noqa: E402
+
+
+def _specs(n, seed):
+    """Uneven small fills: lengths, rates, thresholds and windows vary."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        out.append(synth.FillSpec(seed=synth.fill_seed("serve-test", seed, i),
+                                  n_samples=int(rng.integers(20_000, 90_001)),
+                                  rate=float(rng.uniform(0.5, 4.0)),
+                                  threshold=int(rng.integers(-400, -149)),
+                                  pre=int(rng.integers(4, 17)), post=int(rng.integers(16, 49))))
+    return out
+
+
+@pytest.fixture(scope="module")
+def workload():
+    specs = _specs(12, 7)
+    xs = synth.render_many(specs)
+    refs = oracle_many(xs, [s.n_samples for s in specs],
+                       [{"threshold": s.threshold, "pre": s.pre, "post": s.post, "ped_samples": s.ped_samples}
+                        for s in specs])
+    xd = synth.to_device(xs)
+    fills = [daq.Fill(d, s.n_samples, threshold=s.threshold, pre=s.pre, post=s.post,
+                      ped_samples=s.ped_samples) for d, s in zip(xd, specs)]
+    return specs, xs, xd, fills, refs
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = daq.Context(0)
+    c.set_schedule(256, 16, daq.DAQ_VARIANT_SPLIT)
+    yield c
+    c.close()
+
+
+def _drain(srv, want, timeout_s=60.0):
+    got = {}
+    t_end = time.time() + timeout_s
+    while len(got) < want:
+        assert time.time() < t_end, "server did not finish"
+        for c in srv.poll(64, 20_000):
+            got[c.ticket] = c
+    return got
+
+
+def _check(srv, c, ref, C, what):
+    assert c.error == daq.DAQ_OK, what
+    assert c.status == 0, what
+    assert c.n_islands == ref.n_islands and c.total_len == ref.total_len, what
+    isl, ped, out = srv.results(c, C)
+    np.testing.assert_array_equal(isl, ref.islands, err_msg=what + ": islands")
+    np.testing.assert_array_equal(ped, ref.ped, err_msg=what + ": ped")
+    np.testing.assert_array_equal(out, ref.out, err_msg=what + ": out")
+    return isl, ped, out
+
+
+def test_alone_equals_in_the_mix(ctx, workload):
+    specs, xs, xd, fills, refs = workload
+    C = synth.CHANNELS
+    need = max(daq.slot_bytes(f) for f in fills)
+    arena = torch.empty(6 * need, dtype=torch.uint8, device="cuda")  # room for ~6 fills at once
+    with daq.Server(ctx, arena, n_streams=3, max_batch=4) as srv:
+        alone = {}
+        for i, f in enumerate(fills):
+            log("server alone fill %d N=%d" % (i, specs[i].n_samples))
+            t = srv.submit(f, tag=i)
+            assert t is not None
+            (c,) = _drain(srv, 1).values()
+            assert c.tag == i and c.batch_fills == 1
+            alone[i] = _check(srv, c, refs[i], C, "alone %d" % i)
+            srv.release(t)
+        # the mix: everything at once, admitted as the budget frees up
+        log("server mix of %d fills" % len(fills))
+        order = list(range(len(fills))) * 2
+        pending, got, rejected = list(order), [], 0
+        t_end = time.time() + 60
+        while pending or len(got) < len(order):
+            assert time.time() < t_end, "mix did not finish"
+            while pending:
+                t = srv.submit(fills[pending[0]], tag=pending[0])
+                if t is None:
+                    rejected += 1
+                    break
+                pending.pop(0)
+            for c in srv.poll(64, 2_000):
+                i = c.tag
+                isl, ped, out = _check(srv, c, refs[i], C, "mix %d" % i)
+                np.testing.assert_array_equal(isl, alone[i][0])
+                np.testing.assert_array_equal(out, alone[i][2])
+                got.append(c)
+                srv.release(c.ticket)
+        st = srv.stats()
+        log("mix: %d batches, %d rejected submits, peak %.1f MB of %.1f MB" %
+            (st.batches, st.rejected, st.arena_peak / 1e6, st.arena_bytes / 1e6))
+        assert rejected > 0 and st.rejected == rejected  # the budget did bind
+        assert st.arena_peak <= st.arena_bytes
+        assert st.pending == 0 and st.running == 0 and st.arena_in_use == 0
+        assert max(c.batch_fills for c in got) > 1  # fills were batched
+
+
+def test_batches_overlap_on_the_device(ctx, workload):
+    specs, xs, xd, fills, refs = workload
+    need = sum(daq.slot_bytes(f) for f in fills)
+    arena = torch.empty(need + (1 << 20), dtype=torch.uint8, device="cuda")
+    with daq.Server(ctx, arena, n_streams=3, max_batch=2) as srv:
+        for rep in range(3):
+            tickets = [srv.submit(f, tag=i) for i, f in enumerate(fills)]
+            assert all(t is not None for t in tickets)
+            got = _drain(srv, len(fills))
+            spans = sorted((c.t_launch_ns, c.t_ready_ns) for c in got.values())
+            overlap = any(b0 < a1 for (a0, a1), (b0, b1) in zip(spans, spans[1:]))
+            for c in got.values():
+                _check(srv, c, refs[c.tag], synth.CHANNELS, "overlap %d" % c.tag)
+                assert c.t_submit_ns <= c.t_launch_ns <= c.t_ready_ns
+                srv.release(c.ticket)
+            if overlap:
+                break
+        assert overlap, "no two batches were in flight together"
+
+
+def test_host_fed_fills_match(ctx, workload):
+    specs, xs, xd, fills, refs = workload
+    host = [torch.from_numpy(x).pin_memory() for x in xs[:3]]
+    need = sum(daq.slot_bytes(f, host_raw=True) for f in fills[:3])
+    arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+    with daq.Server(ctx, arena, n_streams=2, max_batch=2) as srv:
+        for i in range(3):
+            assert srv.submit(fills[i], tag=i, host_raw=host[i]) is not None
+        got = _drain(srv, 3)
+        for c in got.values():
+            _check(srv, c, refs[c.tag], synth.CHANNELS, "host-fed %d" % c.tag)
+            srv.release(c.ticket)
+
+
+def test_admission_and_release_rules(ctx, workload):
+    specs, xs, xd, fills, refs = workload
+    f = fills[0]
+    one = daq.slot_bytes(f)
+    arena = torch.empty(2 * one + 1024, dtype=torch.uint8, device="cuda")
+    with daq.Server(ctx, arena, n_streams=1, max_batch=8) as srv:
+        t1 = srv.submit(f, tag=1)
+        t2 = srv.submit(f, tag=2)
+        assert t1 is not None and t2 is not None
+        assert srv.submit(f, tag=3) is None          # budget full: DAQ_EAGAIN
+        big = daq.Fill(xd[0], specs[0].n_samples, threshold=f.threshold, pre=f.pre, post=f.post)
+        with pytest.raises(daq.DaqError) as e:        # a slot that can never fit
+            srv.submit(daq.Fill(torch.empty((54, 8 * (arena.numel() // 54 // 16 + 8)), dtype=torch.int16,
+                                            device="cuda"), 8 * (arena.numel() // 54 // 16 + 8)))
+        assert e.value.code == daq.DAQ_ERANGE
+        got = _drain(srv, 2)
+        assert sorted(c.tag for c in got.values()) == [1, 2]
+        srv.release(t1)
+        assert srv.try_release(t1) == daq.DAQ_EINVAL  # already released
+        assert srv.try_release(12345) == daq.DAQ_EINVAL
+        t3 = srv.submit(big, tag=3)
+        assert t3 is not None
+        _drain(srv, 1)
+        srv.release(t2)
+        srv.release(t3)
+        assert srv.stats().arena_in_use == 0
