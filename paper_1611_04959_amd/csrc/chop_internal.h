@@ -26,6 +26,11 @@ constexpr int kVariantSplit = 5;     // scan pass (mask bits, tile totals), pref
 constexpr int kVariantLast = 5;
 // Guard bytes around each fill's island-mask bits (read as zero past the ends).
 constexpr int kMaskGuard = 16;
+// Packed samples per channel row that one work-group of the copy pass writes.
+#ifndef DAQ_COPY_CHUNK
+#define DAQ_COPY_CHUNK 1024
+#endif
+constexpr int kCopyChunk = DAQ_COPY_CHUNK;
 // Tile of the LDS variant: groups of 8 samples per row buffer, work-group size.
 constexpr int kStreamGroups = 80;
 constexpr int kStreamThreads = 256;
@@ -60,6 +65,10 @@ struct FillDev {
     int64_t out_stride;
     uint8_t *mbits;     // split variant: island-mask bits of the fill (bit t of
                         // byte t / 8), kMaskGuard zero bytes on either side
+    int32_t *runs;      // split variant: (start, offset) of every island
+                        // (room for the worst-case island count)
+    int32_t *cmap;      // split variant: island holding packed position
+                        // k * kCopyChunk, for every such position < total_len
 };
 static_assert(sizeof(FillDev) % 16 == 0, "descriptors are read as 16-byte words");
 
@@ -69,6 +78,8 @@ struct BatchHdr {
     int32_t n_fills;
     int32_t pad;
     int64_t total_tiles;
+    int64_t copy_slots;  // split variant: n_fills x chunks of the longest fill
+    int64_t pad2;
 };
 
 struct KArgs {
@@ -81,6 +92,7 @@ struct KArgs {
     uint32_t *ticket;      // tile dispenser
     int64_t *thr_eff;      // per fill: threshold + sum of pedestals
     uint64_t *tile_pref;   // split variant: exclusive prefix of each tile
+    int64_t copy_slots;    // split variant, when hdr is null
     FillDev one;
 };
 

@@ -1185,38 +1185,17 @@ __device__ __forceinline__ void emit_lines(const int32_t *seg_src, const int32_t
     }
 }
 
-// Tiles of one work-group. Work-groups are handed to the 8 XCDs in turn;
-// giving each XCD one contiguous chunk of tiles keeps neighbouring tiles,
-// which share the 16-byte lines at the ends of their packed ranges, in the
-// same L2.
-struct TileRange {
-    int64_t first, end, stride;
-};
-__device__ __forceinline__ TileRange xcd_tiles(int64_t total) {
-    const int G = (int)gridDim.x;
-    const int X = G < 8 ? G : 8;
-    const int x = (int)blockIdx.x % X;
-    const int64_t per = (total + X - 1) / X;
-    const int64_t first = x * per + (int64_t)blockIdx.x / X;
-    const int64_t end = (x + 1) * per < total ? (x + 1) * per : total;
-    return TileRange{first, end, (G - x + X - 1) / X};
-}
-
-#ifndef DAQ_EMIT_XCD
-#define DAQ_EMIT_XCD 1
-#endif
-
 #ifndef DAQ_EMIT_U
 #define DAQ_EMIT_U 4  // lines per thread with loads in flight
 #endif
 
-// Emit pass, one tile: island edges from the mask bits, records, packed
-// samples. Thread j takes the tile's owned samples t0 + 8j .. t0 + 8j + 7.
-// Run 0 of the run table is the island open at the tile's first sample (it
-// may be empty); the others start at the tile's rising edges.
+// Edge pass, one tile: island edges from the mask bits, the island records
+// (capacity-limited), the fill's run table (start, offset of every island)
+// and, for every multiple k of kCopyChunk among the tile's packed positions,
+// the island holding packed position k. Thread j takes the tile's owned
+// samples t0 + 8j .. t0 + 8j + 7.
 template <int NT>
-__device__ __forceinline__ void emit_pass_tile(const KArgs &a, const FillDev &fd, int64_t tile, int32_t *seg_src,
-                                               int32_t *seg_dst, int32_t *line_run, uint32_t *s_wsum) {
+__device__ __forceinline__ void edge_pass_tile(const KArgs &a, const FillDev &fd, int64_t tile, uint32_t *s_wsum) {
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -1226,6 +1205,7 @@ __device__ __forceinline__ void emit_pass_tile(const KArgs &a, const FillDev &fd
     const int own = (int)(fd.tout / kVec);  // owned groups
     const int64_t p = t0 + (int64_t)tid * kVec;
     const uint8_t *mb = fd.mbits + (t0 >> 3);
+    const uint64_t pref = *gbl(a.tile_pref + tile);
     uint32_t mm = 0, prv = 0, nxt = 0;
     if (tid < own) {
         mm = *gbl(mb + tid);
@@ -1240,61 +1220,40 @@ __device__ __forceinline__ void emit_pass_tile(const KArgs &a, const FillDev &fd
     const uint32_t inc = wave_incl_scan_u32(mine, lane);
     if (lane == 63) s_wsum[wid] = inc;
     lds_barrier();
-    uint32_t before = 0, total = 0;
+    uint32_t before = 0;
 #pragma unroll
-    for (int w = 0; w < NW; w++) {
-        const uint32_t v = s_wsum[w];
-        before += (w < wid) ? v : 0u;
-        total += v;
-    }
+    for (int w = 0; w < NW; w++) before += (w < wid) ? s_wsum[w] : 0u;
     const uint32_t excl = before + inc - mine;
     r.th_m = (int)(excl >> 16);
     r.th_i = (int)(excl & 0xFFFFu);
-    r.tile_m = (int)(total >> 16);
-    r.tile_i = (int)(total & 0xFFFFu);
-    const uint64_t pref = *gbl(a.tile_pref + tile);
     r.m_before = (int64_t)((pref >> 31) & kField);
     r.i_before = (int64_t)(pref & kField);
     write_records(fd, r, p);
-    if (fd.out == nullptr || r.tile_m == 0) return;
-    if (tid == 0) {
-        seg_src[0] = 0;
-        seg_dst[0] = 0;
-    }
-    if (r.rise) {
+    if (fd.out == nullptr || mm == 0) return;
+    const int64_t mbase = r.m_before + r.th_m;
+    const int64_t ibase = r.i_before + r.th_i;
+    DAQ_GLOBAL int32_t *runs = gbl(fd.runs);
 #pragma unroll
-        for (int k = 0; k < kVec; k++) {
-            if ((r.rise >> k) & 1u) {
-                const int j = 1 + r.th_i + __popc(r.rise & ((1u << k) - 1u));
-                seg_src[j] = tid * kVec + k;
-                seg_dst[j] = r.th_m + __popc(r.mm & ((1u << k) - 1u));
-            }
+    for (int k = 0; k < kVec; k++) {
+        if ((r.rise >> k) & 1u) {
+            const int64_t idx = ibase + __popc(r.rise & ((1u << k) - 1u));
+            runs[2 * idx] = (int32_t)(p + k);
+            runs[2 * idx + 1] = (int32_t)(mbase + __popc(r.mm & ((1u << k) - 1u)));
         }
     }
-    lds_barrier();
-    // packed lines of this tile; with one line phase for every row, the run
-    // of each line's first sample
-    const int nrun = r.tile_i + 1;
-    const bool uniform = (fd.out_stride & 7) == 0;
-    const int ph_all = line_phase(fd.out, r.m_before);
-    const int lines = uniform ? (ph_all + r.tile_m + 7) >> 3 : (r.tile_m + 14) >> 3;
-    if (uniform) {
-        for (int jj = tid; jj < lines; jj += NT) {
-            const int q = 8 * jj - ph_all;
-            line_run[jj] = run_at(seg_dst, nrun, q > 0 ? q : 0);
-        }
-        lds_barrier();
+    // at most one multiple of the chunk size among this thread's packed positions
+    const int64_t q = (mbase + kCopyChunk - 1) / kCopyChunk * kCopyChunk;
+    const int cnt = __popc(mm);
+    if (q < mbase + cnt) {
+        uint32_t bits = mm;
+        for (int64_t skip = q - mbase; skip > 0; skip--) bits &= bits - 1;  // drop the lowest set bits
+        const int b = __ffs(bits) - 1;
+        *gbl(fd.cmap + q / kCopyChunk) = (int32_t)(ibase + __popc(r.rise & ((2u << b) - 1u)) - 1);
     }
-    emit_lines<NT, DAQ_EMIT_U>(seg_src, seg_dst, line_run, uniform, ph_all, lines, nrun, r.tile_m, fd.raw, fd.stride, t0,
-                   fd.out, fd.out_stride, fd.C, r.m_before);
 }
 
 template <int NT>
-__global__ void __launch_bounds__(NT) k_emit_pass(KArgs a) {
-    constexpr int kMaxRuns = NT * kVec / 2 + 2;  // the open run and the rises
-    __shared__ int32_t s_src[kMaxRuns];
-    __shared__ int32_t s_dst[kMaxRuns];
-    __shared__ int32_t s_line_run[NT + 2];
+__global__ void __launch_bounds__(NT) k_edge_pass(KArgs a) {
     __shared__ uint32_t s_wsum[NT / 64];
     __shared__ int64_t s_base[kLdsFills];
     const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
@@ -1305,8 +1264,7 @@ __global__ void __launch_bounds__(NT) k_emit_pass(KArgs a) {
     lds_barrier();
     FillDev fd{};
     int cur = -1;
-    const TileRange tr = DAQ_EMIT_XCD ? xcd_tiles(total) : TileRange{blockIdx.x, total, gridDim.x};
-    for (int64_t tile = tr.first; tile < tr.end; tile += tr.stride) {
+    for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
         if (cur < 0 || tile < fd.tile_base || tile >= fd.tile_base + fd.n_tiles) {
             int lo = 0, hi = nf - 1;
             while (lo < hi) {
@@ -1317,8 +1275,221 @@ __global__ void __launch_bounds__(NT) k_emit_pass(KArgs a) {
             fd = fill_at(a, lo);
             cur = lo;
         }
-        emit_pass_tile<NT>(a, fd, tile, s_src, s_dst, s_line_run, s_wsum);
+        edge_pass_tile<NT>(a, fd, tile, s_wsum);
         lds_barrier();
+    }
+}
+
+// Eight consecutive int16 elements of an LDS array, starting at element e
+// (any alignment): five 4-byte reads and, for odd e, byte alignment.
+__device__ __forceinline__ uint4 lds_read8(const uint32_t *base, int e) {
+    const uint32_t *d = base + (e >> 1);
+    const uint32_t w0 = d[0], w1 = d[1], w2 = d[2], w3 = d[3], w4 = d[4];
+    if (e & 1)
+        return make_uint4(__builtin_amdgcn_alignbyte(w1, w0, 2), __builtin_amdgcn_alignbyte(w2, w1, 2),
+                          __builtin_amdgcn_alignbyte(w3, w2, 2), __builtin_amdgcn_alignbyte(w4, w3, 2));
+    return make_uint4(w0, w1, w2, w3);
+}
+
+#ifndef DAQ_STAGE_WORDS
+#define DAQ_STAGE_WORDS 1792
+#endif
+
+// How packed line j of a chunk is assembled from a staged channel row; the
+// same for every channel when all rows share one line phase.
+struct LineDesc {
+    int32_t off0;  // staged element of the line's first sample (run r0)
+    int32_t off1;  // kind 2: staged element holding line element 0 of run r0 + 1
+                   // (elements >= split are taken from there); kind 3: r0
+    int32_t span;  // lo | hi << 8 (tile-relative, minus 8 j - phase)
+    int32_t kind;  // 0 none, 1 one run, 2 two runs, 3 sample by sample | split << 4 | full << 8
+};
+
+// Copy pass: every fill's packed rows are cut into chunks of kCopyChunk
+// packed positions; a work-group copies one chunk of every channel, so each
+// has the same work whatever the island density where the chunk came from.
+// Slot g is chunk g / n_fills of fill g % n_fills (chunks past a fill's
+// total length are empty). The chunk's islands (from the run table, starting
+// at the island that holds its first position) become an LDS run table, and
+// every packed line gets a descriptor saying where its samples sit in a
+// staged channel row. For a group of channels at a time, the aligned 16-byte
+// words holding the chunk's source samples are copied into LDS by direct
+// global-to-LDS loads (all in flight at once); each (channel, line) is then
+// read from LDS and written with one 16-byte store. Chunks whose words do
+// not fit (very many tiny islands) or whose rows have different line phases
+// read global memory directly (emit_lines).
+template <int NT>
+__global__ void __launch_bounds__(NT) k_copy_pass(KArgs a) {
+    constexpr int P = kCopyChunk;
+    constexpr int SW = DAQ_STAGE_WORDS;
+    __shared__ int32_t s_src[P + 2];
+    __shared__ int32_t s_dst[P + 2];
+    __shared__ int32_t s_wb[P + 3];
+    __shared__ int32_t s_line[P / kVec + 2];
+    __shared__ int4 s_desc[P / kVec + 2];
+    __shared__ int32_t s_wsrc[SW];
+    __shared__ uint4 s_stage[SW + 1];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
+    const int64_t slots = a.hdr ? a.hdr->copy_slots : a.copy_slots;
+    for (int64_t g = blockIdx.x; g < slots; g += gridDim.x) {
+        const int f = (int)(g % nf);
+        const int64_t k = g / nf;
+        const FillDev fd = fill_at(a, f);
+        if (fd.out == nullptr) continue;
+        const int64_t q0 = k * P;
+        const int64_t tl = __builtin_amdgcn_readfirstlane((int)*gbl(&fd.counts->total_len));
+        if (q0 >= tl) continue;
+        const int64_t n_isl = __builtin_amdgcn_readfirstlane((int)*gbl(&fd.counts->n_islands));
+        const int m = (int)(tl - q0 < P ? tl - q0 : P);
+        const int i0 = __builtin_amdgcn_readfirstlane(*gbl(fd.cmap + k));
+        const int i1 = q0 + P < tl ? __builtin_amdgcn_readfirstlane(*gbl(fd.cmap + k + 1)) : (int)n_isl - 1;
+        const int nrun = i1 - i0 + 1;  // islands touching [q0, q0 + P], at most P + 1
+        for (int r = tid; r < nrun; r += NT) {
+            const int32_t st = *gbl(fd.runs + 2 * (int64_t)(i0 + r));
+            const int32_t of = *gbl(fd.runs + 2 * (int64_t)(i0 + r) + 1);
+            const int64_t d = (int64_t)of - q0;  // negative only for the first island
+            s_dst[r] = d > 0 ? (int32_t)d : 0;
+            s_src[r] = d > 0 ? st : (int32_t)(st - d);
+        }
+        lds_barrier();
+        // staged words of each run: floor8(src) .. ceil8(src + len); their prefix
+        if (wid == 0) {
+            int carry = 0;
+            for (int r0 = 0; r0 < nrun; r0 += 64) {
+                const int r = r0 + lane;
+                int words = 0;
+                if (r < nrun) {
+                    const int len = ((r + 1 < nrun) ? s_dst[r + 1] : m) - s_dst[r];
+                    words = len > 0 ? ((s_src[r] + len + 7) >> 3) - (s_src[r] >> 3) : 0;
+                }
+                const uint32_t incl = wave_incl_scan_u32((uint32_t)words, lane);
+                if (r < nrun) s_wb[r] = carry + (int)incl - words;
+                carry += (int)__shfl(incl, 63, 64);
+            }
+            if (lane == 0) s_wb[nrun] = carry;
+        }
+        lds_barrier();
+        const int W = s_wb[nrun];
+        const bool uniform = (fd.out_stride & 7) == 0;
+        const int ph_all = line_phase(fd.out, q0);
+        const int lines = uniform ? (ph_all + m + 7) >> 3 : (m + 14) >> 3;
+        const int CG = uniform ? (SW - NT) / W : 0;  // channels per staging round
+        if (CG < 1) {
+            // direct path: run of each line's first sample, then emit_lines
+            if (uniform)
+                for (int jj = tid; jj < lines; jj += NT) {
+                    const int q = 8 * jj - ph_all;
+                    s_line[jj] = run_at(s_dst, nrun, q > 0 ? q : 0);
+                }
+            lds_barrier();
+            emit_lines<NT, DAQ_EMIT_U>(s_src, s_dst, s_line, uniform, ph_all, lines, nrun, m, fd.raw, fd.stride, 0,
+                                       fd.out, fd.out_stride, fd.C, q0);
+            lds_barrier();
+            continue;
+        }
+        // source word of every staged word, and the descriptor of every line
+        for (int w = tid; w < W; w += NT) {
+            const int r = run_at(s_wb, nrun, w);
+            s_wsrc[w] = (s_src[r] >> 3) + (w - s_wb[r]);
+        }
+        for (int jj = tid; jj < lines; jj += NT) {
+            const int qa = 8 * jj - ph_all;
+            const int lo = qa > 0 ? qa : 0;
+            int hi = qa + 8 < m ? qa + 8 : m;
+            if (q0 + hi > fd.out_stride) hi = (int)(fd.out_stride - q0);
+            int4 d = make_int4(0, 0, 0, 0);
+            if (lo < hi) {
+                const int r0 = run_at(s_dst, nrun, lo);
+                const int end0 = (r0 + 1 < nrun) ? s_dst[r0 + 1] : m;
+                const int full = (lo == qa && hi == qa + 8) ? 1 : 0;
+                d.x = 8 * s_wb[r0] + (s_src[r0] & 7) + (lo - s_dst[r0]);
+                d.z = (lo - qa) | ((hi - qa) << 8);
+                if (end0 >= hi) {
+                    d.w = 1 | (full << 8);
+                } else {
+                    const int end1 = (r0 + 2 < nrun) ? s_dst[r0 + 2] : m;
+                    const int sp = end0 - lo;
+                    if (end1 >= hi) {
+                        // runs are separated by at least one sample, so this is >= 8 * wb + 1
+                        d.y = 8 * s_wb[r0 + 1] + (s_src[r0 + 1] & 7) - sp;
+                        d.w = 2 | (sp << 4) | (full << 8);
+                    } else {
+                        d.y = r0;
+                        d.w = 3 | (full << 8);
+                    }
+                }
+            }
+            s_desc[jj] = d;
+        }
+        lds_barrier();
+        const uint32_t *stage32 = reinterpret_cast<const uint32_t *>(s_stage);
+        for (int c0 = 0; c0 < fd.C; c0 += CG) {
+            const int CGn = fd.C - c0 < CG ? fd.C - c0 : CG;
+            const int n_it = CGn * W;
+            {
+                // words (cl, w) in order: slot i = cl * W + w
+                const int dq = NT / W, dr = NT - dq * W;
+                int cl = tid / W, w = tid - cl * W;
+                for (int it = 0; it * NT < n_it; it++) {
+                    const int16_t *src = fd.raw;  // slots past the group's words load a harmless word
+                    if (it * NT + tid < n_it)
+                        src = fd.raw + (int64_t)(c0 + cl) * fd.stride + (int64_t)s_wsrc[w] * kVec;
+                    __builtin_amdgcn_global_load_lds(src, (lds_void *)(s_stage + it * NT + wid * 64), 16, 0, 0);
+                    w += dr;
+                    cl += dq;
+                    if (w >= W) {
+                        w -= W;
+                        cl++;
+                    }
+                }
+            }
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's words are in LDS
+            lds_barrier();
+            {
+                const int items = CGn * lines;
+                const int dq = NT / lines, dr = NT - dq * lines;
+                int cl = tid / lines, j = tid - cl * lines;
+                for (int i = tid; i < items; i += NT) {
+                    const int4 d = s_desc[j];
+                    const int kind = d.w & 15;
+                    if (kind != 0) {
+                        const uint32_t *row = stage32 + cl * W * 4;
+                        int16_t *orow = fd.out + (int64_t)(c0 + cl) * fd.out_stride + q0 + 8 * j - ph_all;
+                        const int lo = d.z & 0xFF, hi = d.z >> 8;
+                        if (kind == 3) {
+                            int r = d.y;
+                            for (int e = lo; e < hi; e++) {
+                                const int q = 8 * j - ph_all + e;
+                                while (r + 1 < nrun && s_dst[r + 1] <= q) r++;
+                                const int el = 8 * s_wb[r] + (s_src[r] & 7) + (q - s_dst[r]);
+                                *gbl(orow + e) = reinterpret_cast<const int16_t *>(row)[el];
+                            }
+                        } else {
+                            uint4 v = lds_read8(row, d.x);
+                            if (kind == 2) v = blend8(v, lds_read8(row, d.y), (d.w >> 4) & 15);
+                            if (d.w & 256) {
+                                store16(orow, v);
+                            } else {
+                                // a line shared with a neighbouring chunk: this chunk's samples only
+                                const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+                                for (int e = lo; e < hi; e++)
+                                    *gbl(orow + e) = (int16_t)((wv[(e - lo) >> 1] >> (((e - lo) & 1) * 16)) & 0xFFFFu);
+                            }
+                        }
+                    }
+                    j += dr;
+                    cl += dq;
+                    if (j >= lines) {
+                        j -= lines;
+                        cl++;
+                    }
+                }
+            }
+            lds_barrier();
+        }
     }
 }
 
@@ -1454,22 +1625,21 @@ hipError_t launch_chop(const KArgs &a, int threads, int variant, int grid, hipSt
     return hipGetLastError();
 }
 
-#ifndef DAQ_EMIT_GRID_MULT
-#define DAQ_EMIT_GRID_MULT 1
-#endif
-
 hipError_t launch_split(const KArgs &a, int threads, int grid, int prefix_blocks, hipStream_t s) {
-    int64_t eg = (int64_t)grid * DAQ_EMIT_GRID_MULT;
-    if (!a.hdr && eg > a.total_tiles) eg = a.total_tiles > grid ? a.total_tiles : grid;
-    const int egrid = (int)(eg < (1 << 30) ? eg : (1 << 30));
+    // the copy pass: as many work-groups as the chunks of the batch (graphs:
+    // the persistent grid, which strides over them)
+    int64_t cg = a.hdr ? (int64_t)grid : a.copy_slots;
+    cg = cg < 1 ? 1 : (cg < (1 << 30) ? cg : (1 << 30));
     if (threads == 256) {
         hipLaunchKernelGGL((k_scan_pass<256, 6>), dim3(grid), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_prefix_pass, dim3(prefix_blocks), dim3(256), 0, s, a);
-        hipLaunchKernelGGL((k_emit_pass<256>), dim3(egrid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_edge_pass<256>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_copy_pass<256>), dim3((int)cg), dim3(256), 0, s, a);
     } else if (threads == 512) {
         hipLaunchKernelGGL((k_scan_pass<512, 6>), dim3(grid), dim3(512), 0, s, a);
         hipLaunchKernelGGL(k_prefix_pass, dim3(prefix_blocks), dim3(256), 0, s, a);
-        hipLaunchKernelGGL((k_emit_pass<512>), dim3(egrid), dim3(512), 0, s, a);
+        hipLaunchKernelGGL((k_edge_pass<512>), dim3(grid), dim3(512), 0, s, a);
+        hipLaunchKernelGGL((k_copy_pass<512>), dim3((int)cg), dim3(512), 0, s, a);
     } else {
         return hipErrorInvalidValue;
     }

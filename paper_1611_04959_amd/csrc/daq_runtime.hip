@@ -248,11 +248,22 @@ int64_t tiles_of(const daq_fill &f, const daq_schedule &sc) {
     return (f.n_samples + T - 1) / T;
 }
 
-// Bytes of island-mask bits (with guards) the split variant needs for a fill.
-int64_t mask_bytes_of(const daq_fill &f, const daq_schedule &sc) {
+// Scratch of one fill under the split variant: island-mask bits (with
+// guards), the (start, offset) run table for the worst-case island count and
+// the island of every chunk start, each part 16-byte aligned.
+struct SplitLayout {
+    int64_t runs = 0, cmap = 0, bytes = 0;
+};
+SplitLayout split_layout_of(const daq_fill &f, const daq_schedule &sc) {
     const int64_t tout = daqk::tile_shape(f.pre, f.post, f.n_channels, sc.threads, sc.variant).tout;
     const int64_t data = tiles_of(f, sc) * tout / daqk::kVec;
-    return (data + 2 * daqk::kMaskGuard + 15) / 16 * 16;
+    SplitLayout L;
+    L.runs = (data + 2 * daqk::kMaskGuard + 15) / 16 * 16;
+    const int64_t isl = std::max<int64_t>(daq_max_islands(f.n_samples, f.pre, f.post), 0);
+    L.cmap = L.runs + (8 * isl + 15) / 16 * 16;
+    const int64_t chunks = (f.n_samples + daqk::kCopyChunk - 1) / daqk::kCopyChunk + 2;
+    L.bytes = L.cmap + (4 * chunks + 15) / 16 * 16;
+    return L;
 }
 
 FillDev make_desc(const daq_fill &f, const daq_fill_out &o, int64_t tile_base, const daq_schedule &sc) {
@@ -378,15 +389,19 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     // the register variant keeps exactly 54 rows per thread: calls with other
     // channel counts run the re-read variant
     if (sc.variant == daqk::kVariantResident && !all_calorimeters(fills, n)) sc.variant = daqk::kVariantReload;
-    int64_t total = 0, mask_total = 0;
+    int64_t total = 0, mask_total = 0, max_chunks = 0;
     std::vector<int64_t> base((size_t)n), moff((size_t)n, -1);
+    std::vector<SplitLayout> lay((size_t)n);
     const bool split = sc.variant == daqk::kVariantSplit;
     for (int32_t i = 0; i < n; i++) {
         base[(size_t)i] = total;
         total += tiles_of(fills[i], sc);
         if (split) {
             moff[(size_t)i] = mask_total;
-            mask_total += mask_bytes_of(fills[i], sc);
+            lay[(size_t)i] = split_layout_of(fills[i], sc);
+            mask_total += lay[(size_t)i].bytes;
+            max_chunks = std::max<int64_t>(max_chunks, (fills[i].n_samples + daqk::kCopyChunk - 1) /
+                                                           daqk::kCopyChunk);
         }
     }
     Scratch *s = scratch_for(ctx, stream);
@@ -395,6 +410,8 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     auto desc = [&](int32_t i) {
         FillDev d = make_desc(fills[i], outs[i], base[(size_t)i], sc);
         d.mbits = split ? s->mask + moff[(size_t)i] + daqk::kMaskGuard : nullptr;
+        d.runs = split ? reinterpret_cast<int32_t *>(s->mask + moff[(size_t)i] + lay[(size_t)i].runs) : nullptr;
+        d.cmap = split ? reinterpret_cast<int32_t *>(s->mask + moff[(size_t)i] + lay[(size_t)i].cmap) : nullptr;
         return d;
     };
     KArgs a{};
@@ -404,6 +421,7 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     a.tile_pref = s->tile_pref;
     a.n_fills = n;
     a.total_tiles = total;
+    a.copy_slots = split ? max_chunks * n : 0;
     if (n == 1 && !force_table) {
         a.one = desc(0);
         return launch_pair(ctx, a, total, stream, sc);
@@ -417,6 +435,8 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     h->n_fills = n;
     h->pad = 0;
     h->total_tiles = total;
+    h->copy_slots = a.copy_slots;
+    h->pad2 = 0;
     for (int32_t i = 0; i < n; i++) tab[i] = desc(i);
     HIP_TRY(hipMemcpyAsync(s->hdr, h, sizeof(BatchHdr), hipMemcpyHostToDevice, stream));
     HIP_TRY(hipMemcpyAsync(s->table, tab, (size_t)n * sizeof(FillDev), hipMemcpyHostToDevice, stream));
