@@ -922,6 +922,10 @@ __global__ void __launch_bounds__(NT) k_chop(KArgs a) {
 // island samples. No tile waits for another, so the streaming pass keeps as
 // many loads in flight as the CU holds.
 
+#ifndef DAQ_SCAN_ROWS
+#define DAQ_SCAN_ROWS 6  // channel rows each thread has in flight
+#endif
+
 // Scan pass, one tile: flags, dilation, mask bits, totals.
 template <int NT, int R>
 __device__ __forceinline__ void scan_pass_tile(const KArgs &a, const FillDev &fd, int32_t thr_eff, int64_t tile,
@@ -1631,12 +1635,12 @@ hipError_t launch_split(const KArgs &a, int threads, int grid, int prefix_blocks
     int64_t cg = a.hdr ? (int64_t)grid : a.copy_slots;
     cg = cg < 1 ? 1 : (cg < (1 << 30) ? cg : (1 << 30));
     if (threads == 256) {
-        hipLaunchKernelGGL((k_scan_pass<256, 6>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_scan_pass<256, DAQ_SCAN_ROWS>), dim3(grid), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_prefix_pass, dim3(prefix_blocks), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_edge_pass<256>), dim3(grid), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_copy_pass<256>), dim3((int)cg), dim3(256), 0, s, a);
     } else if (threads == 512) {
-        hipLaunchKernelGGL((k_scan_pass<512, 6>), dim3(grid), dim3(512), 0, s, a);
+        hipLaunchKernelGGL((k_scan_pass<512, DAQ_SCAN_ROWS>), dim3(grid), dim3(512), 0, s, a);
         hipLaunchKernelGGL(k_prefix_pass, dim3(prefix_blocks), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_edge_pass<512>), dim3(grid), dim3(512), 0, s, a);
         hipLaunchKernelGGL((k_copy_pass<512>), dim3((int)cg), dim3(512), 0, s, a);

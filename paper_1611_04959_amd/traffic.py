@@ -9,8 +9,10 @@ the reported figures are bytes.
   python -m paper_1611_04959_amd.traffic copy [MiB]
   python -m paper_1611_04959_amd.traffic summarize FETCH_DIR WRITE_DIR \
          COPY_FETCH_DIR COPY_WRITE_DIR OUT_JSON [fills]
+  python -m paper_1611_04959_amd.traffic stats KERNEL_STATS_CSV
 
-``summarize`` writes OUT_JSON (read by bench.py) and prints a text summary.
+``summarize`` writes OUT_JSON (read by bench.py) and prints a text summary;
+``stats`` prints a rocprofv3 ``--stats`` kernel table as markdown.
 """
 from __future__ import annotations
 
@@ -24,7 +26,7 @@ from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(HERE, "csrc", "chop_kernels.hip")
-PASS_KERNELS = ("k_prepare", "k_scan_pass", "k_prefix_pass", "k_emit_pass", "k_chop")
+PASS_KERNELS = ("k_prepare", "k_scan_pass", "k_prefix_pass", "k_edge_pass", "k_copy_pass", "k_emit_pass", "k_chop")
 
 
 def kernel_sha() -> str:
@@ -112,9 +114,27 @@ def summarize(fetch_dir, write_dir, cf_dir, cw_dir, out_json, fills=16, mib=1024
     return res
 
 
+def stats_table(path):
+    rows = list(csv.DictReader(open(path, newline="")))
+    print("| Kernel | Calls | Average (us) | Min (us) | Max (us) | Share |")
+    print("|---|---|---|---|---|---|")
+    for r in rows:
+        name = r["Name"].replace("daqk::(anonymous namespace)::", "").replace("void ", "")
+        name = name if len(name) <= 60 else name[:57] + "..."
+        print("| `%s` | %s | %.1f | %.1f | %.1f | %.1f %% |" % (
+            name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+            float(r["Percentage"])))
+    pas = [r for r in rows if any(k in r["Name"] for k in PASS_KERNELS if k != "k_prepare")]
+    tot = sum(float(r["AverageNs"]) for r in pas) / 1e3
+    print()
+    print("Timed launch (every kernel above named k_* except k_prepare): %.1f us." % tot)
+
+
 if __name__ == "__main__":
     if len(sys.argv) >= 2 and sys.argv[1] == "copy":
         copy_run(int(sys.argv[2]) if len(sys.argv) > 2 else 1024)
+    elif len(sys.argv) == 3 and sys.argv[1] == "stats":
+        stats_table(sys.argv[2])
     elif len(sys.argv) >= 7 and sys.argv[1] == "summarize":
         summarize(*sys.argv[2:7], fills=int(sys.argv[7]) if len(sys.argv) > 7 else 16)
     else:
