@@ -44,6 +44,57 @@ def kernel_sha():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
+def batch_bench(daq, synth, specs, what, steps=20, warmup=3):
+    """One batched launch over `specs` (autotuned on that batch): raw GB/s,
+    the chop pass's HIP-event time, and parity of the first fill."""
+    import numpy as np
+    import torch
+    log("batch %s: rendering %d fills" % (what.split(":")[0], len(specs)))
+    xs = synth.render_many(specs)
+    xd = synth.to_device(xs)
+    fills = [daq.Fill(d, sp.n_samples, threshold=sp.threshold, pre=sp.pre, post=sp.post,
+                      ped_samples=sp.ped_samples) for d, sp in zip(xd, specs)]
+    outs = [daq.alloc_out(f) for f in fills]
+    raw = sum(sp.raw_bytes for sp in specs)
+    ctx = daq.Context(0)
+    best = ctx.daq_autotune(fills, outs)
+    ctx.set_graphs(True)
+    for _ in range(warmup):
+        ctx.daq_process_batch(fills, outs)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.daq_process_batch(fills, outs)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    kern = ctx.kernel_times_ms()
+    ctx.set_timing(False)
+    parity = None
+    try:
+        import oracle
+        ref = oracle.chop(xs[0], n_samples=specs[0].n_samples, ped_samples=specs[0].ped_samples,
+                          threshold=specs[0].threshold, pre=specs[0].pre, post=specs[0].post)
+        isl, n, total, st, ped, out = outs[0].host()
+        parity = bool(n == ref.n_islands and total == ref.total_len and st == 0 and
+                      np.array_equal(isl, ref.islands) and np.array_equal(ped, ref.ped) and
+                      np.array_equal(out, ref.out))
+    except ImportError:
+        pass
+    tot = sum(int(o.counts[1].item()) for o in outs)
+    ctx.close()
+    res = {"workload": what, "fills": len(specs), "raw_gb": round(raw / 1e9, 3),
+           "ms_per_step": round(ms, 4), "gbs": round(raw / (ms * 1e-3) / 1e9, 1),
+           "pct_hbm_peak": round(100 * raw / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
+           "kernel_ms_mean": round(float(np.mean(kern)), 4) if kern else None,
+           "occupancy": round(tot / sum(sp.n_samples for sp in specs), 4),
+           "schedule": {"threads": best.threads, "wgs_per_cu": best.wgs_per_cu, "variant": best.variant},
+           "steps": steps, "parity_fill0": parity}
+    del xd, fills, outs
+    torch.cuda.empty_cache()
+    return res
+
+
 def arrivals(rate, seconds, rng, burst_x=5.0, burst_s=0.080, duty=0.10):
     """Arrival times (s) of a Poisson process of long-run mean `rate` per second
     whose rate is burst_x times higher inside bursts of burst_s seconds that
@@ -164,6 +215,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default schedule")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="serving loop at the nominal arrival rate (0 = skip)")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch line")
+    ap.add_argument("--stress", action="store_true",
+                    help="also time the whole-detector stress batch (96 calorimeter fills, 5.8 GB)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -295,6 +349,17 @@ def main():
                            "p50_fill_ms": round(pct(lat, 50), 4), "p99_fill_ms": round(pct(lat, 99), 4)}
             log("plain %s: %.1f GB/s" % (mode, plain[mode]["gbs"]))
 
+    # ---- the other batch shapes: uneven batch, whole-detector stress -----------------
+    others = {}
+    if not args.no_uneven:
+        others["uneven"] = batch_bench(daq, synth, synth.config_c2(), "24 uneven calorimeter streams: N ~ "
+                                       "U{100k..560k}, rate 0.5-4x, thr -400..-150, pre 4-16, post 16-48",
+                                       steps=max(10, args.steps // 2))
+    if args.stress:
+        others["stress"] = batch_bench(daq, synth, synth.config_c4(), "whole detector: 4 fills x 24 "
+                                       "calorimeters x 54 ch x 560,000, 10x rate, thr -100, pre 8, post 48",
+                                       steps=max(5, args.steps // 10))
+
     # ---- serving loop: Poisson arrivals with bursts, HBM-budget admission -------------
     serving = None
     if args.serve_seconds > 0:
@@ -344,6 +409,7 @@ def main():
         "occupancy": round(sum(tot) / (N * len(specs)), 4),
         "parity_fill0": parity,
         "roofline": roofline,
+        "other_batches": others,
         "serving": serving,
         "cpu_baseline": cpu,
     }
