@@ -134,7 +134,11 @@ typedef struct daq_schedule {
                             cannot take (other channel counts, halos wider
                             than a quarter of its tile) use the re-read path
                             inside the same launch                             */
-    int32_t reserved;
+    int32_t parts;       /* DAQ_VARIANT_SPLIT only: a batch is cut into this
+                            many groups of fills (0 or 1: one group, at most
+                            4), each on its own HIP stream, group k's scan
+                            starting after group k-1's so that it overlaps
+                            group k-1's copy; 0 for the other variants       */
 } daq_schedule;
 
 typedef struct daq_ctx daq_ctx;

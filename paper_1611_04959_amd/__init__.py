@@ -56,7 +56,7 @@ class daq_fill_out(ctypes.Structure):
 
 class daq_schedule(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
-                ("variant", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("variant", ctypes.c_int32), ("parts", ctypes.c_int32)]
 
 
 class daq_counts(ctypes.Structure):
@@ -307,8 +307,8 @@ class Context:
         return best
 
     # -- settings ----------------------------------------------------------
-    def set_schedule(self, threads: int = 256, wgs_per_cu: int = 16, variant: int = 5):
-        s = daq_schedule(threads, wgs_per_cu, variant, 0)
+    def set_schedule(self, threads: int = 256, wgs_per_cu: int = 16, variant: int = 5, parts: int = 0):
+        s = daq_schedule(threads, wgs_per_cu, variant, parts)
         _check(self._lib.daq_ctx_set_schedule(self.handle, ctypes.byref(s)), "daq_ctx_set_schedule")
 
     def get_schedule(self) -> daq_schedule:

@@ -93,6 +93,8 @@ struct KArgs {
     int64_t *thr_eff;      // per fill: threshold + sum of pedestals
     uint64_t *tile_pref;   // split variant: exclusive prefix of each tile
     int64_t copy_slots;    // split variant, when hdr is null
+    int32_t part, parts;   // split variant: this launch covers fill group `part`
+                           // of `parts` equal groups of the batch
     FillDev one;
 };
 
@@ -134,8 +136,12 @@ inline TileShape tile_shape(int32_t pre, int32_t post, int32_t channels, int thr
 
 hipError_t launch_prepare(const KArgs &a, int blocks, hipStream_t s);
 hipError_t launch_chop(const KArgs &a, int threads, int variant, int grid, hipStream_t s);
-// Split variant: scan pass, per-fill prefix pass, emit pass.
-hipError_t launch_split(const KArgs &a, int threads, int grid, int prefix_blocks, hipStream_t s);
+// Split variant: the scan pass, then the prefix, edge and copy passes, over
+// the fill group a.part of a.parts.
+hipError_t launch_scan(const KArgs &a, int threads, int grid, hipStream_t s);
+hipError_t launch_emit(const KArgs &a, int threads, int grid, int prefix_blocks, hipStream_t s);
+// Most fill groups a split launch is cut into (one HIP stream each).
+constexpr int kMaxParts = 4;
 hipError_t launch_gather(const GatherArgs &g, int grid, hipStream_t s);
 
 }  // namespace daqk

@@ -922,6 +922,23 @@ __global__ void __launch_bounds__(NT) k_chop(KArgs a) {
 // island samples. No tile waits for another, so the streaming pass keeps as
 // many loads in flight as the CU holds.
 
+// Fills [lo, hi) and their tiles [tile_lo, tile_hi) of the launch's part of
+// the batch (the whole batch when parts <= 1).
+struct PartRange {
+    int lo, hi;
+    int64_t tile_lo, tile_hi;
+};
+__device__ __forceinline__ PartRange part_range(const KArgs &a, int nf, int64_t total) {
+    PartRange r{0, nf, 0, total};
+    if (a.parts > 1) {
+        r.lo = (int)((int64_t)nf * a.part / a.parts);
+        r.hi = (int)((int64_t)nf * (a.part + 1) / a.parts);
+        r.tile_lo = r.lo < nf ? tile_base_at(a, r.lo) : total;
+        r.tile_hi = r.hi < nf ? tile_base_at(a, r.hi) : total;
+    }
+    return r;
+}
+
 #ifndef DAQ_SCAN_ROWS
 #define DAQ_SCAN_ROWS 6  // channel rows each thread has in flight
 #endif
@@ -999,7 +1016,8 @@ __global__ void __launch_bounds__(NT) k_scan_pass(KArgs a) {
     FillDev fd{};
     int cur = -1;
     int32_t thr_eff = 0;
-    for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const PartRange pr = part_range(a, nf, total);
+    for (int64_t tile = pr.tile_lo + blockIdx.x; tile < pr.tile_hi; tile += gridDim.x) {
         if (cur < 0 || tile < fd.tile_base || tile >= fd.tile_base + fd.n_tiles) {
             int lo = 0, hi = nf - 1;
             while (lo < hi) {
@@ -1023,7 +1041,9 @@ __global__ void __launch_bounds__(256) k_prefix_pass(KArgs a) {
     const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
-    for (int f = blockIdx.x; f < nf; f += gridDim.x) {
+    const int64_t total = a.hdr ? a.hdr->total_tiles : a.total_tiles;
+    const PartRange pr = part_range(a, nf, total);
+    for (int f = pr.lo + blockIdx.x; f < pr.hi; f += gridDim.x) {
         const FillDev fd = fill_at(a, f);
         uint64_t carry = 0;
         for (int64_t i0 = 0; i0 < fd.n_tiles; i0 += 256) {
@@ -1268,7 +1288,8 @@ __global__ void __launch_bounds__(NT) k_edge_pass(KArgs a) {
     lds_barrier();
     FillDev fd{};
     int cur = -1;
-    for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const PartRange pr = part_range(a, nf, total);
+    for (int64_t tile = pr.tile_lo + blockIdx.x; tile < pr.tile_hi; tile += gridDim.x) {
         if (cur < 0 || tile < fd.tile_base || tile >= fd.tile_base + fd.n_tiles) {
             int lo = 0, hi = nf - 1;
             while (lo < hi) {
@@ -1312,8 +1333,8 @@ struct LineDesc {
 // Copy pass: every fill's packed rows are cut into chunks of kCopyChunk
 // packed positions; a work-group copies one chunk of every channel, so each
 // has the same work whatever the island density where the chunk came from.
-// Slot g is chunk g / n_fills of fill g % n_fills (chunks past a fill's
-// total length are empty). The chunk's islands (from the run table, starting
+// Slot g is chunk g / n of fill g % n of the launch's n fills (chunks past a
+// fill's total length are empty). The chunk's islands (from the run table, starting
 // at the island that holds its first position) become an LDS run table, and
 // every packed line gets a descriptor saying where its samples sit in a
 // staged channel row. For a group of channels at a time, the aligned 16-byte
@@ -1337,10 +1358,13 @@ __global__ void __launch_bounds__(NT) k_copy_pass(KArgs a) {
     const int lane = tid & 63;
     const int wid = tid >> 6;
     const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
-    const int64_t slots = a.hdr ? a.hdr->copy_slots : a.copy_slots;
+    const int64_t all_slots = a.hdr ? a.hdr->copy_slots : a.copy_slots;
+    const PartRange pr = part_range(a, nf, a.hdr ? a.hdr->total_tiles : a.total_tiles);
+    const int nfp = pr.hi - pr.lo;
+    const int64_t slots = nf > 0 ? all_slots / nf * nfp : 0;  // the part's fills x chunks of the longest fill
     for (int64_t g = blockIdx.x; g < slots; g += gridDim.x) {
-        const int f = (int)(g % nf);
-        const int64_t k = g / nf;
+        const int f = pr.lo + (int)(g % nfp);
+        const int64_t k = g / nfp;
         const FillDev fd = fill_at(a, f);
         if (fd.out == nullptr) continue;
         const int64_t q0 = k * P;
@@ -1629,18 +1653,23 @@ hipError_t launch_chop(const KArgs &a, int threads, int variant, int grid, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_split(const KArgs &a, int threads, int grid, int prefix_blocks, hipStream_t s) {
+hipError_t launch_scan(const KArgs &a, int threads, int grid, hipStream_t s) {
+    if (threads == 256) hipLaunchKernelGGL((k_scan_pass<256, DAQ_SCAN_ROWS>), dim3(grid), dim3(256), 0, s, a);
+    else if (threads == 512) hipLaunchKernelGGL((k_scan_pass<512, DAQ_SCAN_ROWS>), dim3(grid), dim3(512), 0, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const KArgs &a, int threads, int grid, int prefix_blocks, hipStream_t s) {
     // the copy pass: as many work-groups as the chunks of the batch (graphs:
     // the persistent grid, which strides over them)
     int64_t cg = a.hdr ? (int64_t)grid : a.copy_slots;
     cg = cg < 1 ? 1 : (cg < (1 << 30) ? cg : (1 << 30));
     if (threads == 256) {
-        hipLaunchKernelGGL((k_scan_pass<256, DAQ_SCAN_ROWS>), dim3(grid), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_prefix_pass, dim3(prefix_blocks), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_edge_pass<256>), dim3(grid), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_copy_pass<256>), dim3((int)cg), dim3(256), 0, s, a);
     } else if (threads == 512) {
-        hipLaunchKernelGGL((k_scan_pass<512, DAQ_SCAN_ROWS>), dim3(grid), dim3(512), 0, s, a);
         hipLaunchKernelGGL(k_prefix_pass, dim3(prefix_blocks), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_edge_pass<512>), dim3(grid), dim3(512), 0, s, a);
         hipLaunchKernelGGL((k_copy_pass<512>), dim3((int)cg), dim3(512), 0, s, a);

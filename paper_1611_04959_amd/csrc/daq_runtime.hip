@@ -45,12 +45,12 @@ constexpr int kPrepareBlocks = 1024;
 constexpr int kPrefixBlocks = 256;
 
 struct GraphKey {
-    int threads = 0, wgs = 0, variant = 0;
+    int threads = 0, wgs = 0, variant = 0, parts = 0;
     const void *table = nullptr;
     const void *state = nullptr;
     bool operator==(const GraphKey &o) const {
-        return threads == o.threads && wgs == o.wgs && variant == o.variant && table == o.table &&
-               state == o.state;
+        return threads == o.threads && wgs == o.wgs && variant == o.variant && parts == o.parts &&
+               table == o.table && state == o.state;
     }
 };
 
@@ -67,13 +67,19 @@ struct Scratch {
     hipEvent_t ring_ev[kRing] = {};
     bool ring_used[kRing] = {};
     int ring_pos = 0;
-    hipGraphExec_t g_prep = nullptr, g_chop = nullptr;
+    hipGraphExec_t g_prep = nullptr, g_chop = nullptr;  // the two halves (timed launches)
+    hipGraphExec_t g_all = nullptr;                     // both in one graph (untimed launches)
     GraphKey key;
     uint64_t *digest = nullptr;  // autotune digests
     int32_t digest_cap = 0;
     uint64_t *tile_pref = nullptr;  // split variant: tile prefixes (tile_cap)
     uint8_t *mask = nullptr;        // split variant: island-mask bits of all fills
     int64_t mask_cap = 0;
+    // split variant with fill groups: streams of groups 1.., fork/join events
+    hipStream_t part_stream[daqk::kMaxParts] = {};
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_scan[daqk::kMaxParts] = {};
+    hipEvent_t ev_join[daqk::kMaxParts] = {};
 };
 
 }  // namespace
@@ -137,12 +143,20 @@ int timing_end(daq_ctx *ctx, hipStream_t stream, size_t slot) {
 void free_graphs(Scratch *s) {
     if (s->g_prep) (void)hipGraphExecDestroy(s->g_prep);
     if (s->g_chop) (void)hipGraphExecDestroy(s->g_chop);
-    s->g_prep = s->g_chop = nullptr;
+    if (s->g_all) (void)hipGraphExecDestroy(s->g_all);
+    s->g_prep = s->g_chop = s->g_all = nullptr;
     s->key = GraphKey{};
 }
 
 void free_scratch(Scratch *s) {
     free_graphs(s);
+    for (int k = 0; k < daqk::kMaxParts; k++) {
+        if (s->part_stream[k]) (void)hipStreamSynchronize(s->part_stream[k]);
+        if (s->part_stream[k]) (void)hipStreamDestroy(s->part_stream[k]);
+        if (s->ev_scan[k]) (void)hipEventDestroy(s->ev_scan[k]);
+        if (s->ev_join[k]) (void)hipEventDestroy(s->ev_join[k]);
+    }
+    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
     (void)hipFree(s->tile_state);
     (void)hipFree(s->ticket);
     (void)hipFree(s->thr_eff);
@@ -305,18 +319,61 @@ bool all_calorimeters(const daq_fill *fills, int32_t n) {
     return true;
 }
 
-int launch_main(const daq_ctx *ctx, const KArgs &a, const daq_schedule &s, int grid, hipStream_t stream) {
+// Streams and events for cutting a split launch into `parts` fill groups.
+int ensure_parts(Scratch *sc, int parts) {
+    if (!sc->ev_fork) HIP_TRY(hipEventCreateWithFlags(&sc->ev_fork, hipEventDisableTiming));
+    for (int k = 0; k < parts; k++) {
+        if (k > 0 && !sc->part_stream[k]) HIP_TRY(hipStreamCreateWithFlags(&sc->part_stream[k], hipStreamNonBlocking));
+        if (!sc->ev_scan[k]) HIP_TRY(hipEventCreateWithFlags(&sc->ev_scan[k], hipEventDisableTiming));
+        if (!sc->ev_join[k]) HIP_TRY(hipEventCreateWithFlags(&sc->ev_join[k], hipEventDisableTiming));
+    }
+    return DAQ_OK;
+}
+
+int launch_main(const daq_ctx *ctx, Scratch *sc, const KArgs &a, const daq_schedule &s, int grid,
+                hipStream_t stream) {
     if (s.variant == daqk::kVariantSplit) {
         const int pb = std::max(1, std::min(a.hdr ? kPrefixBlocks : a.n_fills, kPrefixBlocks));
-        HIP_TRY(daqk::launch_split(a, s.threads, grid, pb, stream));
+        const int parts = (a.table && s.parts > 1) ? std::min(s.parts, daqk::kMaxParts) : 1;
+        if (parts == 1) {
+            KArgs a1 = a;
+            a1.part = 0;
+            a1.parts = 1;
+            HIP_TRY(daqk::launch_scan(a1, s.threads, grid, stream));
+            HIP_TRY(daqk::launch_emit(a1, s.threads, grid, pb, stream));
+            return DAQ_OK;
+        }
+        // fill group k runs on its own stream; its scan starts when group
+        // k-1's scan has finished, so group k's scan overlaps the edge and
+        // copy passes of group k-1
+        int rc = ensure_parts(sc, parts);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(sc->ev_fork, stream));
+        for (int k = 0; k < parts; k++) {
+            hipStream_t sk = k == 0 ? stream : sc->part_stream[k];
+            KArgs ak = a;
+            ak.part = k;
+            ak.parts = parts;
+            if (k > 0) {
+                HIP_TRY(hipStreamWaitEvent(sk, sc->ev_fork, 0));
+                HIP_TRY(hipStreamWaitEvent(sk, sc->ev_scan[k - 1], 0));
+            }
+            HIP_TRY(daqk::launch_scan(ak, s.threads, grid, sk));
+            HIP_TRY(hipEventRecord(sc->ev_scan[k], sk));
+            HIP_TRY(daqk::launch_emit(ak, s.threads, grid, pb, sk));
+            if (k > 0) HIP_TRY(hipEventRecord(sc->ev_join[k], sk));
+        }
+        for (int k = 1; k < parts; k++) HIP_TRY(hipStreamWaitEvent(stream, sc->ev_join[k], 0));
         return DAQ_OK;
     }
     (void)ctx;
+    (void)sc;
     HIP_TRY(daqk::launch_chop(a, s.threads, s.variant, grid, stream));
     return DAQ_OK;
 }
 
-int launch_pair(daq_ctx *ctx, const KArgs &a, int64_t total_tiles, hipStream_t stream, const daq_schedule &s) {
+int launch_pair(daq_ctx *ctx, Scratch *sc, const KArgs &a, int64_t total_tiles, hipStream_t stream,
+                const daq_schedule &s) {
     int prep_blocks = (int)std::min<int64_t>(kPrepareBlocks, std::max<int64_t>(1, (total_tiles + 2047) / 2048));
     prep_blocks = std::max(prep_blocks, std::min(a.n_fills, kPrepareBlocks));
     prep_blocks = std::min(prep_blocks, std::max(a.n_fills, 64));
@@ -327,7 +384,7 @@ int launch_pair(daq_ctx *ctx, const KArgs &a, int64_t total_tiles, hipStream_t s
         int rc = timing_begin(ctx, stream, &slot);
         if (rc) return rc;
     }
-    int rc = launch_main(ctx, a, s, chop_grid(ctx, s, total_tiles), stream);
+    int rc = launch_main(ctx, sc, a, s, chop_grid(ctx, s, total_tiles), stream);
     if (rc) return rc;
     if (ctx->timing) return timing_end(ctx, stream, slot);
     return DAQ_OK;
@@ -356,16 +413,28 @@ int capture_graphs(daq_ctx *ctx, Scratch *s, const daq_schedule &sc) {
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(e);
     HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
-    const int rc0 = launch_main(ctx, a, sc, sc.wgs_per_cu * ctx->n_cu, ctx->capture);
+    const int rc0 = launch_main(ctx, s, a, sc, sc.wgs_per_cu * ctx->n_cu, ctx->capture);
     e2 = hipStreamEndCapture(ctx->capture, &g);
     if (rc0) return rc0;
     if (e2 != hipSuccess) return hip_fail(e2);
     e = hipGraphInstantiate(&s->g_chop, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(e);
+    // prepare and main pass in one graph: one launch, no gap between the two
+    HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+    e = daqk::launch_prepare(a, kPrepareBlocks, ctx->capture);
+    const int rc1 = e == hipSuccess ? launch_main(ctx, s, a, sc, sc.wgs_per_cu * ctx->n_cu, ctx->capture) : DAQ_OK;
+    e2 = hipStreamEndCapture(ctx->capture, &g);
+    if (e != hipSuccess) return hip_fail(e);
+    if (rc1) return rc1;
+    if (e2 != hipSuccess) return hip_fail(e2);
+    e = hipGraphInstantiate(&s->g_all, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e);
     s->key.threads = sc.threads;
     s->key.wgs = sc.wgs_per_cu;
     s->key.variant = sc.variant;
+    s->key.parts = sc.parts;
     s->key.table = s->table;
     s->key.state = s->tile_state;
     return DAQ_OK;
@@ -424,7 +493,7 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     a.copy_slots = split ? max_chunks * n : 0;
     if (n == 1 && !force_table) {
         a.one = desc(0);
-        return launch_pair(ctx, a, total, stream, sc);
+        return launch_pair(ctx, s, a, total, stream, sc);
     }
     // stage the descriptors
     const int rs = s->ring_pos;
@@ -445,16 +514,21 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     a.table = s->table;
     a.hdr = s->hdr;
     const bool use_graph = ctx->graphs && sc.wgs_per_cu > 0;
-    if (!use_graph) return launch_pair(ctx, a, total, stream, sc);
+    if (!use_graph) return launch_pair(ctx, s, a, total, stream, sc);
     GraphKey want;
     want.threads = sc.threads;
     want.wgs = sc.wgs_per_cu;
     want.variant = sc.variant;
+    want.parts = sc.parts;
     want.table = s->table;
     want.state = s->tile_state;
     if (!s->g_chop || !(s->key == want)) {
         rc = capture_graphs(ctx, s, sc);
         if (rc) return rc;
+    }
+    if (!ctx->timing) {
+        HIP_TRY(hipGraphLaunch(s->g_all, stream));
+        return DAQ_OK;
     }
     HIP_TRY(hipGraphLaunch(s->g_prep, stream));
     size_t slot = 0;
@@ -654,7 +728,8 @@ int daq_process_batch(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *o
 int daq_ctx_set_schedule(daq_ctx *ctx, const daq_schedule *s) {
     if (!ctx || !s) return DAQ_EINVAL;
     if ((s->threads != 128 && s->threads != 256 && s->threads != 512) || s->wgs_per_cu < 0 || s->wgs_per_cu > 16 ||
-        s->variant < daqk::kVariantReload || s->variant > daqk::kVariantLast || s->reserved != 0)
+        s->variant < daqk::kVariantReload || s->variant > daqk::kVariantLast || s->parts < 0 ||
+        s->parts > daqk::kMaxParts || (s->parts > 1 && s->variant != daqk::kVariantSplit))
         return DAQ_EINVAL;
     if (s->variant == daqk::kVariantStream && s->threads != daqk::kStreamThreads) return DAQ_EINVAL;
     if (s->variant == daqk::kVariantSplit && s->threads == 128) return DAQ_EINVAL;
@@ -718,7 +793,7 @@ int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, 
             const size_t bar = line.find('|');
             if (bar == std::string::npos || line.substr(0, bar) != key) continue;
             daq_schedule s{};
-            if (sscanf(line.c_str() + bar + 1, "%d %d %d", &s.threads, &s.wgs_per_cu, &s.variant) == 3 &&
+            if (sscanf(line.c_str() + bar + 1, "%d %d %d %d", &s.threads, &s.wgs_per_cu, &s.variant, &s.parts) == 4 &&
                 daq_ctx_set_schedule(ctx, &s) == DAQ_OK) {
                 if (best) *best = s;
                 return DAQ_OK;
@@ -729,11 +804,12 @@ int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, 
     const bool calo = all_calorimeters(fills, n);
     const int V0 = daqk::kVariantReload, V1 = daqk::kVariantResident, V2 = daqk::kVariantStream;
     const int V3 = daqk::kVariantReload18, V4 = daqk::kVariantReload27, V5 = daqk::kVariantSplit;
-    const daq_schedule menu[] = {{256, 16, V5, 0}, {256, 8, V5, 0}, {512, 4, V5, 0}, {256, 4, V0, 0},
-                                 {256, 8, V0, 0},  {512, 2, V0, 0}, {256, 2, V2, 0}, {256, 4, V3, 0},
-                                 {256, 3, V4, 0},  {128, 8, V0, 0}, {256, 1, V1, 0}};
+    const daq_schedule menu[] = {{256, 16, V5, 0}, {256, 16, V5, 2}, {256, 16, V5, 3}, {256, 16, V5, 4},
+                                 {256, 8, V5, 0},  {256, 8, V5, 2},  {512, 4, V5, 0},  {256, 4, V0, 0},
+                                 {256, 8, V0, 0},  {512, 2, V0, 0},  {256, 2, V2, 0},  {256, 4, V3, 0},
+                                 {256, 3, V4, 0},  {128, 8, V0, 0},  {256, 1, V1, 0}};
     for (const daq_schedule &m : menu)
-        if ((m.variant != V1 && m.variant != V2) || calo) cand.push_back(m);
+        if (((m.variant != V1 && m.variant != V2) || calo) && (m.parts <= 1 || n >= 2 * m.parts)) cand.push_back(m);
     const daq_schedule saved = ctx->sched;
     const bool saved_timing = ctx->timing;
     ctx->timing = true;
@@ -778,7 +854,7 @@ int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, 
     if (cache_path) {
         std::ofstream o(cache_path, std::ios::app);
         o << key << "|" << best_s.threads << " " << best_s.wgs_per_cu << " " << best_s.variant << " "
-          << best_ms << "\n";
+          << best_s.parts << " " << best_ms << "\n";
     }
     return DAQ_OK;
 }

@@ -22,9 +22,10 @@ import paper_1611_04959_amd as daq  # noqa: E402
 from gpu_util import (assert_same, dev, log, make_fill, oracle_many, oracle_result, pad_stride,  # noqa: E402
                       run)
 
-SCHEDULES = [(256, 2, 2), (256, 1, 2), (256, 0, 2), (256, 4, 0), (256, 1, 1), (512, 2, 0), (512, 1, 1),
-             (128, 8, 0), (128, 2, 1), (256, 0, 0), (512, 0, 1), (256, 4, 3), (512, 2, 3), (256, 3, 4),
-             (256, 8, 5), (512, 2, 5), (256, 0, 5)]
+SCHEDULES = [(256, 2, 2, 0), (256, 1, 2, 0), (256, 0, 2, 0), (256, 4, 0, 0), (256, 1, 1, 0), (512, 2, 0, 0),
+             (512, 1, 1, 0), (128, 8, 0, 0), (128, 2, 1, 0), (256, 0, 0, 0), (512, 0, 1, 0), (256, 4, 3, 0),
+             (512, 2, 3, 0), (256, 3, 4, 0), (256, 8, 5, 0), (512, 2, 5, 0), (256, 0, 5, 0), (256, 16, 5, 2),
+             (256, 16, 5, 3), (512, 4, 5, 4), (256, 0, 5, 2)]
 MODES = ["chop", "twopass", "batch"]
 
 
@@ -71,7 +72,7 @@ def _random_fill(rng, C, N):
     return pad_stride(x)
 
 
-@pytest.mark.parametrize("sched", SCHEDULES, ids=lambda s: "t%d_w%d_r%d" % s)
+@pytest.mark.parametrize("sched", SCHEDULES, ids=lambda s: "t%d_w%d_v%d_p%d" % s)
 def test_random_fills_all_schedules_and_modes(ctx, sched):
     ctx.set_schedule(*sched)
     rng = np.random.default_rng(sum(sched) * 7919)
@@ -116,10 +117,12 @@ def test_batch_of_uneven_random_fills(ctx):
     ctx.set_schedule(256, 2, 2)
 
 
-def test_graph_replays_match_eager(ctx):
+@pytest.mark.parametrize("sched", [(256, 2, 2, 0), (256, 16, 5, 0), (256, 16, 5, 3)],
+                         ids=lambda s: "t%d_w%d_v%d_p%d" % s)
+def test_graph_replays_match_eager(ctx, sched):
     """Replays of the captured graphs, with eager work and syncs between them."""
-    rng = np.random.default_rng(17)
-    ctx.set_schedule(256, 2, 2)
+    rng = np.random.default_rng(17 + sched[3])
+    ctx.set_schedule(*sched)
     for rep in range(4):
         n = int(rng.integers(2, 9))
         xs = [_random_fill(rng, 54, int(rng.integers(1000, 20_000))) for _ in range(n)]
