@@ -33,6 +33,8 @@ DAQ_EMISMATCH = -7
 DAQ_STATUS_CAPACITY = 1
 DAQ_STATUS_OUT_STRIDE = 2
 DAQ_MAX_WINDOW = 32768
+DAQ_MAX_SAMPLES = 0x7FFFFFFF
+DAQ_MAX_CHANNELS = 65535
 DAQ_VARIANT_RELOAD = 0
 DAQ_VARIANT_REGISTERS = 1
 DAQ_VARIANT_LDS = 2

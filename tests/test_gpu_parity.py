@@ -27,6 +27,7 @@ SCHEDULES = [(256, 2, 2, 0), (256, 1, 2, 0), (256, 0, 2, 0), (256, 4, 0, 0), (25
              (512, 2, 3, 0), (256, 3, 4, 0), (256, 8, 5, 0), (512, 2, 5, 0), (256, 0, 5, 0), (256, 16, 5, 2),
              (256, 16, 5, 3), (512, 4, 5, 4), (256, 0, 5, 2)]
 MODES = ["chop", "twopass", "batch"]
+DEFAULT = (256, 16, 5, 0)  # the library's default schedule
 
 
 @pytest.fixture(scope="module")
@@ -92,7 +93,7 @@ def test_random_fills_all_schedules_and_modes(ctx, sched):
                 o = daq.alloc_out(f)
                 run(ctx, mode, [f], [o])
                 assert_same(o, ref, ctx="C=%d N=%d pre=%d post=%d %s %s" % (C, N, pre, post, sched, mode))
-    ctx.set_schedule(256, 2, 2)
+    ctx.set_schedule(*DEFAULT)
 
 
 def test_batch_of_uneven_random_fills(ctx):
@@ -114,7 +115,7 @@ def test_batch_of_uneven_random_fills(ctx):
         run(ctx, "batch", fills, outs)
         for i, (o, r) in enumerate(zip(outs, refs)):
             assert_same(o, r, ctx="fill %d sched %s" % (i, sched))
-    ctx.set_schedule(256, 2, 2)
+    ctx.set_schedule(*DEFAULT)
 
 
 @pytest.mark.parametrize("sched", [(256, 2, 2, 0), (256, 16, 5, 0), (256, 16, 5, 3)],
@@ -269,13 +270,84 @@ def test_workload_plain_single_fill(ctx):
 
 
 def test_workload_16_fills_batched(ctx):
-    ctx.set_schedule(256, 2, 2)
-    refs = _workload(synth.config_c1(), "batch", ctx)
+    """The benchmark's launch: the 16 fills autotuned, then replayed from graphs."""
+    specs = synth.config_c1()
+    xs = synth.render_many(specs)
+    ns = [s.n_samples for s in specs]
+    ps = [params(s.threshold, s.pre, s.post, s.ped_samples) for s in specs]
+    refs = oracle_many(xs, ns, ps)
+    fills = [make_fill(d, n, p) for d, n, p in zip(synth.to_device(xs), ns, ps)]
+    outs = [daq.alloc_out(f) for f in fills]
+    best = ctx.daq_autotune(fills, outs)
+    log("autotuned: threads %d wgs %d variant %d parts %d" % (best.threads, best.wgs_per_cu, best.variant,
+                                                             best.parts))
+    ctx.set_graphs(True)
+    for rep in range(3):
+        for o in outs:
+            o.out.zero_()
+            o.islands.zero_()
+        run(ctx, "batch", fills, outs)
+        for i, (o, r) in enumerate(zip(outs, refs)):
+            assert_same(o, r, ctx="rep %d fill %d (seed %d)" % (rep, i, specs[i].seed))
     assert sum(r.n_islands for r in refs) > 10_000
+    ctx.set_schedule(*DEFAULT)
 
 
 def test_workload_16_fills_per_fill(ctx):
     _workload(synth.config_c1(), "chop", ctx)
+
+
+def test_max_channels(ctx):
+    """65535 channels (the largest count whose int16 sums stay exact in int32),
+    ragged length, values at both int16 extremes in places."""
+    rng = np.random.default_rng(65535)
+    C, N = daq.DAQ_MAX_CHANNELS, 1001
+    x = rng.integers(-5, 6, size=(C, N)).astype(np.int16)
+    x[:, 500:540] = -32768
+    x[:, 700:710] = 32767
+    x[rng.integers(0, C, 2000), rng.integers(0, N, 2000)] -= 3000
+    x = pad_stride(x)
+    S = x[:, :N].astype(np.int64).sum(0)
+    for thr in (int(np.quantile(S, 0.05)), -(2 ** 31) + 1, 2 ** 31 - 1):
+        p = params(thr, 3, 5, 20)
+        ref = oracle_result(x, N, p)
+        for mode in MODES:
+            log("max channels thr=%d mode=%s" % (thr, mode))
+            f = make_fill(dev(x), N, p)
+            o = daq.alloc_out(f)
+            run(ctx, mode, [f], [o])
+            assert_same(o, ref, ctx="C=65535 thr %d %s" % (thr, mode))
+
+
+def test_max_samples(ctx):
+    """One channel of 2^31 - 1 samples (the largest fill), with pulses at known
+    places near both ends and the middle; islands and packed samples are
+    checked against their closed form (windows [t - pre, t + post], clipped,
+    merged)."""
+    N = daq.DAQ_MAX_SAMPLES
+    stride = N + 1
+    x = torch.full((1, stride), 1000, dtype=torch.int16, device="cuda")
+    pulses = [0, 5, 1000, 1 << 30, N - 99, N - 1]
+    for t in pulses:
+        x[0, t] = 400
+    # pedestal of the first 1000 samples: (998 * 1000 + 2 * 400) / 1000 = 998.8 -> 999
+    p = params(-100, 8, 24, 1000)
+    expect = [(0, 30), (992, 1025), ((1 << 30) - 8, (1 << 30) + 25), (N - 107, N - 74), (N - 9, N)]
+    offs = np.cumsum([0] + [b - a for a, b in expect])
+    isl_ref = np.array([(a, b, o) for (a, b), o in zip(expect, offs[:-1])], np.int64)
+    out_ref = np.concatenate([np.where(np.isin(np.arange(a, b), pulses), 400, 1000) for a, b in expect])
+    for mode in MODES:
+        log("max samples N=%d mode=%s" % (N, mode))
+        f = daq.Fill(x, N, threshold=-100, pre=8, post=24, ped_samples=1000)
+        o = daq.alloc_out(f)
+        run(ctx, mode, [f], [o])
+        isl, n, total, status, ped, out = o.host()
+        assert (n, total, status) == (len(expect), int(offs[-1]), 0), mode
+        np.testing.assert_array_equal(ped, [999])
+        np.testing.assert_array_equal(isl, isl_ref)
+        np.testing.assert_array_equal(out[0], out_ref)
+        del o
+        torch.cuda.empty_cache()
 
 
 def test_workload_uneven_24_streams(ctx):
@@ -284,6 +356,7 @@ def test_workload_uneven_24_streams(ctx):
 
 def test_workload_detector_stress(ctx):
     # four whole-detector fills: 96 calorimeter units of 54 x 560,000
+    ctx.set_schedule(*DEFAULT)
     _workload(synth.config_c4(), "batch", ctx)
 
 
@@ -304,4 +377,4 @@ def test_autotune_candidates_agree(ctx, tmp_path):
     # the cached choice is reused
     best2 = ctx.daq_autotune(fills, outs, cache_path=str(tmp_path / "tune.txt"))
     assert (best2.threads, best2.wgs_per_cu, best2.variant) == (best.threads, best.wgs_per_cu, best.variant)
-    ctx.set_schedule(256, 2, 2)
+    ctx.set_schedule(*DEFAULT)
