@@ -1317,7 +1317,7 @@ __device__ __forceinline__ uint4 lds_read8(const uint32_t *base, int e) {
 }
 
 #ifndef DAQ_STAGE_WORDS
-#define DAQ_STAGE_WORDS 1792
+#define DAQ_STAGE_WORDS 2048
 #endif
 
 // How packed line j of a chunk is assembled from a staged channel row; the
@@ -1338,21 +1338,23 @@ struct LineDesc {
 // at the island that holds its first position) become an LDS run table, and
 // every packed line gets a descriptor saying where its samples sit in a
 // staged channel row. For a group of channels at a time, the aligned 16-byte
-// words holding the chunk's source samples are copied into LDS by direct
-// global-to-LDS loads (all in flight at once); each (channel, line) is then
-// read from LDS and written with one 16-byte store. Chunks whose words do
-// not fit (very many tiny islands) or whose rows have different line phases
-// read global memory directly (emit_lines).
+// words holding the chunk's source samples are staged in LDS (two buffers:
+// the next group's words are loaded while the current group is written);
+// each (channel, line) is then read from LDS and written with one 16-byte
+// store. Chunks whose words do not fit (very many tiny islands) or whose
+// rows have different line phases read global memory directly (emit_lines).
 template <int NT>
 __global__ void __launch_bounds__(NT) k_copy_pass(KArgs a) {
     constexpr int P = kCopyChunk;
     constexpr int SW = DAQ_STAGE_WORDS;
+    constexpr int HW = SW / 2;            // words of one of the two staging buffers
+    constexpr int KI = (HW + NT - 1) / NT;  // staging loads per thread and group
     __shared__ int32_t s_src[P + 2];
     __shared__ int32_t s_dst[P + 2];
     __shared__ int32_t s_wb[P + 3];
     __shared__ int32_t s_line[P / kVec + 2];
     __shared__ int4 s_desc[P / kVec + 2];
-    __shared__ int32_t s_wsrc[SW];
+    __shared__ int32_t s_wsrc[HW];
     __shared__ uint4 s_stage[SW + 1];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -1404,7 +1406,7 @@ __global__ void __launch_bounds__(NT) k_copy_pass(KArgs a) {
         const bool uniform = (fd.out_stride & 7) == 0;
         const int ph_all = line_phase(fd.out, q0);
         const int lines = uniform ? (ph_all + m + 7) >> 3 : (m + 14) >> 3;
-        const int CG = uniform ? (SW - NT) / W : 0;  // channels per staging round
+        const int CG = uniform ? HW / W : 0;  // channels per staging round
         if (CG < 1) {
             // direct path: run of each line's first sample, then emit_lines
             if (uniform)
@@ -1453,29 +1455,42 @@ __global__ void __launch_bounds__(NT) k_copy_pass(KArgs a) {
             s_desc[jj] = d;
         }
         lds_barrier();
-        const uint32_t *stage32 = reinterpret_cast<const uint32_t *>(s_stage);
-        for (int c0 = 0; c0 < fd.C; c0 += CG) {
-            const int CGn = fd.C - c0 < CG ? fd.C - c0 : CG;
-            const int n_it = CGn * W;
-            {
-                // words (cl, w) in order: slot i = cl * W + w
-                const int dq = NT / W, dr = NT - dq * W;
-                int cl = tid / W, w = tid - cl * W;
-                for (int it = 0; it * NT < n_it; it++) {
-                    const int16_t *src = fd.raw;  // slots past the group's words load a harmless word
-                    if (it * NT + tid < n_it)
-                        src = fd.raw + (int64_t)(c0 + cl) * fd.stride + (int64_t)s_wsrc[w] * kVec;
-                    __builtin_amdgcn_global_load_lds(src, (lds_void *)(s_stage + it * NT + wid * 64), 16, 0, 0);
-                    w += dr;
-                    cl += dq;
-                    if (w >= W) {
-                        w -= W;
-                        cl++;
-                    }
+        // channel groups of CG rows, double-buffered: group g + 1's words are
+        // loaded into registers while group g is written out from LDS
+        const int ngroups = (fd.C + CG - 1) / CG;
+        uint4 nxt[KI];
+        auto load_group = [&](int grp) {
+            const int c0 = grp * CG;
+            const int n_it = (fd.C - c0 < CG ? fd.C - c0 : CG) * W;
+            const int dq = NT / W, dr = NT - dq * W;
+            int cl = tid / W, w = tid - cl * W;  // word (cl, w) of the group is slot cl * W + w
+#pragma unroll
+            for (int it = 0; it < KI; it++) {
+                if (it * NT + tid < n_it)
+                    nxt[it] = load16(fd.raw + (int64_t)(c0 + cl) * fd.stride + (int64_t)s_wsrc[w] * kVec);
+                w += dr;
+                cl += dq;
+                if (w >= W) {
+                    w -= W;
+                    cl++;
                 }
             }
-            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's words are in LDS
-            lds_barrier();
+        };
+        auto store_group = [&](uint4 *buf, int grp) {
+            const int c0 = grp * CG;
+            const int n_it = (fd.C - c0 < CG ? fd.C - c0 : CG) * W;
+#pragma unroll
+            for (int it = 0; it < KI; it++)
+                if (it * NT + tid < n_it) buf[it * NT + tid] = nxt[it];
+        };
+        load_group(0);
+        store_group(s_stage, 0);
+        lds_barrier();
+        for (int grp = 0; grp < ngroups; grp++) {
+            if (grp + 1 < ngroups) load_group(grp + 1);
+            const int c0 = grp * CG;
+            const int CGn = fd.C - c0 < CG ? fd.C - c0 : CG;
+            const uint32_t *stage32 = reinterpret_cast<const uint32_t *>(s_stage + (grp & 1) * HW);
             {
                 const int items = CGn * lines;
                 const int dq = NT / lines, dr = NT - dq * lines;
@@ -1516,6 +1531,7 @@ __global__ void __launch_bounds__(NT) k_copy_pass(KArgs a) {
                     }
                 }
             }
+            if (grp + 1 < ngroups) store_group(s_stage + ((grp + 1) & 1) * HW, grp + 1);
             lds_barrier();
         }
     }
