@@ -141,7 +141,10 @@ hipError_t launch_chop(const KArgs &a, int threads, int variant, int grid, hipSt
 hipError_t launch_scan(const KArgs &a, int threads, int grid, hipStream_t s);
 hipError_t launch_emit(const KArgs &a, int threads, int grid, int prefix_blocks, hipStream_t s);
 // Most fill groups a split launch is cut into (one HIP stream each).
-constexpr int kMaxParts = 4;
+#ifndef DAQ_MAX_PARTS
+#define DAQ_MAX_PARTS 4
+#endif
+constexpr int kMaxParts = DAQ_MAX_PARTS;
 hipError_t launch_gather(const GatherArgs &g, int grid, hipStream_t s);
 
 }  // namespace daqk

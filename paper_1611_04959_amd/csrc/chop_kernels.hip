@@ -958,29 +958,50 @@ __device__ __forceinline__ void scan_pass_tile(const KArgs &a, const FillDev &fd
     chop_flags<NT, R>(fd, q, thr_eff, s_bits);
     const int Wn = (q.G + 7) >> 3;
     const uint64_t *words = reinterpret_cast<const uint64_t *>(s_bits);
-    if (wid == 0) {
-        uint32_t carry = 0;
-        for (int w0 = 0; w0 <= Wn; w0 += 64) {
-            const int w = w0 + lane;
-            const uint32_t c = (w <= Wn) ? (uint32_t)__popcll(words[w]) : 0u;
-            const uint32_t inc = wave_incl_scan_u32(c, lane);
-            if (w <= Wn) s_pc[w] = carry + inc - c;
-            carry += __shfl(inc, 63, 64);
+    // windows of at most 55 samples: the flags around a group fit one 64-bit
+    // word; wider ones go through popcount prefixes of the bitmap
+    const bool narrow = fd.pre + fd.post <= 54;
+    if (!narrow) {
+        if (wid == 0) {
+            uint32_t carry = 0;
+            for (int w0 = 0; w0 <= Wn; w0 += 64) {
+                const int w = w0 + lane;
+                const uint32_t c = (w <= Wn) ? (uint32_t)__popcll(words[w]) : 0u;
+                const uint32_t inc = wave_incl_scan_u32(c, lane);
+                if (w <= Wn) s_pc[w] = carry + inc - c;
+                carry += __shfl(inc, 63, 64);
+            }
         }
+        lds_barrier();
     }
-    lds_barrier();
-    // dilation (Table 2 pre/post row) of the owned samples p-1 .. p+8
+    // dilation (Table 2 pre/post row) of the owned samples p-1 .. p+8: sample
+    // t is marked when some flag lies in [t - post, t + pre]
     uint32_t m10 = 0;
     if (q.owner) {
         const int r0 = q.g * kVec;
-        uint32_t lo[10], hi[10];
-        prefix_bits10(words, s_pc, r0 - 1 - fd.post, lo);
-        prefix_bits10(words, s_pc, r0 + fd.pre, hi);
+        if (narrow) {
+            // bits r0 - 1 - post .. r0 + 62 - post of the bitmap (r0 - 1 - post >= 0)
+            const int x0 = r0 - 1 - fd.post;
+            const int w = x0 >> 6, b = x0 & 63;
+            const uint64_t w0 = words[w], w1 = words[w + 1];
+            const uint64_t win = b ? ((w0 >> b) | (w1 << (64 - b))) : w0;
+            const uint64_t span = (2ull << (fd.pre + fd.post)) - 1ull;  // pre + post + 1 ones
 #pragma unroll
-        for (int j = 0; j < 10; j++) {
-            const int64_t t = q.p + j - 1;
-            const bool in = (hi[j] != lo[j]) && t >= 0 && t < N;
-            m10 |= (in ? 1u : 0u) << j;
+            for (int j = 0; j < 10; j++) {
+                const int64_t t = q.p + j - 1;
+                const bool in = ((win >> j) & span) != 0 && t >= 0 && t < N;
+                m10 |= (in ? 1u : 0u) << j;
+            }
+        } else {
+            uint32_t lo[10], hi[10];
+            prefix_bits10(words, s_pc, r0 - 1 - fd.post, lo);
+            prefix_bits10(words, s_pc, r0 + fd.pre, hi);
+#pragma unroll
+            for (int j = 0; j < 10; j++) {
+                const int64_t t = q.p + j - 1;
+                const bool in = (hi[j] != lo[j]) && t >= 0 && t < N;
+                m10 |= (in ? 1u : 0u) << j;
+            }
         }
         // the owned samples' mask byte: t0 is a multiple of 8
         const int64_t byte = (q.t0 >> 3) + (q.g - fd.gl);
