@@ -44,6 +44,30 @@ def kernel_sha():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
+def ceiling():
+    """A plain HBM rate on this GPU for context: a 1 GiB device copy (read +
+    write bytes), by HIP events."""
+    import torch
+    n = 1 << 30
+    src = torch.ones(n // 2, dtype=torch.int16, device="cuda")
+    dst = torch.empty_like(src)
+    out = {}
+    for name, fn, nbytes in (("copy_gbs", lambda: dst.copy_(src), 2 * n),):
+        for _ in range(3):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(10):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        out[name] = round(nbytes * 10 / (a.elapsed_time(b) * 1e-3) / 1e9, 1)
+    del src, dst
+    torch.cuda.empty_cache()
+    out["what"] = "torch device copy of 1 GiB, read + write bytes"
+    return out
+
+
 def batch_bench(daq, synth, specs, what, steps=20, warmup=3):
     """One batched launch over `specs` (autotuned on that batch): raw GB/s,
     the chop pass's HIP-event time, and parity of the first fill."""
@@ -356,6 +380,10 @@ def main():
                            "p50_fill_ms": round(pct(lat, 50), 4), "p99_fill_ms": round(pct(lat, 99), 4)}
             log("plain %s: %.1f GB/s" % (mode, plain[mode]["gbs"]))
 
+    # ---- plain HBM rates for context ------------------------------------------------
+    ceil = ceiling()
+    log("ceiling: device copy %.0f GB/s" % ceil["copy_gbs"])
+
     # ---- the other batch shapes: uneven batch, whole-detector stress -----------------
     others = {}
     if not args.no_uneven:
@@ -417,6 +445,7 @@ def main():
         "occupancy": round(sum(tot) / (N * len(specs)), 4),
         "parity_fill0": parity,
         "roofline": roofline,
+        "hbm_ceiling": ceil,
         "other_batches": others,
         "serving": serving,
         "cpu_baseline": cpu,

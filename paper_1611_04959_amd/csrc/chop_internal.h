@@ -81,6 +81,7 @@ struct BatchHdr {
     int64_t copy_slots;  // split variant: n_fills x chunks of the longest fill
     int64_t pad2;
 };
+static_assert(sizeof(BatchHdr) % 16 == 0, "the descriptor table follows the header in one buffer");
 
 struct KArgs {
     const FillDev *table;  // device table of n_fills entries, or null: use `one`
