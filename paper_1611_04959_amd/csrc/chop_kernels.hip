@@ -471,6 +471,371 @@ __device__ __forceinline__ int32_t clamp_thr(int64_t te) {
     return (int32_t)(te > 2147483647LL ? 2147483647LL : (te < -2147483648LL ? -2147483648LL : te));
 }
 
+// ---- packed write-out from a run table ----------------------------------------------
+
+// Last run whose packed start is <= q (runs with equal starts: the later,
+// non-empty one).
+__device__ __forceinline__ int run_at(const int32_t *seg_dst, int nrun, int q) {
+    int lo = 0, hi = nrun - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg_dst[mid] <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Elements [0, split) of a, [split, 8) of b.
+__device__ __forceinline__ uint4 blend8(const uint4 a, const uint4 b, int split) {
+    auto m = [split](int k) -> uint32_t {
+        return (2 * k + 1 < split) ? 0xFFFFFFFFu : (2 * k < split ? 0x0000FFFFu : 0u);
+    };
+    const uint32_t m0 = m(0), m1 = m(1), m2 = m(2), m3 = m(3);
+    return make_uint4((a.x & m0) | (b.x & ~m0), (a.y & m1) | (b.y & ~m1), (a.z & m2) | (b.z & ~m2),
+                      (a.w & m3) | (b.w & ~m3));
+}
+
+// Chopped islands of one tile copied from the raw rows (emit pass). Run r
+// moves tile samples [src_r, ...) to packed positions [dst_r, dst_{r+1})
+// (tile-relative; the last run ends at tile_m). A work item is one 16-byte
+// line of one channel's packed row. A line inside one run, or across the
+// boundary of two runs, is read as aligned 16-byte words, realigned (and
+// blended) and written with one 16-byte store; lines at the tile's ends
+// (shared with the neighbouring tiles) or across three or more runs go
+// sample by sample. When every row has the same line phase (out_stride a
+// multiple of 8), line_run[j] holds the run of line j's first sample.
+template <int NT, int U>
+__device__ __forceinline__ void emit_lines(const int32_t *seg_src, const int32_t *seg_dst, const int32_t *line_run,
+                                           bool uniform, int ph_all, int lines, int nrun, int tile_m,
+                                           const int16_t *raw, int64_t stride, int64_t t0, int16_t *out,
+                                           int64_t ostride, int C, int64_t m0) {
+    const int items = C * lines;
+    const int dq = NT / lines, dr = NT - dq * lines;
+    int c = (int)threadIdx.x / lines, j = (int)threadIdx.x - c * lines;
+    auto step = [&]() {
+        j += dr;
+        c += dq;
+        if (j >= lines) {
+            j -= lines;
+            c++;
+        }
+    };
+    // the line's tile-relative packed range [lo, hi) and its position q0
+    auto span = [&](int cc, int jj, int &q0, int &lo, int &hi) {
+        const int ph = uniform ? ph_all : line_phase(out + (int64_t)cc * ostride, m0);
+        q0 = 8 * jj - ph;
+        lo = q0 > 0 ? q0 : 0;
+        hi = q0 + 8 < tile_m ? q0 + 8 : tile_m;
+        if (m0 + hi > ostride) hi = (int)(ostride - m0);
+    };
+    for (int i0 = threadIdx.x; i0 < items; i0 += NT * U) {
+        const int c_first = c, j_first = j;
+        uint4 A0[U], B0[U], A1[U], B1[U];
+        int meta[U];  // kind (0 none, 1 one run, 2 two runs, 3 sample by sample) | split << 2 | shifts
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            meta[u] = 0;
+            A0[u] = B0[u] = A1[u] = B1[u] = make_uint4(0, 0, 0, 0);
+            if (i0 + u * NT < items) {
+                int q0, lo, hi;
+                span(c, j, q0, lo, hi);
+                if (lo < hi) {
+                    // the samples go to packed positions lo .. hi - 1; v[e] below is position lo + e
+                    const int r0 = uniform ? line_run[j] : run_at(seg_dst, nrun, lo);
+                    const int end0 = (r0 + 1 < nrun) ? seg_dst[r0 + 1] : tile_m;
+                    const int16_t *row = raw + (int64_t)c * stride + t0;  // t0 is a multiple of 8
+                    const int s0 = seg_src[r0] + lo - seg_dst[r0];
+                    meta[u] = 3;
+                    if (end0 >= hi) {
+                        meta[u] = 1 | ((s0 & 7) << 6);
+                        A0[u] = load16(row + (s0 & ~7));
+                        if ((s0 & 7) + (hi - lo) > 8) B0[u] = load16(row + (s0 & ~7) + 8);
+                    } else {
+                        const int end1 = (r0 + 2 < nrun) ? seg_dst[r0 + 2] : tile_m;
+                        if (end1 >= hi) {
+                            // runs are separated by at least one sample: s1 >= s0 + 1 >= 1
+                            const int sp = end0 - lo;
+                            const int s1 = seg_src[r0 + 1] - sp;
+                            meta[u] = 2 | (sp << 2) | ((s0 & 7) << 6) | ((s1 & 7) << 9);
+                            A0[u] = load16(row + (s0 & ~7));
+                            if ((s0 & 7) + sp > 8) B0[u] = load16(row + (s0 & ~7) + 8);
+                            A1[u] = load16(row + (s1 & ~7));
+                            if ((s1 & 7) + (hi - lo) > 8) B1[u] = load16(row + (s1 & ~7) + 8);
+                        }
+                    }
+                }
+            }
+            step();
+        }
+        c = c_first;
+        j = j_first;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int kind = meta[u] & 3;
+            if (kind != 0) {
+                int q0, lo, hi;
+                span(c, j, q0, lo, hi);
+                int16_t *orow = out + (int64_t)c * ostride + m0;
+                if (kind == 3) {
+                    const int16_t *row = raw + (int64_t)c * stride + t0;
+                    int r = run_at(seg_dst, nrun, lo);
+                    for (int q = lo; q < hi; q++) {
+                        while (r + 1 < nrun && seg_dst[r + 1] <= q) r++;
+                        *gbl(orow + q) = *gbl(row + seg_src[r] + (q - seg_dst[r]));
+                    }
+                } else {
+                    uint4 v = realign8(A0[u], B0[u], (meta[u] >> 6) & 7);
+                    if (kind == 2) v = blend8(v, realign8(A1[u], B1[u], (meta[u] >> 9) & 7), (meta[u] >> 2) & 15);
+                    if (lo == q0 && hi == q0 + 8) {
+                        store16(orow + q0, v);
+                    } else {
+                        // a line shared with a neighbouring tile: this tile's samples only
+                        uint32_t w[4] = {v.x, v.y, v.z, v.w};
+                        for (int e = 0; e < hi - lo; e++)
+                            *gbl(orow + lo + e) = (int16_t)((w[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu);
+                    }
+                }
+            }
+            step();
+        }
+    }
+}
+
+#ifndef DAQ_EMIT_U
+#define DAQ_EMIT_U 4  // lines per thread with loads in flight
+#endif
+
+// Eight consecutive int16 elements of an LDS array, starting at element e
+// (any alignment): five 4-byte reads and, for odd e, byte alignment.
+__device__ __forceinline__ uint4 lds_read8(const uint32_t *base, int e) {
+    const uint32_t *d = base + (e >> 1);
+    const uint32_t w0 = d[0], w1 = d[1], w2 = d[2], w3 = d[3], w4 = d[4];
+    if (e & 1)
+        return make_uint4(__builtin_amdgcn_alignbyte(w1, w0, 2), __builtin_amdgcn_alignbyte(w2, w1, 2),
+                          __builtin_amdgcn_alignbyte(w3, w2, 2), __builtin_amdgcn_alignbyte(w4, w3, 2));
+    return make_uint4(w0, w1, w2, w3);
+}
+
+#ifndef DAQ_STAGE_WORDS
+#define DAQ_STAGE_WORDS 2048  // staged words of the copy pass (two buffers)
+#endif
+
+// Descriptor of packed line j (an int4, the same for every channel when all
+// rows share one line phase): x = staged element of the line's first sample
+// (run r0); y = kind 2: staged element holding line element 0 of run r0 + 1
+// (elements >= split are taken from there), kind 3: r0; z = lo | hi << 8
+// (the line's samples, relative to 8 j - phase); w = kind (0 none, 1 one run,
+// 2 two runs, 3 sample by sample) | split << 4 | full << 8.
+
+// LDS of one packed write-out: the run table (source sample, packed position
+// of every run, their staged-word prefix), per-line run and descriptor, the
+// source word of every staged word, and two staging buffers of HW words.
+template <int MAXRUNS, int MAXLINES, int HW_>
+struct CopyLayout {
+    static constexpr int kMaxRuns = MAXRUNS;
+    static constexpr int kMaxLines = MAXLINES;
+    static constexpr int kHW = HW_;
+    static constexpr int kSrc = 0;
+    static constexpr int kDst = kSrc + MAXRUNS * 4;
+    static constexpr int kWb = kDst + MAXRUNS * 4;
+    static constexpr int kLine = kWb + (MAXRUNS + 1) * 4;
+    static constexpr int kDesc = (kLine + MAXLINES * 4 + 15) / 16 * 16;
+    static constexpr int kWsrc = kDesc + MAXLINES * 16;
+    static constexpr int kStage = (kWsrc + HW_ * 4 + 15) / 16 * 16;
+    static constexpr int kBytes = kStage + (2 * HW_ + 1) * 16;
+};
+
+struct CopyView {
+    int32_t *src, *dst, *wb, *line;
+    int4 *desc;
+    int32_t *wsrc;
+    uint4 *stage;
+};
+
+template <class L>
+__device__ __forceinline__ CopyView copy_view(uint8_t *base) {
+    CopyView v;
+    v.src = reinterpret_cast<int32_t *>(base + L::kSrc);
+    v.dst = reinterpret_cast<int32_t *>(base + L::kDst);
+    v.wb = reinterpret_cast<int32_t *>(base + L::kWb);
+    v.line = reinterpret_cast<int32_t *>(base + L::kLine);
+    v.desc = reinterpret_cast<int4 *>(base + L::kDesc);
+    v.wsrc = reinterpret_cast<int32_t *>(base + L::kWsrc);
+    v.stage = reinterpret_cast<uint4 *>(base + L::kStage);
+    return v;
+}
+
+// Packed samples of every channel for positions [q0, q0 + m) of a fill from
+// a run table in LDS: run r moves source samples src[r] .. (absolute) to
+// packed positions dst[r] .. dst[r + 1] - 1 (relative to q0; the last run
+// ends at m); consecutive runs are separated by at least one sample. Every
+// packed line gets a descriptor saying where its samples sit in a staged
+// channel row. For a group of channels at a time, the aligned 16-byte words
+// holding the source samples are staged in LDS (two buffers: the next
+// group's words are loaded while the current group is written); each
+// (channel, line) is then read from LDS and written with one 16-byte store.
+// Words that do not fit (very many tiny islands), or rows with different
+// line phases, go through emit_lines, which reads global memory directly.
+// Called by every thread of the work-group with the run table in place;
+// ends with a barrier.
+template <int NT, class L, int FALLBACK_U = DAQ_EMIT_U>
+__device__ __forceinline__ void copy_runs(const FillDev &fd, const CopyView &v, int nrun, int m, int64_t q0) {
+    constexpr int HW = L::kHW;            // words of one of the two staging buffers
+    constexpr int KI = (HW + NT - 1) / NT;  // staging loads per thread and group
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    // staged words of each run: floor8(src) .. ceil8(src + len); their prefix
+    if (wid == 0) {
+        int carry = 0;
+        for (int r0 = 0; r0 < nrun; r0 += 64) {
+            const int r = r0 + lane;
+            int words = 0;
+            if (r < nrun) {
+                const int len = ((r + 1 < nrun) ? v.dst[r + 1] : m) - v.dst[r];
+                words = len > 0 ? ((v.src[r] + len + 7) >> 3) - (v.src[r] >> 3) : 0;
+            }
+            const uint32_t incl = wave_incl_scan_u32((uint32_t)words, lane);
+            if (r < nrun) v.wb[r] = carry + (int)incl - words;
+            carry += (int)__shfl(incl, 63, 64);
+        }
+        if (lane == 0) v.wb[nrun] = carry;
+    }
+    lds_barrier();
+    const int W = v.wb[nrun];
+    const bool uniform = (fd.out_stride & 7) == 0;
+    const int ph_all = line_phase(fd.out, q0);
+    const int lines = uniform ? (ph_all + m + 7) >> 3 : (m + 14) >> 3;
+    const int CG = uniform ? HW / W : 0;  // channels per staging round
+    if (CG < 1) {
+        // direct path: run of each line's first sample, then emit_lines
+        if (uniform)
+            for (int jj = tid; jj < lines; jj += NT) {
+                const int q = 8 * jj - ph_all;
+                v.line[jj] = run_at(v.dst, nrun, q > 0 ? q : 0);
+            }
+        lds_barrier();
+        emit_lines<NT, FALLBACK_U>(v.src, v.dst, v.line, uniform, ph_all, lines, nrun, m, fd.raw, fd.stride, 0,
+                                   fd.out, fd.out_stride, fd.C, q0);
+        lds_barrier();
+        return;
+    }
+    // source word of every staged word, and the descriptor of every line
+    for (int w = tid; w < W; w += NT) {
+        const int r = run_at(v.wb, nrun, w);
+        v.wsrc[w] = (v.src[r] >> 3) + (w - v.wb[r]);
+    }
+    for (int jj = tid; jj < lines; jj += NT) {
+        const int qa = 8 * jj - ph_all;
+        const int lo = qa > 0 ? qa : 0;
+        int hi = qa + 8 < m ? qa + 8 : m;
+        if (q0 + hi > fd.out_stride) hi = (int)(fd.out_stride - q0);
+        int4 d = make_int4(0, 0, 0, 0);
+        if (lo < hi) {
+            const int r0 = run_at(v.dst, nrun, lo);
+            const int end0 = (r0 + 1 < nrun) ? v.dst[r0 + 1] : m;
+            const int full = (lo == qa && hi == qa + 8) ? 1 : 0;
+            d.x = 8 * v.wb[r0] + (v.src[r0] & 7) + (lo - v.dst[r0]);
+            d.z = (lo - qa) | ((hi - qa) << 8);
+            if (end0 >= hi) {
+                d.w = 1 | (full << 8);
+            } else {
+                const int end1 = (r0 + 2 < nrun) ? v.dst[r0 + 2] : m;
+                const int sp = end0 - lo;
+                if (end1 >= hi) {
+                    // runs are separated by at least one sample, so this is >= 8 * wb + 1
+                    d.y = 8 * v.wb[r0 + 1] + (v.src[r0 + 1] & 7) - sp;
+                    d.w = 2 | (sp << 4) | (full << 8);
+                } else {
+                    d.y = r0;
+                    d.w = 3 | (full << 8);
+                }
+            }
+        }
+        v.desc[jj] = d;
+    }
+    lds_barrier();
+    // channel groups of CG rows, double-buffered: group g + 1's words are
+    // loaded into registers while group g is written out from LDS
+    const int ngroups = (fd.C + CG - 1) / CG;
+    uint4 nxt[KI];
+    auto load_group = [&](int grp) {
+        const int c0 = grp * CG;
+        const int n_it = (fd.C - c0 < CG ? fd.C - c0 : CG) * W;
+        const int dq = NT / W, dr = NT - dq * W;
+        int cl = tid / W, w = tid - cl * W;  // word (cl, w) of the group is slot cl * W + w
+#pragma unroll
+        for (int it = 0; it < KI; it++) {
+            if (it * NT + tid < n_it)
+                nxt[it] = load16(fd.raw + (int64_t)(c0 + cl) * fd.stride + (int64_t)v.wsrc[w] * kVec);
+            w += dr;
+            cl += dq;
+            if (w >= W) {
+                w -= W;
+                cl++;
+            }
+        }
+    };
+    auto store_group = [&](uint4 *buf, int grp) {
+        const int c0 = grp * CG;
+        const int n_it = (fd.C - c0 < CG ? fd.C - c0 : CG) * W;
+#pragma unroll
+        for (int it = 0; it < KI; it++)
+            if (it * NT + tid < n_it) buf[it * NT + tid] = nxt[it];
+    };
+    load_group(0);
+    store_group(v.stage, 0);
+    lds_barrier();
+    for (int grp = 0; grp < ngroups; grp++) {
+        if (grp + 1 < ngroups) load_group(grp + 1);
+        const int c0 = grp * CG;
+        const int CGn = fd.C - c0 < CG ? fd.C - c0 : CG;
+        const uint32_t *stage32 = reinterpret_cast<const uint32_t *>(v.stage + (grp & 1) * HW);
+        {
+            const int items = CGn * lines;
+            const int dq = NT / lines, dr = NT - dq * lines;
+            int cl = tid / lines, j = tid - cl * lines;
+            for (int i = tid; i < items; i += NT) {
+                const int4 d = v.desc[j];
+                const int kind = d.w & 15;
+                if (kind != 0) {
+                    const uint32_t *row = stage32 + cl * W * 4;
+                    int16_t *orow = fd.out + (int64_t)(c0 + cl) * fd.out_stride + q0 + 8 * j - ph_all;
+                    const int lo = d.z & 0xFF, hi = d.z >> 8;
+                    if (kind == 3) {
+                        int r = d.y;
+                        for (int e = lo; e < hi; e++) {
+                            const int q = 8 * j - ph_all + e;
+                            while (r + 1 < nrun && v.dst[r + 1] <= q) r++;
+                            const int el = 8 * v.wb[r] + (v.src[r] & 7) + (q - v.dst[r]);
+                            *gbl(orow + e) = reinterpret_cast<const int16_t *>(row)[el];
+                        }
+                    } else {
+                        uint4 v = lds_read8(row, d.x);
+                        if (kind == 2) v = blend8(v, lds_read8(row, d.y), (d.w >> 4) & 15);
+                        if (d.w & 256) {
+                            store16(orow, v);
+                        } else {
+                            // a line shared with a neighbouring chunk: this chunk's samples only
+                            const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+                            for (int e = lo; e < hi; e++)
+                                *gbl(orow + e) = (int16_t)((wv[(e - lo) >> 1] >> (((e - lo) & 1) * 16)) & 0xFFFFu);
+                        }
+                    }
+                }
+                j += dr;
+                cl += dq;
+                if (j >= lines) {
+                    j -= lines;
+                    cl++;
+                }
+            }
+        }
+        if (grp + 1 < ngroups) store_group(v.stage + ((grp + 1) & 1) * HW, grp + 1);
+        lds_barrier();
+    }
+}
+
 // ---- variant 0 / 1: rows read into registers ------------------------------------
 
 template <int NT>
@@ -481,7 +846,11 @@ struct ChopLds {
     static constexpr int kCB = NT <= 256 ? 8 : 4;            // channels staged per round
     static constexpr int kRowStride = NT * kVec + 16;        // elements per staged row
     static constexpr int kStageBytes = kCB * kRowStride * 2;
-    static constexpr int kBytes = kBitsBytes > kStageBytes ? kBitsBytes : kStageBytes;
+    // the re-read write-out: a run per rise of the tile plus the open run,
+    // lines of any phase, two staging buffers of 512 (1024 for 512 threads) words
+    using Copy = CopyLayout<NT * kVec / 2 + 2, NT + 3, NT <= 256 ? 512 : 1024>;
+    static constexpr int kMax2 = kBitsBytes > kStageBytes ? kBitsBytes : kStageBytes;
+    static constexpr int kBytes = kMax2 > Copy::kBytes ? kMax2 : Copy::kBytes;
 };
 
 // Geometry of a tile of NT groups of 8 samples (the halo groups included, or
@@ -553,40 +922,36 @@ __device__ __forceinline__ ReloadTile reload_front(const KArgs &a, const FillDev
 // Back half: prefix, records, totals and the chopped islands, whose raw
 // samples are read again and staged in LDS per CB channels so that global
 // stores are aligned 16-byte lines.
+// Back half of a re-read tile: the look-back, the island records and the
+// packed samples. The tile's runs (the island open at its first owned sample,
+// then one per rising edge) go into an LDS run table and copy_runs writes
+// them, reading the raw rows again (recently read, so mostly from cache).
 template <int NT>
 __device__ __forceinline__ void reload_back(const KArgs &a, const FillDev &fd, ReloadTile &t, uint8_t *lds,
                                             uint64_t *s_excl) {
-    constexpr int CB = ChopLds<NT>::kCB;
-    constexpr int RS = ChopLds<NT>::kRowStride;
     scan_back(a, fd, t.lt, t.r, s_excl);
     const TileScan &r = t.r;
     write_records(fd, r, t.p);
     write_counts(fd, t.lt, r);
     if (fd.out == nullptr || r.tile_m == 0) return;
-    int16_t *s_stage = reinterpret_cast<int16_t *>(lds);
-    int16_t *out = fd.out;
-    const int64_t ostride = fd.out_stride;
-    const int64_t m0 = r.m_before;
-    const uint32_t mm = r.mm;
-    const int C = fd.C;
-    for (int c0 = 0; c0 < C; c0 += CB) {
-        if (mm) {
-            uint4 v[CB];
+    using L = typename ChopLds<NT>::Copy;
+    const CopyView v = copy_view<L>(lds);
+    if (threadIdx.x == 0) {
+        v.src[0] = (int32_t)(t.lt * fd.tout);
+        v.dst[0] = 0;
+    }
+    if (r.rise) {
 #pragma unroll
-            for (int cl = 0; cl < CB; cl++)
-                if (c0 + cl < C) v[cl] = load16(fd.raw + t.p + (int64_t)(c0 + cl) * fd.stride);
-#pragma unroll
-            for (int cl = 0; cl < CB; cl++) {
-                if (c0 + cl < C) {
-                    const int ph = line_phase(out + (int64_t)(c0 + cl) * ostride, m0);
-                    stage_put(s_stage + cl * RS, ph + r.th_m, mm, v[cl]);
-                }
+        for (int k = 0; k < kVec; k++) {
+            if ((r.rise >> k) & 1u) {
+                const int j = 1 + r.th_i + __popc(r.rise & ((1u << k) - 1u));
+                v.src[j] = (int32_t)(t.p + k);
+                v.dst[j] = r.th_m + __popc(r.mm & ((1u << k) - 1u));
             }
         }
-        lds_barrier();
-        stage_flush<NT, CB>(s_stage, RS, out, ostride, c0, C, m0, r.tile_m);
-        lds_barrier();
     }
+    lds_barrier();
+    copy_runs<NT, L, 1>(fd, v, r.tile_i + 1, r.tile_m, r.m_before);
 }
 
 // A whole tile at once. RESIDENT keeps each thread's 54 channel chunks in
@@ -1102,137 +1467,6 @@ __global__ void __launch_bounds__(256) k_prefix_pass(KArgs a) {
     }
 }
 
-// Last run whose packed start is <= q (runs with equal starts: the later,
-// non-empty one).
-__device__ __forceinline__ int run_at(const int32_t *seg_dst, int nrun, int q) {
-    int lo = 0, hi = nrun - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (seg_dst[mid] <= q) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-// Elements [0, split) of a, [split, 8) of b.
-__device__ __forceinline__ uint4 blend8(const uint4 a, const uint4 b, int split) {
-    auto m = [split](int k) -> uint32_t {
-        return (2 * k + 1 < split) ? 0xFFFFFFFFu : (2 * k < split ? 0x0000FFFFu : 0u);
-    };
-    const uint32_t m0 = m(0), m1 = m(1), m2 = m(2), m3 = m(3);
-    return make_uint4((a.x & m0) | (b.x & ~m0), (a.y & m1) | (b.y & ~m1), (a.z & m2) | (b.z & ~m2),
-                      (a.w & m3) | (b.w & ~m3));
-}
-
-// Chopped islands of one tile copied from the raw rows (emit pass). Run r
-// moves tile samples [src_r, ...) to packed positions [dst_r, dst_{r+1})
-// (tile-relative; the last run ends at tile_m). A work item is one 16-byte
-// line of one channel's packed row. A line inside one run, or across the
-// boundary of two runs, is read as aligned 16-byte words, realigned (and
-// blended) and written with one 16-byte store; lines at the tile's ends
-// (shared with the neighbouring tiles) or across three or more runs go
-// sample by sample. When every row has the same line phase (out_stride a
-// multiple of 8), line_run[j] holds the run of line j's first sample.
-template <int NT, int U>
-__device__ __forceinline__ void emit_lines(const int32_t *seg_src, const int32_t *seg_dst, const int32_t *line_run,
-                                           bool uniform, int ph_all, int lines, int nrun, int tile_m,
-                                           const int16_t *raw, int64_t stride, int64_t t0, int16_t *out,
-                                           int64_t ostride, int C, int64_t m0) {
-    const int items = C * lines;
-    const int dq = NT / lines, dr = NT - dq * lines;
-    int c = (int)threadIdx.x / lines, j = (int)threadIdx.x - c * lines;
-    auto step = [&]() {
-        j += dr;
-        c += dq;
-        if (j >= lines) {
-            j -= lines;
-            c++;
-        }
-    };
-    // the line's tile-relative packed range [lo, hi) and its position q0
-    auto span = [&](int cc, int jj, int &q0, int &lo, int &hi) {
-        const int ph = uniform ? ph_all : line_phase(out + (int64_t)cc * ostride, m0);
-        q0 = 8 * jj - ph;
-        lo = q0 > 0 ? q0 : 0;
-        hi = q0 + 8 < tile_m ? q0 + 8 : tile_m;
-        if (m0 + hi > ostride) hi = (int)(ostride - m0);
-    };
-    for (int i0 = threadIdx.x; i0 < items; i0 += NT * U) {
-        const int c_first = c, j_first = j;
-        uint4 A0[U], B0[U], A1[U], B1[U];
-        int meta[U];  // kind (0 none, 1 one run, 2 two runs, 3 sample by sample) | split << 2 | shifts
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            meta[u] = 0;
-            A0[u] = B0[u] = A1[u] = B1[u] = make_uint4(0, 0, 0, 0);
-            if (i0 + u * NT < items) {
-                int q0, lo, hi;
-                span(c, j, q0, lo, hi);
-                if (lo < hi) {
-                    // the samples go to packed positions lo .. hi - 1; v[e] below is position lo + e
-                    const int r0 = uniform ? line_run[j] : run_at(seg_dst, nrun, lo);
-                    const int end0 = (r0 + 1 < nrun) ? seg_dst[r0 + 1] : tile_m;
-                    const int16_t *row = raw + (int64_t)c * stride + t0;  // t0 is a multiple of 8
-                    const int s0 = seg_src[r0] + lo - seg_dst[r0];
-                    meta[u] = 3;
-                    if (end0 >= hi) {
-                        meta[u] = 1 | ((s0 & 7) << 6);
-                        A0[u] = load16(row + (s0 & ~7));
-                        if ((s0 & 7) + (hi - lo) > 8) B0[u] = load16(row + (s0 & ~7) + 8);
-                    } else {
-                        const int end1 = (r0 + 2 < nrun) ? seg_dst[r0 + 2] : tile_m;
-                        if (end1 >= hi) {
-                            // runs are separated by at least one sample: s1 >= s0 + 1 >= 1
-                            const int sp = end0 - lo;
-                            const int s1 = seg_src[r0 + 1] - sp;
-                            meta[u] = 2 | (sp << 2) | ((s0 & 7) << 6) | ((s1 & 7) << 9);
-                            A0[u] = load16(row + (s0 & ~7));
-                            if ((s0 & 7) + sp > 8) B0[u] = load16(row + (s0 & ~7) + 8);
-                            A1[u] = load16(row + (s1 & ~7));
-                            if ((s1 & 7) + (hi - lo) > 8) B1[u] = load16(row + (s1 & ~7) + 8);
-                        }
-                    }
-                }
-            }
-            step();
-        }
-        c = c_first;
-        j = j_first;
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int kind = meta[u] & 3;
-            if (kind != 0) {
-                int q0, lo, hi;
-                span(c, j, q0, lo, hi);
-                int16_t *orow = out + (int64_t)c * ostride + m0;
-                if (kind == 3) {
-                    const int16_t *row = raw + (int64_t)c * stride + t0;
-                    int r = run_at(seg_dst, nrun, lo);
-                    for (int q = lo; q < hi; q++) {
-                        while (r + 1 < nrun && seg_dst[r + 1] <= q) r++;
-                        *gbl(orow + q) = *gbl(row + seg_src[r] + (q - seg_dst[r]));
-                    }
-                } else {
-                    uint4 v = realign8(A0[u], B0[u], (meta[u] >> 6) & 7);
-                    if (kind == 2) v = blend8(v, realign8(A1[u], B1[u], (meta[u] >> 9) & 7), (meta[u] >> 2) & 15);
-                    if (lo == q0 && hi == q0 + 8) {
-                        store16(orow + q0, v);
-                    } else {
-                        // a line shared with a neighbouring tile: this tile's samples only
-                        uint32_t w[4] = {v.x, v.y, v.z, v.w};
-                        for (int e = 0; e < hi - lo; e++)
-                            *gbl(orow + lo + e) = (int16_t)((w[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu);
-                    }
-                }
-            }
-            step();
-        }
-    }
-}
-
-#ifndef DAQ_EMIT_U
-#define DAQ_EMIT_U 4  // lines per thread with loads in flight
-#endif
 
 // Edge pass, one tile: island edges from the mask bits, the island records
 // (capacity-limited), the fill's run table (start, offset of every island)
@@ -1326,60 +1560,21 @@ __global__ void __launch_bounds__(NT) k_edge_pass(KArgs a) {
     }
 }
 
-// Eight consecutive int16 elements of an LDS array, starting at element e
-// (any alignment): five 4-byte reads and, for odd e, byte alignment.
-__device__ __forceinline__ uint4 lds_read8(const uint32_t *base, int e) {
-    const uint32_t *d = base + (e >> 1);
-    const uint32_t w0 = d[0], w1 = d[1], w2 = d[2], w3 = d[3], w4 = d[4];
-    if (e & 1)
-        return make_uint4(__builtin_amdgcn_alignbyte(w1, w0, 2), __builtin_amdgcn_alignbyte(w2, w1, 2),
-                          __builtin_amdgcn_alignbyte(w3, w2, 2), __builtin_amdgcn_alignbyte(w4, w3, 2));
-    return make_uint4(w0, w1, w2, w3);
-}
-
-#ifndef DAQ_STAGE_WORDS
-#define DAQ_STAGE_WORDS 2048
-#endif
-
-// How packed line j of a chunk is assembled from a staged channel row; the
-// same for every channel when all rows share one line phase.
-struct LineDesc {
-    int32_t off0;  // staged element of the line's first sample (run r0)
-    int32_t off1;  // kind 2: staged element holding line element 0 of run r0 + 1
-                   // (elements >= split are taken from there); kind 3: r0
-    int32_t span;  // lo | hi << 8 (tile-relative, minus 8 j - phase)
-    int32_t kind;  // 0 none, 1 one run, 2 two runs, 3 sample by sample | split << 4 | full << 8
-};
-
 // Copy pass: every fill's packed rows are cut into chunks of kCopyChunk
 // packed positions; a work-group copies one chunk of every channel, so each
 // has the same work whatever the island density where the chunk came from.
 // Slot g is chunk g / n of fill g % n of the launch's n fills (chunks past a
-// fill's total length are empty). The chunk's islands (from the run table, starting
-// at the island that holds its first position) become an LDS run table, and
-// every packed line gets a descriptor saying where its samples sit in a
-// staged channel row. For a group of channels at a time, the aligned 16-byte
-// words holding the chunk's source samples are staged in LDS (two buffers:
-// the next group's words are loaded while the current group is written);
-// each (channel, line) is then read from LDS and written with one 16-byte
-// store. Chunks whose words do not fit (very many tiny islands) or whose
-// rows have different line phases read global memory directly (emit_lines).
+// fill's total length are empty). The chunk's islands (from the run table,
+// starting at the island that holds its first position) become an LDS run
+// table, written out by copy_runs.
+using CopyPassLayout = CopyLayout<kCopyChunk + 2, kCopyChunk / kVec + 3, DAQ_STAGE_WORDS / 2>;
+
 template <int NT>
 __global__ void __launch_bounds__(NT) k_copy_pass(KArgs a) {
     constexpr int P = kCopyChunk;
-    constexpr int SW = DAQ_STAGE_WORDS;
-    constexpr int HW = SW / 2;            // words of one of the two staging buffers
-    constexpr int KI = (HW + NT - 1) / NT;  // staging loads per thread and group
-    __shared__ int32_t s_src[P + 2];
-    __shared__ int32_t s_dst[P + 2];
-    __shared__ int32_t s_wb[P + 3];
-    __shared__ int32_t s_line[P / kVec + 2];
-    __shared__ int4 s_desc[P / kVec + 2];
-    __shared__ int32_t s_wsrc[HW];
-    __shared__ uint4 s_stage[SW + 1];
+    __shared__ __align__(16) uint8_t s_lds[CopyPassLayout::kBytes];
+    const CopyView v = copy_view<CopyPassLayout>(s_lds);
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wid = tid >> 6;
     const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
     const int64_t all_slots = a.hdr ? a.hdr->copy_slots : a.copy_slots;
     const PartRange pr = part_range(a, nf, a.hdr ? a.hdr->total_tiles : a.total_tiles);
@@ -1402,159 +1597,11 @@ __global__ void __launch_bounds__(NT) k_copy_pass(KArgs a) {
             const int32_t st = *gbl(fd.runs + 2 * (int64_t)(i0 + r));
             const int32_t of = *gbl(fd.runs + 2 * (int64_t)(i0 + r) + 1);
             const int64_t d = (int64_t)of - q0;  // negative only for the first island
-            s_dst[r] = d > 0 ? (int32_t)d : 0;
-            s_src[r] = d > 0 ? st : (int32_t)(st - d);
+            v.dst[r] = d > 0 ? (int32_t)d : 0;
+            v.src[r] = d > 0 ? st : (int32_t)(st - d);
         }
         lds_barrier();
-        // staged words of each run: floor8(src) .. ceil8(src + len); their prefix
-        if (wid == 0) {
-            int carry = 0;
-            for (int r0 = 0; r0 < nrun; r0 += 64) {
-                const int r = r0 + lane;
-                int words = 0;
-                if (r < nrun) {
-                    const int len = ((r + 1 < nrun) ? s_dst[r + 1] : m) - s_dst[r];
-                    words = len > 0 ? ((s_src[r] + len + 7) >> 3) - (s_src[r] >> 3) : 0;
-                }
-                const uint32_t incl = wave_incl_scan_u32((uint32_t)words, lane);
-                if (r < nrun) s_wb[r] = carry + (int)incl - words;
-                carry += (int)__shfl(incl, 63, 64);
-            }
-            if (lane == 0) s_wb[nrun] = carry;
-        }
-        lds_barrier();
-        const int W = s_wb[nrun];
-        const bool uniform = (fd.out_stride & 7) == 0;
-        const int ph_all = line_phase(fd.out, q0);
-        const int lines = uniform ? (ph_all + m + 7) >> 3 : (m + 14) >> 3;
-        const int CG = uniform ? HW / W : 0;  // channels per staging round
-        if (CG < 1) {
-            // direct path: run of each line's first sample, then emit_lines
-            if (uniform)
-                for (int jj = tid; jj < lines; jj += NT) {
-                    const int q = 8 * jj - ph_all;
-                    s_line[jj] = run_at(s_dst, nrun, q > 0 ? q : 0);
-                }
-            lds_barrier();
-            emit_lines<NT, DAQ_EMIT_U>(s_src, s_dst, s_line, uniform, ph_all, lines, nrun, m, fd.raw, fd.stride, 0,
-                                       fd.out, fd.out_stride, fd.C, q0);
-            lds_barrier();
-            continue;
-        }
-        // source word of every staged word, and the descriptor of every line
-        for (int w = tid; w < W; w += NT) {
-            const int r = run_at(s_wb, nrun, w);
-            s_wsrc[w] = (s_src[r] >> 3) + (w - s_wb[r]);
-        }
-        for (int jj = tid; jj < lines; jj += NT) {
-            const int qa = 8 * jj - ph_all;
-            const int lo = qa > 0 ? qa : 0;
-            int hi = qa + 8 < m ? qa + 8 : m;
-            if (q0 + hi > fd.out_stride) hi = (int)(fd.out_stride - q0);
-            int4 d = make_int4(0, 0, 0, 0);
-            if (lo < hi) {
-                const int r0 = run_at(s_dst, nrun, lo);
-                const int end0 = (r0 + 1 < nrun) ? s_dst[r0 + 1] : m;
-                const int full = (lo == qa && hi == qa + 8) ? 1 : 0;
-                d.x = 8 * s_wb[r0] + (s_src[r0] & 7) + (lo - s_dst[r0]);
-                d.z = (lo - qa) | ((hi - qa) << 8);
-                if (end0 >= hi) {
-                    d.w = 1 | (full << 8);
-                } else {
-                    const int end1 = (r0 + 2 < nrun) ? s_dst[r0 + 2] : m;
-                    const int sp = end0 - lo;
-                    if (end1 >= hi) {
-                        // runs are separated by at least one sample, so this is >= 8 * wb + 1
-                        d.y = 8 * s_wb[r0 + 1] + (s_src[r0 + 1] & 7) - sp;
-                        d.w = 2 | (sp << 4) | (full << 8);
-                    } else {
-                        d.y = r0;
-                        d.w = 3 | (full << 8);
-                    }
-                }
-            }
-            s_desc[jj] = d;
-        }
-        lds_barrier();
-        // channel groups of CG rows, double-buffered: group g + 1's words are
-        // loaded into registers while group g is written out from LDS
-        const int ngroups = (fd.C + CG - 1) / CG;
-        uint4 nxt[KI];
-        auto load_group = [&](int grp) {
-            const int c0 = grp * CG;
-            const int n_it = (fd.C - c0 < CG ? fd.C - c0 : CG) * W;
-            const int dq = NT / W, dr = NT - dq * W;
-            int cl = tid / W, w = tid - cl * W;  // word (cl, w) of the group is slot cl * W + w
-#pragma unroll
-            for (int it = 0; it < KI; it++) {
-                if (it * NT + tid < n_it)
-                    nxt[it] = load16(fd.raw + (int64_t)(c0 + cl) * fd.stride + (int64_t)s_wsrc[w] * kVec);
-                w += dr;
-                cl += dq;
-                if (w >= W) {
-                    w -= W;
-                    cl++;
-                }
-            }
-        };
-        auto store_group = [&](uint4 *buf, int grp) {
-            const int c0 = grp * CG;
-            const int n_it = (fd.C - c0 < CG ? fd.C - c0 : CG) * W;
-#pragma unroll
-            for (int it = 0; it < KI; it++)
-                if (it * NT + tid < n_it) buf[it * NT + tid] = nxt[it];
-        };
-        load_group(0);
-        store_group(s_stage, 0);
-        lds_barrier();
-        for (int grp = 0; grp < ngroups; grp++) {
-            if (grp + 1 < ngroups) load_group(grp + 1);
-            const int c0 = grp * CG;
-            const int CGn = fd.C - c0 < CG ? fd.C - c0 : CG;
-            const uint32_t *stage32 = reinterpret_cast<const uint32_t *>(s_stage + (grp & 1) * HW);
-            {
-                const int items = CGn * lines;
-                const int dq = NT / lines, dr = NT - dq * lines;
-                int cl = tid / lines, j = tid - cl * lines;
-                for (int i = tid; i < items; i += NT) {
-                    const int4 d = s_desc[j];
-                    const int kind = d.w & 15;
-                    if (kind != 0) {
-                        const uint32_t *row = stage32 + cl * W * 4;
-                        int16_t *orow = fd.out + (int64_t)(c0 + cl) * fd.out_stride + q0 + 8 * j - ph_all;
-                        const int lo = d.z & 0xFF, hi = d.z >> 8;
-                        if (kind == 3) {
-                            int r = d.y;
-                            for (int e = lo; e < hi; e++) {
-                                const int q = 8 * j - ph_all + e;
-                                while (r + 1 < nrun && s_dst[r + 1] <= q) r++;
-                                const int el = 8 * s_wb[r] + (s_src[r] & 7) + (q - s_dst[r]);
-                                *gbl(orow + e) = reinterpret_cast<const int16_t *>(row)[el];
-                            }
-                        } else {
-                            uint4 v = lds_read8(row, d.x);
-                            if (kind == 2) v = blend8(v, lds_read8(row, d.y), (d.w >> 4) & 15);
-                            if (d.w & 256) {
-                                store16(orow, v);
-                            } else {
-                                // a line shared with a neighbouring chunk: this chunk's samples only
-                                const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
-                                for (int e = lo; e < hi; e++)
-                                    *gbl(orow + e) = (int16_t)((wv[(e - lo) >> 1] >> (((e - lo) & 1) * 16)) & 0xFFFFu);
-                            }
-                        }
-                    }
-                    j += dr;
-                    cl += dq;
-                    if (j >= lines) {
-                        j -= lines;
-                        cl++;
-                    }
-                }
-            }
-            if (grp + 1 < ngroups) store_group(s_stage + ((grp + 1) & 1) * HW, grp + 1);
-            lds_barrier();
-        }
+        copy_runs<NT, CopyPassLayout>(fd, v, nrun, m, q0);
     }
 }
 
