@@ -44,6 +44,17 @@ def kernel_sha():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
+def distinct_copies(xd, k):
+    """The device fills and k - 1 copies of each rotated along time by
+    different amounts (same statistics, distinct memory)."""
+    import torch
+    out = list(xd)
+    for v in range(1, k):
+        for x in xd:
+            out.append(torch.roll(x, shifts=v * 70_001, dims=1).contiguous())
+    return out
+
+
 def ceiling():
     """A plain HBM rate on this GPU for context: a 1 GiB device copy (read +
     write bytes), by HIP events."""
@@ -154,9 +165,14 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
     specs = [synth.config_c3_fill(s, 0) for s in range(n_streams_in)]
     log("serving: rendering %d stream fills" % len(specs))
     xs = synth.render_many(specs)
-    xd = synth.to_device(xs)
-    fills = [daq.Fill(d, sp.n_samples, threshold=sp.threshold, pre=sp.pre, post=sp.post,
-                      ped_samples=sp.ped_samples) for d, sp in zip(xd, specs)]
+    # a pool of distinct fills in HBM, far larger than what is in flight, so
+    # that no fill is read while its previous copy may still be cached: each
+    # rendered fill and seven copies rotated along time
+    xd = distinct_copies(synth.to_device(xs), 8)
+    sp0 = specs[0]
+    fills = [daq.Fill(d, sp0.n_samples, threshold=sp0.threshold, pre=sp0.pre, post=sp0.post,
+                      ped_samples=sp0.ped_samples) for d in xd]
+    n_pool = len(fills)
     raw = specs[0].raw_bytes
     arena = torch.empty(int(budget_gb * 1e9), dtype=torch.uint8, device="cuda")
     srv = daq.Server(ctx, arena, n_streams=n_streams, max_batch=max_batch)
@@ -174,11 +190,11 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
             now = time.monotonic_ns()
             if times is not None:
                 while i < len(times) and t0 + int(times[i] * 1e9) <= now:
-                    pending.append((t0 + int(times[i] * 1e9), i % n_streams_in))
+                    pending.append((t0 + int(times[i] * 1e9), i % n_pool))
                     i += 1
             else:
                 while now < end_ns and len(pending) + len(arr_ns) < depth:
-                    pending.append((now, n_off % n_streams_in))
+                    pending.append((now, n_off % n_pool))
                     n_off += 1
             while pending:
                 a_ns, st = pending[0]
@@ -307,6 +323,45 @@ def main():
     kern_ms = ctx.kernel_times_ms()
     ctx.set_timing(False)
 
+    # ---- pipelined: consecutive batches on two streams --------------------------------
+    # a second batch of 16 distinct fills (the same fills rotated along time)
+    # and a second context and stream: batch i + 1's scan overlaps batch i's
+    # later passes
+    log("pipelined: two batches alternating over two streams")
+    xd2 = distinct_copies(xd, 2)[len(xd):]
+    fills2 = [daq.Fill(d, s.n_samples, threshold=s.threshold, pre=s.pre, post=s.post,
+                       ped_samples=s.ped_samples) for d, s in zip(xd2, specs)]
+    outs2 = [daq.alloc_out(f) for f in fills2]
+    ctx2 = daq.Context(0)
+    stream2 = torch.cuda.Stream()
+    pipe = [(ctx, fills, outs, stream), (ctx2, fills2, outs2, stream2)]
+    pipelined = None
+    # overlapping batches want a smaller persistent grid: try the tuned one and 8 per CU
+    for cand in sorted({sched, (sched[0], 8, sched[2], sched[3])}):
+        ctx.set_schedule(*cand)
+        ctx2.set_schedule(*cand)
+        for i in range(4):
+            c, f, o, st = pipe[i % 2]
+            c.daq_process_batch(f, o, st)
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        for i in range(args.steps):
+            c, f, o, st = pipe[i % 2]
+            c.daq_process_batch(f, o, st)
+        torch.cuda.synchronize()
+        pipe_ms = (time.perf_counter() - tp0) * 1e3 / args.steps
+        if pipelined is None or pipe_ms < pipelined["ms_per_batch"]:
+            pipelined = {"streams": 2, "ms_per_batch": round(pipe_ms, 4),
+                         "gbs": round(raw_bytes / (pipe_ms * 1e-3) / 1e9, 1),
+                         "pct_hbm_peak": round(100 * raw_bytes / (pipe_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
+                         "schedule": {"threads": cand[0], "wgs_per_cu": cand[1], "variant": cand[2],
+                                      "parts": cand[3]},
+                         "what": "batches of the same 16-fill shape alternating over two HIP streams, each "
+                                 "batch on its own fills (distinct memory) and context"}
+    ctx.set_schedule(*sched)
+    ctx2.close()
+    del xd2, fills2, outs2
+
     # ---- results of the timed steps, checked against the oracle on a sample --
     counts = [o.counts.cpu().numpy() for o in outs]
     n_isl = [int(c[0]) for c in counts]
@@ -398,7 +453,11 @@ def main():
     # ---- serving loop: Poisson arrivals with bursts, HBM-budget admission -------------
     serving = None
     if args.serve_seconds > 0:
+        ps = pipelined["schedule"]
+        ctx.set_schedule(ps["threads"], ps["wgs_per_cu"], ps["variant"], ps["parts"])
         serving = serve_bench(daq, synth, ctx, args.serve_seconds)
+        serving["schedule"] = ps
+        ctx.set_schedule(*sched)
 
     # ---- CPU oracle on a bounded sample --------------------------------------------------
     cpu = None
@@ -440,6 +499,7 @@ def main():
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "batched": {"gbs": round(value, 1), "p50_fill_ms": round(pct(step_ms, 50), 4),
                     "p99_fill_ms": round(pct(step_ms, 99), 4)},
+        "pipelined": pipelined,
         "plain": plain,
         "islands_per_fill": round(float(np.mean(n_isl)), 1),
         "occupancy": round(sum(tot) / (N * len(specs)), 4),
