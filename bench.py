@@ -257,6 +257,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="serving loop at the nominal arrival rate (0 = skip)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch line")
+    ap.add_argument("--no-pipelined", action="store_true", help="skip the two-stream batched line")
     ap.add_argument("--stress", action="store_true",
                     help="also time the whole-detector stress batch (96 calorimeter fills, 5.8 GB)")
     args = ap.parse_args()
@@ -324,43 +325,45 @@ def main():
     ctx.set_timing(False)
 
     # ---- pipelined: consecutive batches on two streams --------------------------------
-    # a second batch of 16 distinct fills (the same fills rotated along time)
-    # and a second context and stream: batch i + 1's scan overlaps batch i's
-    # later passes
-    log("pipelined: two batches alternating over two streams")
-    xd2 = distinct_copies(xd, 2)[len(xd):]
-    fills2 = [daq.Fill(d, s.n_samples, threshold=s.threshold, pre=s.pre, post=s.post,
-                       ped_samples=s.ped_samples) for d, s in zip(xd2, specs)]
-    outs2 = [daq.alloc_out(f) for f in fills2]
-    ctx2 = daq.Context(0)
-    stream2 = torch.cuda.Stream()
-    pipe = [(ctx, fills, outs, stream), (ctx2, fills2, outs2, stream2)]
     pipelined = None
-    # overlapping batches want a smaller persistent grid: try the tuned one and 8 per CU
-    for cand in sorted({sched, (sched[0], 8, sched[2], sched[3])}):
-        ctx.set_schedule(*cand)
-        ctx2.set_schedule(*cand)
-        for i in range(4):
-            c, f, o, st = pipe[i % 2]
-            c.daq_process_batch(f, o, st)
-        torch.cuda.synchronize()
-        tp0 = time.perf_counter()
-        for i in range(args.steps):
-            c, f, o, st = pipe[i % 2]
-            c.daq_process_batch(f, o, st)
-        torch.cuda.synchronize()
-        pipe_ms = (time.perf_counter() - tp0) * 1e3 / args.steps
-        if pipelined is None or pipe_ms < pipelined["ms_per_batch"]:
-            pipelined = {"streams": 2, "ms_per_batch": round(pipe_ms, 4),
-                         "gbs": round(raw_bytes / (pipe_ms * 1e-3) / 1e9, 1),
-                         "pct_hbm_peak": round(100 * raw_bytes / (pipe_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
-                         "schedule": {"threads": cand[0], "wgs_per_cu": cand[1], "variant": cand[2],
-                                      "parts": cand[3]},
-                         "what": "batches of the same 16-fill shape alternating over two HIP streams, each "
-                                 "batch on its own fills (distinct memory) and context"}
-    ctx.set_schedule(*sched)
-    ctx2.close()
-    del xd2, fills2, outs2
+    if not args.no_pipelined:
+        # a second batch of 16 distinct fills (the same fills rotated along time)
+        # and a second context and stream: batch i + 1's scan overlaps batch i's
+        # later passes
+        log("pipelined: two batches alternating over two streams")
+        xd2 = distinct_copies(xd, 2)[len(xd):]
+        fills2 = [daq.Fill(d, s.n_samples, threshold=s.threshold, pre=s.pre, post=s.post,
+                           ped_samples=s.ped_samples) for d, s in zip(xd2, specs)]
+        outs2 = [daq.alloc_out(f) for f in fills2]
+        ctx2 = daq.Context(0)
+        stream2 = torch.cuda.Stream()
+        pipe = [(ctx, fills, outs, stream), (ctx2, fills2, outs2, stream2)]
+        pipelined = None
+        # overlapping batches want a smaller persistent grid: try the tuned one and 8 per CU
+        for cand in sorted({sched, (sched[0], 8, sched[2], sched[3])}):
+            ctx.set_schedule(*cand)
+            ctx2.set_schedule(*cand)
+            for i in range(4):
+                c, f, o, st = pipe[i % 2]
+                c.daq_process_batch(f, o, st)
+            torch.cuda.synchronize()
+            tp0 = time.perf_counter()
+            for i in range(args.steps):
+                c, f, o, st = pipe[i % 2]
+                c.daq_process_batch(f, o, st)
+            torch.cuda.synchronize()
+            pipe_ms = (time.perf_counter() - tp0) * 1e3 / args.steps
+            if pipelined is None or pipe_ms < pipelined["ms_per_batch"]:
+                pipelined = {"streams": 2, "ms_per_batch": round(pipe_ms, 4),
+                             "gbs": round(raw_bytes / (pipe_ms * 1e-3) / 1e9, 1),
+                             "pct_hbm_peak": round(100 * raw_bytes / (pipe_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
+                             "schedule": {"threads": cand[0], "wgs_per_cu": cand[1], "variant": cand[2],
+                                          "parts": cand[3]},
+                             "what": "batches of the same 16-fill shape alternating over two HIP streams, each "
+                                     "batch on its own fills (distinct memory) and context"}
+        ctx.set_schedule(*sched)
+        ctx2.close()
+        del xd2, fills2, outs2
 
     # ---- results of the timed steps, checked against the oracle on a sample --
     counts = [o.counts.cpu().numpy() for o in outs]
@@ -453,7 +456,8 @@ def main():
     # ---- serving loop: Poisson arrivals with bursts, HBM-budget admission -------------
     serving = None
     if args.serve_seconds > 0:
-        ps = pipelined["schedule"]
+        ps = pipelined["schedule"] if pipelined else {"threads": sched[0], "wgs_per_cu": sched[1],
+                                                      "variant": sched[2], "parts": sched[3]}
         ctx.set_schedule(ps["threads"], ps["wgs_per_cu"], ps["variant"], ps["parts"])
         serving = serve_bench(daq, synth, ctx, args.serve_seconds)
         serving["schedule"] = ps
