@@ -66,6 +66,10 @@ extern "C" {
                                    hold the true totals                       */
 #define DAQ_STATUS_OUT_STRIDE 2 /* total_len > out_stride: samples at packed
                                    positions >= out_stride were not written   */
+#define DAQ_STATUS_INCOMPLETE 4 /* DAQ_VARIANT_PIPE: a work-group gave up
+                                   waiting for other work-groups (a launch
+                                   that never drained); the fill's packed rows
+                                   are incomplete                             */
 
 /* ---- limits --------------------------------------------------------------- */
 #define DAQ_MAX_SAMPLES ((int64_t)0x7FFFFFFF) /* N per fill                    */
@@ -126,6 +130,11 @@ typedef struct daq_fill_out {
                                   island-mask bits and tile totals, a prefix
                                   pass, and an emit pass that copies only the
                                   island samples (threads = 256 or 512)       */
+#define DAQ_VARIANT_PIPE 6     /* one persistent kernel: work-groups take scan
+                                  tiles (each finds its islands and prefix at
+                                  once) and copy chunks of fills whose tiles
+                                  are all done, so a fill's copy overlaps the
+                                  scan of later fills (threads = 256 or 512) */
 typedef struct daq_schedule {
     int32_t threads;     /* work-group size: 128, 256 or 512                    */
     int32_t wgs_per_cu;  /* persistent grid = wgs_per_cu x CUs (1..16); 0 =

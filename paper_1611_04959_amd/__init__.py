@@ -32,6 +32,7 @@ DAQ_ERANGE = -6
 DAQ_EMISMATCH = -7
 DAQ_STATUS_CAPACITY = 1
 DAQ_STATUS_OUT_STRIDE = 2
+DAQ_STATUS_INCOMPLETE = 4
 DAQ_MAX_WINDOW = 32768
 DAQ_MAX_SAMPLES = 0x7FFFFFFF
 DAQ_MAX_CHANNELS = 65535
@@ -41,6 +42,7 @@ DAQ_VARIANT_LDS = 2
 DAQ_VARIANT_RELOAD18 = 3
 DAQ_VARIANT_RELOAD27 = 4
 DAQ_VARIANT_SPLIT = 5
+DAQ_VARIANT_PIPE = 6
 
 
 class daq_fill(ctypes.Structure):

@@ -23,7 +23,8 @@ constexpr int kVariantStream = 2;    // rows DMA'd into LDS; two work-groups per
 constexpr int kVariantReload18 = 3;  // as kVariantReload, 18 rows in flight per round (6 there)
 constexpr int kVariantReload27 = 4;  // as kVariantReload, 27 rows in flight per round
 constexpr int kVariantSplit = 5;     // scan pass (mask bits, tile totals), prefix pass, emit pass
-constexpr int kVariantLast = 5;
+constexpr int kVariantPipe = 6;      // one persistent kernel: scan tiles and copy chunks from shared counters
+constexpr int kVariantLast = 6;
 // Guard bytes around each fill's island-mask bits (read as zero past the ends).
 constexpr int kMaskGuard = 16;
 // Packed samples per channel row that one work-group of the copy pass writes.
@@ -90,9 +91,10 @@ struct KArgs {
     int32_t pad;
     int64_t total_tiles;
     uint64_t *tile_state;  // one look-back word per tile (split variant: tile totals)
-    uint32_t *ticket;      // tile dispenser
+    uint32_t *ticket;      // 16 words: tile dispenser; pipe variant: copy cursor, give-up flag
     int64_t *thr_eff;      // per fill: threshold + sum of pedestals
-    uint64_t *tile_pref;   // split variant: exclusive prefix of each tile
+    uint64_t *tile_pref;   // split variant: exclusive prefix of each tile; pipe variant:
+                           // finished tiles of each fill (one word per fill)
     int64_t copy_slots;    // split variant, when hdr is null
     int32_t part, parts;   // split variant: this launch covers fill group `part`
                            // of `parts` equal groups of the batch
@@ -141,6 +143,7 @@ hipError_t launch_chop(const KArgs &a, int threads, int variant, int grid, hipSt
 // the fill group a.part of a.parts.
 hipError_t launch_scan(const KArgs &a, int threads, int grid, hipStream_t s);
 hipError_t launch_emit(const KArgs &a, int threads, int grid, int prefix_blocks, hipStream_t s);
+hipError_t launch_pipe(const KArgs &a, int threads, int grid, hipStream_t s);
 // Most fill groups a split launch is cut into (one HIP stream each).
 #ifndef DAQ_MAX_PARTS
 #define DAQ_MAX_PARTS 4

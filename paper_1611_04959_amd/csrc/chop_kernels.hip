@@ -184,11 +184,17 @@ __device__ __forceinline__ void prefix_bits10(const uint64_t *words, const uint3
     }
 }
 
+// Polls of a bounded look-back before it gives up.
+constexpr uint32_t kLookBackSpins = 1u << 22;
+
 // Sum of the published values of this fill's tiles [0, lt): the exclusive
-// prefix of (island samples, islands). Executed by one whole wave.
-__device__ uint64_t look_back(uint64_t *st, int64_t lt, int lane) {
+// prefix of (island samples, islands). Executed by one whole wave. With
+// gave_up set the wait is bounded: past kLookBackSpins polls the flag is set
+// and the partial sum returned.
+__device__ uint64_t look_back(uint64_t *st, int64_t lt, int lane, uint32_t *gave_up = nullptr) {
     uint64_t acc = 0;
     int64_t hi = lt - 1;
+    uint32_t spins = 0;
     for (;;) {
         const int64_t j = hi - lane;
         uint64_t s = kFlagIncl;  // before the fill's first tile: empty prefix
@@ -199,6 +205,10 @@ __device__ uint64_t look_back(uint64_t *st, int64_t lt, int lane) {
         const uint64_t first = b_incl & (0ull - b_incl);         // lowest lane with a prefix
         const uint64_t need = b_incl ? (first | (first - 1ull)) : ~0ull;
         if (b_none & need) {  // a tile we depend on has not published yet
+            if (gave_up != nullptr && ++spins > kLookBackSpins) {
+                if (lane == 0) __hip_atomic_store(gave_up, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return acc;
+            }
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
@@ -317,51 +327,18 @@ struct TileScan {
     int64_t m_before, i_before;  // totals of the fill's earlier tiles
 };
 
-// Step 2 of a tile whose flag bitmap (G groups of 8 bits, zero padding up to
-// word Wn included) is in s_bits: popcount prefix, dilation of the calling
-// thread's group g (owners only; its first sample is p) and work-group scan.
-// Ends by publishing the tile's total (its inclusive prefix for a fill's
-// first tile); never waits for another tile.
+// Steps 2c and 3a of a tile, from the island-mask bits m10 of samples p - 1
+// .. p + 8 of the calling thread (zero for threads that own no samples):
+// island edges, work-group exclusive scan and tile totals, and the total
+// published at once (the inclusive prefix for a fill's first tile); never
+// waits for another tile.
 template <int NT>
-__device__ __forceinline__ TileScan scan_front(const KArgs &a, const FillDev &fd, int64_t lt, int G, int g,
-                                               bool owner, int64_t p, const uint8_t *s_bits, uint32_t *s_pc,
-                                               uint32_t *s_wsum) {
+__device__ __forceinline__ TileScan tile_totals(const KArgs &a, const FillDev &fd, int64_t lt, uint32_t m10,
+                                                uint32_t *s_wsum) {
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
-    const int64_t N = fd.n;
-    const int Wn = (G + 7) >> 3;
-
-    // 2a. exclusive popcount prefix over the bitmap words (wave 0)
-    const uint64_t *words = reinterpret_cast<const uint64_t *>(s_bits);
-    if (wid == 0) {
-        uint32_t carry = 0;
-        for (int w0 = 0; w0 <= Wn; w0 += 64) {
-            const int w = w0 + lane;
-            const uint32_t c = (w <= Wn) ? (uint32_t)__popcll(words[w]) : 0u;
-            const uint32_t inc = wave_incl_scan_u32(c, lane);
-            if (w <= Wn) s_pc[w] = carry + inc - c;
-            carry += __shfl(inc, 63, 64);
-        }
-    }
-    lds_barrier();
-
-    // 2b. dilation (Table 2 pre/post row): sample t is inside an island when
-    //     a flag lies in [t - post, t + pre]; masks for p-1 .. p+8
-    uint32_t m10 = 0;
-    if (owner) {
-        const int r0 = g * kVec;
-        uint32_t lo[10], hi[10];
-        prefix_bits10(words, s_pc, r0 - 1 - fd.post, lo);
-        prefix_bits10(words, s_pc, r0 + fd.pre, hi);
-#pragma unroll
-        for (int j = 0; j < 10; j++) {
-            const int64_t t = p + j - 1;
-            const bool in = (hi[j] != lo[j]) && t >= 0 && t < N;
-            m10 |= (in ? 1u : 0u) << j;
-        }
-    }
     TileScan r;
     r.mm = (m10 >> 1) & 0xFFu;
     r.rise = r.mm & ~(((r.mm << 1) | (m10 & 1u)) & 0xFFu);
@@ -397,10 +374,57 @@ __device__ __forceinline__ TileScan scan_front(const KArgs &a, const FillDev &fd
     return r;
 }
 
+// Step 2 of a tile whose flag bitmap (G groups of 8 bits, zero padding up to
+// word Wn included) is in s_bits: popcount prefix, dilation of the calling
+// thread's group g (owners only; its first sample is p) and work-group scan.
+// Ends by publishing the tile's total (its inclusive prefix for a fill's
+// first tile); never waits for another tile.
+template <int NT>
+__device__ __forceinline__ TileScan scan_front(const KArgs &a, const FillDev &fd, int64_t lt, int G, int g,
+                                               bool owner, int64_t p, const uint8_t *s_bits, uint32_t *s_pc,
+                                               uint32_t *s_wsum) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    const int64_t N = fd.n;
+    const int Wn = (G + 7) >> 3;
+
+    // 2a. exclusive popcount prefix over the bitmap words (wave 0)
+    const uint64_t *words = reinterpret_cast<const uint64_t *>(s_bits);
+    if (wid == 0) {
+        uint32_t carry = 0;
+        for (int w0 = 0; w0 <= Wn; w0 += 64) {
+            const int w = w0 + lane;
+            const uint32_t c = (w <= Wn) ? (uint32_t)__popcll(words[w]) : 0u;
+            const uint32_t inc = wave_incl_scan_u32(c, lane);
+            if (w <= Wn) s_pc[w] = carry + inc - c;
+            carry += __shfl(inc, 63, 64);
+        }
+    }
+    lds_barrier();
+
+    // 2b. dilation (Table 2 pre/post row): sample t is inside an island when
+    //     a flag lies in [t - post, t + pre]; masks for p-1 .. p+8
+    uint32_t m10 = 0;
+    if (owner) {
+        const int r0 = g * kVec;
+        uint32_t lo[10], hi[10];
+        prefix_bits10(words, s_pc, r0 - 1 - fd.post, lo);
+        prefix_bits10(words, s_pc, r0 + fd.pre, hi);
+#pragma unroll
+        for (int j = 0; j < 10; j++) {
+            const int64_t t = p + j - 1;
+            const bool in = (hi[j] != lo[j]) && t >= 0 && t < N;
+            m10 |= (in ? 1u : 0u) << j;
+        }
+    }
+    return tile_totals<NT>(a, fd, lt, m10, s_wsum);
+}
+
 // Step 3b: decoupled look-back over the fill's earlier tiles (wave 0), the
 // tile's inclusive prefix, and the prefix broadcast to the work-group.
 __device__ __forceinline__ void scan_back(const KArgs &a, const FillDev &fd, int64_t lt, TileScan &r,
-                                          uint64_t *s_excl) {
+                                          uint64_t *s_excl, uint32_t *gave_up = nullptr) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     if ((tid >> 6) == 0) {
@@ -408,7 +432,7 @@ __device__ __forceinline__ void scan_back(const KArgs &a, const FillDev &fd, int
         if (lt > 0) {
             uint64_t *st = a.tile_state + fd.tile_base;
             const uint64_t agg = ((uint64_t)r.tile_m << 31) | (uint64_t)r.tile_i;
-            ex = look_back(st, lt, lane);
+            ex = look_back(st, lt, lane, gave_up);
             if (lane == 0)
                 __hip_atomic_store(gbl(st + lt), kFlagIncl | (ex + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -454,6 +478,9 @@ __device__ __forceinline__ void write_records(const FillDev &fd, const TileScan 
 }
 
 // Step 5: totals, written by the fill's last tile (right after its scan).
+// COHERENT: device-scope stores that work-groups on any XCD can read in the
+// same launch.
+template <bool COHERENT = false>
 __device__ __forceinline__ void write_counts(const FillDev &fd, int64_t lt, const TileScan &r) {
     if (threadIdx.x != 0 || lt != fd.n_tiles - 1 || fd.counts == nullptr) return;
     const int64_t n_isl = r.i_before + r.tile_i;
@@ -461,10 +488,17 @@ __device__ __forceinline__ void write_counts(const FillDev &fd, int64_t lt, cons
     int32_t status = (n_isl > fd.cap) ? DAQ_STATUS_CAPACITY : 0;
     if (fd.out != nullptr && tl > fd.out_stride) status |= DAQ_STATUS_OUT_STRIDE;
     DAQ_GLOBAL daq_counts *cnt = gbl(fd.counts);
-    cnt->n_islands = n_isl;
-    cnt->total_len = tl;
-    cnt->status = status;
-    cnt->reserved = 0;
+    if constexpr (COHERENT) {
+        __hip_atomic_store(&cnt->n_islands, n_isl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&cnt->total_len, tl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&cnt->status, status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&cnt->reserved, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        cnt->n_islands = n_isl;
+        cnt->total_len = tl;
+        cnt->status = status;
+        cnt->reserved = 0;
+    }
 }
 
 __device__ __forceinline__ int32_t clamp_thr(int64_t te) {
@@ -1308,15 +1342,15 @@ __device__ __forceinline__ PartRange part_range(const KArgs &a, int nf, int64_t 
 #define DAQ_SCAN_ROWS 6  // channel rows each thread has in flight
 #endif
 
-// Scan pass, one tile: flags, dilation, mask bits, totals.
+// Flags and dilation of one tile (Table 2 threshold and pre/post rows): the
+// island-mask bits of samples p - 1 .. p + 8 of the calling thread (zero for
+// threads that own no samples).
 template <int NT, int R>
-__device__ __forceinline__ void scan_pass_tile(const KArgs &a, const FillDev &fd, int32_t thr_eff, int64_t tile,
-                                               uint8_t *lds, uint32_t *s_wsum) {
-    constexpr int NW = NT / 64;
+__device__ __forceinline__ uint32_t tile_mask10(const FillDev &fd, const ChopGeom<NT> &q, int32_t thr_eff,
+                                                uint8_t *lds) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
-    const ChopGeom<NT> q(fd, tile);
     const int64_t N = fd.n;
     uint8_t *s_bits = lds;
     uint32_t *s_pc = reinterpret_cast<uint32_t *>(lds + ChopLds<NT>::kWords * 8);
@@ -1339,8 +1373,7 @@ __device__ __forceinline__ void scan_pass_tile(const KArgs &a, const FillDev &fd
         }
         lds_barrier();
     }
-    // dilation (Table 2 pre/post row) of the owned samples p-1 .. p+8: sample
-    // t is marked when some flag lies in [t - post, t + pre]
+    // sample t is marked when some flag lies in [t - post, t + pre]
     uint32_t m10 = 0;
     if (q.owner) {
         const int r0 = q.g * kVec;
@@ -1368,6 +1401,21 @@ __device__ __forceinline__ void scan_pass_tile(const KArgs &a, const FillDev &fd
                 m10 |= (in ? 1u : 0u) << j;
             }
         }
+    }
+    return m10;
+}
+
+// Scan pass, one tile: flags, dilation, mask bits, totals.
+template <int NT, int R>
+__device__ __forceinline__ void scan_pass_tile(const KArgs &a, const FillDev &fd, int32_t thr_eff, int64_t tile,
+                                               uint8_t *lds, uint32_t *s_wsum) {
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    const ChopGeom<NT> q(fd, tile);
+    const uint32_t m10 = tile_mask10<NT, R>(fd, q, thr_eff, lds);
+    if (q.owner) {
         // the owned samples' mask byte: t0 is a multiple of 8
         const int64_t byte = (q.t0 >> 3) + (q.g - fd.gl);
         *gbl(fd.mbits + byte) = (uint8_t)((m10 >> 1) & 0xFFu);
@@ -1468,6 +1516,39 @@ __global__ void __launch_bounds__(256) k_prefix_pass(KArgs a) {
 }
 
 
+// The run table entries (start, packed offset) of the islands the calling
+// thread begins and, for the multiple k of kCopyChunk among its packed
+// positions (at most one), the island holding packed position k; the thread
+// owns samples p .. p + 7 with island mask r.mm and the prefixes of r.
+// COHERENT: device-scope stores (read by other work-groups of the launch).
+template <bool COHERENT = false>
+__device__ __forceinline__ void write_runs(const FillDev &fd, const TileScan &r, int64_t p) {
+    auto put = [](DAQ_GLOBAL int32_t *dst, int32_t v) {
+        if constexpr (COHERENT) __hip_atomic_store(dst, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else *dst = v;
+    };
+    if (fd.out == nullptr || r.mm == 0) return;
+    const int64_t mbase = r.m_before + r.th_m;
+    const int64_t ibase = r.i_before + r.th_i;
+    DAQ_GLOBAL int32_t *runs = gbl(fd.runs);
+#pragma unroll
+    for (int k = 0; k < kVec; k++) {
+        if ((r.rise >> k) & 1u) {
+            const int64_t idx = ibase + __popc(r.rise & ((1u << k) - 1u));
+            put(runs + 2 * idx, (int32_t)(p + k));
+            put(runs + 2 * idx + 1, (int32_t)(mbase + __popc(r.mm & ((1u << k) - 1u))));
+        }
+    }
+    const int64_t q = (mbase + kCopyChunk - 1) / kCopyChunk * kCopyChunk;
+    const int cnt = __popc(r.mm);
+    if (q < mbase + cnt) {
+        uint32_t bits = r.mm;
+        for (int64_t skip = q - mbase; skip > 0; skip--) bits &= bits - 1;  // drop the lowest set bits
+        const int b = __ffs(bits) - 1;
+        put(gbl(fd.cmap + q / kCopyChunk), (int32_t)(ibase + __popc(r.rise & ((2u << b) - 1u)) - 1));
+    }
+}
+
 // Edge pass, one tile: island edges from the mask bits, the island records
 // (capacity-limited), the fill's run table (start, offset of every island)
 // and, for every multiple k of kCopyChunk among the tile's packed positions,
@@ -1508,27 +1589,7 @@ __device__ __forceinline__ void edge_pass_tile(const KArgs &a, const FillDev &fd
     r.m_before = (int64_t)((pref >> 31) & kField);
     r.i_before = (int64_t)(pref & kField);
     write_records(fd, r, p);
-    if (fd.out == nullptr || mm == 0) return;
-    const int64_t mbase = r.m_before + r.th_m;
-    const int64_t ibase = r.i_before + r.th_i;
-    DAQ_GLOBAL int32_t *runs = gbl(fd.runs);
-#pragma unroll
-    for (int k = 0; k < kVec; k++) {
-        if ((r.rise >> k) & 1u) {
-            const int64_t idx = ibase + __popc(r.rise & ((1u << k) - 1u));
-            runs[2 * idx] = (int32_t)(p + k);
-            runs[2 * idx + 1] = (int32_t)(mbase + __popc(r.mm & ((1u << k) - 1u)));
-        }
-    }
-    // at most one multiple of the chunk size among this thread's packed positions
-    const int64_t q = (mbase + kCopyChunk - 1) / kCopyChunk * kCopyChunk;
-    const int cnt = __popc(mm);
-    if (q < mbase + cnt) {
-        uint32_t bits = mm;
-        for (int64_t skip = q - mbase; skip > 0; skip--) bits &= bits - 1;  // drop the lowest set bits
-        const int b = __ffs(bits) - 1;
-        *gbl(fd.cmap + q / kCopyChunk) = (int32_t)(ibase + __popc(r.rise & ((2u << b) - 1u)) - 1);
-    }
+    write_runs(fd, r, p);
 }
 
 template <int NT>
@@ -1569,12 +1630,55 @@ __global__ void __launch_bounds__(NT) k_edge_pass(KArgs a) {
 // table, written out by copy_runs.
 using CopyPassLayout = CopyLayout<kCopyChunk + 2, kCopyChunk / kVec + 3, DAQ_STAGE_WORDS / 2>;
 
+// The values a copy of chunk k needs besides the run table: the fill's
+// counts and the islands holding the chunk's first and last positions.
+struct ChunkInfo {
+    int64_t tl, n_isl;
+    int32_t i0, i1;
+};
+__device__ __forceinline__ ChunkInfo chunk_info(const FillDev &fd, int64_t k) {
+    ChunkInfo c;
+    c.tl = *gbl(&fd.counts->total_len);
+    c.n_isl = *gbl(&fd.counts->n_islands);
+    c.i0 = k * kCopyChunk < c.tl ? *gbl(fd.cmap + k) : 0;
+    c.i1 = (k + 1) * kCopyChunk < c.tl ? *gbl(fd.cmap + k + 1) : (int32_t)c.n_isl - 1;
+    return c;
+}
+
+// Chunk k of fill fd's packed rows (the fill's counts, run table and chunk
+// map complete; ci the same in every thread); L is a CopyLayout for
+// kCopyChunk + 1 runs. COHERENT: the run table is read with device-scope
+// loads (it was written in the same launch).
+template <int NT, class L, bool COHERENT = false, int U = DAQ_EMIT_U>
+__device__ __forceinline__ void copy_chunk(const FillDev &fd, int64_t k, const ChunkInfo &ci, const CopyView &v) {
+    constexpr int P = kCopyChunk;
+    const int tid = threadIdx.x;
+    const int64_t q0 = k * P;
+    if (q0 >= ci.tl) return;
+    const int m = (int)(ci.tl - q0 < P ? ci.tl - q0 : P);
+    const int nrun = ci.i1 - ci.i0 + 1;  // islands touching [q0, q0 + P], at most P + 1
+    for (int r = tid; r < nrun; r += NT) {
+        const DAQ_GLOBAL int32_t *e = gbl(fd.runs + 2 * (int64_t)(ci.i0 + r));
+        int32_t st, of;
+        if constexpr (COHERENT) {
+            st = __hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            of = __hip_atomic_load(e + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            st = e[0];
+            of = e[1];
+        }
+        const int64_t d = (int64_t)of - q0;  // negative only for the first island
+        v.dst[r] = d > 0 ? (int32_t)d : 0;
+        v.src[r] = d > 0 ? st : (int32_t)(st - d);
+    }
+    lds_barrier();
+    copy_runs<NT, L, U>(fd, v, nrun, m, q0);
+}
+
 template <int NT>
 __global__ void __launch_bounds__(NT) k_copy_pass(KArgs a) {
-    constexpr int P = kCopyChunk;
     __shared__ __align__(16) uint8_t s_lds[CopyPassLayout::kBytes];
     const CopyView v = copy_view<CopyPassLayout>(s_lds);
-    const int tid = threadIdx.x;
     const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
     const int64_t all_slots = a.hdr ? a.hdr->copy_slots : a.copy_slots;
     const PartRange pr = part_range(a, nf, a.hdr ? a.hdr->total_tiles : a.total_tiles);
@@ -1582,26 +1686,184 @@ __global__ void __launch_bounds__(NT) k_copy_pass(KArgs a) {
     const int64_t slots = nf > 0 ? all_slots / nf * nfp : 0;  // the part's fills x chunks of the longest fill
     for (int64_t g = blockIdx.x; g < slots; g += gridDim.x) {
         const int f = pr.lo + (int)(g % nfp);
-        const int64_t k = g / nfp;
         const FillDev fd = fill_at(a, f);
         if (fd.out == nullptr) continue;
-        const int64_t q0 = k * P;
-        const int64_t tl = __builtin_amdgcn_readfirstlane((int)*gbl(&fd.counts->total_len));
-        if (q0 >= tl) continue;
-        const int64_t n_isl = __builtin_amdgcn_readfirstlane((int)*gbl(&fd.counts->n_islands));
-        const int m = (int)(tl - q0 < P ? tl - q0 : P);
-        const int i0 = __builtin_amdgcn_readfirstlane(*gbl(fd.cmap + k));
-        const int i1 = q0 + P < tl ? __builtin_amdgcn_readfirstlane(*gbl(fd.cmap + k + 1)) : (int)n_isl - 1;
-        const int nrun = i1 - i0 + 1;  // islands touching [q0, q0 + P], at most P + 1
-        for (int r = tid; r < nrun; r += NT) {
-            const int32_t st = *gbl(fd.runs + 2 * (int64_t)(i0 + r));
-            const int32_t of = *gbl(fd.runs + 2 * (int64_t)(i0 + r) + 1);
-            const int64_t d = (int64_t)of - q0;  // negative only for the first island
-            v.dst[r] = d > 0 ? (int32_t)d : 0;
-            v.src[r] = d > 0 ? st : (int32_t)(st - d);
+        const int64_t k = g / nfp;
+        ChunkInfo ci = chunk_info(fd, k);
+        ci.tl = __builtin_amdgcn_readfirstlane((int)ci.tl);
+        ci.n_isl = __builtin_amdgcn_readfirstlane((int)ci.n_isl);
+        ci.i0 = __builtin_amdgcn_readfirstlane(ci.i0);
+        ci.i1 = __builtin_amdgcn_readfirstlane(ci.i1);
+        copy_chunk<NT, CopyPassLayout>(fd, k, ci, v);
+    }
+}
+
+// ---- variant 6: one persistent kernel, copies overlapped with the scan ----------
+//
+// Work-groups take two kinds of work from shared counters: scan tiles, in
+// batch order, and chunks of packed rows of fills whose every tile is done.
+// A scan tile streams its raw rows once, takes its exclusive prefix by the
+// decoupled look-back over its fill's earlier tiles and writes its island
+// records, run-table entries and chunk-map entries at once; the copy of a
+// finished fill then runs beside the scan of later fills, so the copy's
+// arithmetic fills the time the scan waits for memory. Chunks are taken
+// before scan tiles. No work-group waits for work that was handed out after
+// its own (a tile's look-back only for earlier tiles of its fill, which are
+// being scanned; an idle work-group for tiles being scanned), so the launch
+// always drains.
+//
+// Shared words: ticket[0] dispenses scan tiles; ticket[2] is the first fill
+// whose chunks may remain; ticket[4] is set when a work-group gave up
+// waiting. tile_pref[f] holds the finished tiles of fill f (low half) and
+// its chunks handed out (high half).
+
+#ifndef DAQ_PIPE_STAGE_WORDS
+#define DAQ_PIPE_STAGE_WORDS 1024  // staged source words of a copy (two buffers)
+#endif
+using PipeCopyLayout = CopyLayout<kCopyChunk + 2, kCopyChunk / kVec + 3, DAQ_PIPE_STAGE_WORDS / 2>;
+
+template <int NT>
+struct PipeLds {
+    static constexpr int kScan = ChopLds<NT>::kBitsBytes;
+    static constexpr int kBytes = kScan > PipeCopyLayout::kBytes ? kScan : PipeCopyLayout::kBytes;
+};
+
+constexpr int64_t kJobExit = -1;         // nothing left
+constexpr int64_t kJobCopy = -2;         // kJobCopy - (fill << 32 | chunk): a chunk to copy
+constexpr uint32_t kPipeSpins = 1u << 20;  // idle polls before a work-group gives up
+
+// The next work item of the calling work-group (thread 0 only): a chunk of a
+// finished fill (kJobCopy - (fill << 32 | chunk), with its ChunkInfo in
+// *ci), else a scan tile (>= 0), else, once every fill's chunks are handed
+// out, kJobExit. Chunks are claimed with one atomic add on the fill's word
+// (high half), so claims never retry. Waiting polls back off and are
+// bounded: past the limit the work-group marks the launch and the waited-for
+// fill as incomplete and leaves.
+__device__ int64_t pipe_next(const KArgs &a, int nf, int64_t total, ChunkInfo *ci) {
+    uint32_t *copy_fill = a.ticket + 2;  // first fill whose chunks may remain
+    uint32_t *gave_up = a.ticket + 4;
+    for (uint32_t spin = 0;; spin++) {
+        int f = (int)__hip_atomic_load(copy_fill, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while (f < nf) {
+            const FillDev fc = fill_at(a, f);
+            // the fill's counts, run table and chunk map were stored (device
+            // scope) before its tiles were counted; they are read with
+            // device-scope loads after the count is seen
+            const uint64_t w = __hip_atomic_load(a.tile_pref + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((int64_t)(uint32_t)w < fc.n_tiles) break;
+            int64_t tl = 0, nch = 0;
+            if (fc.out != nullptr && fc.counts != nullptr) {
+                tl = __hip_atomic_load(&fc.counts->total_len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                nch = (tl + kCopyChunk - 1) / kCopyChunk;
+            }
+            if ((int64_t)(w >> 32) < nch) {
+                const int64_t k = (int64_t)(__hip_atomic_fetch_add(a.tile_pref + f, (uint64_t)1 << 32, __ATOMIC_RELAXED,
+                                                                   __HIP_MEMORY_SCOPE_AGENT) >> 32);
+                if (k < nch) {
+                    const int64_t n_isl = __hip_atomic_load(&fc.counts->n_islands, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+                    ci->tl = tl;
+                    ci->n_isl = n_isl;
+                    ci->i0 = __hip_atomic_load(fc.cmap + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ci->i1 = (k + 1) * kCopyChunk < tl
+                                 ? __hip_atomic_load(fc.cmap + k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                 : (int32_t)n_isl - 1;
+                    return kJobCopy - (int64_t)(((uint64_t)f << 32) | (uint64_t)k);
+                }
+            }
+            // every chunk of fill f is handed out: move the shared pointer on
+            uint32_t expect = (uint32_t)f;
+            __hip_atomic_compare_exchange_strong(copy_fill, &expect, (uint32_t)(f + 1), __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            f++;
+        }
+        if (__hip_atomic_load(a.ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (uint64_t)total) {
+            const uint32_t t = atomicAdd(a.ticket, 1u);
+            if ((int64_t)t < total) return (int64_t)t;
+        }
+        if (f >= nf) return kJobExit;
+        if (__hip_atomic_load(gave_up, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || spin >= kPipeSpins) {
+            __hip_atomic_store(gave_up, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const FillDev fc = fill_at(a, f);
+            if (fc.counts != nullptr)
+                __hip_atomic_fetch_or(&fc.counts->status, DAQ_STATUS_INCOMPLETE, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+            return kJobExit;
+        }
+        // idle: poll rarely, the shared words sit on one memory channel
+        if (spin < 4) __builtin_amdgcn_s_sleep(16);
+        else __builtin_amdgcn_s_sleep(127);
+    }
+}
+
+// One scan tile of the persistent kernel: flags, dilation, totals (published
+// at once), look-back, records, counts (the fill's last tile), run table and
+// chunk map; then the tile is counted as finished.
+template <int NT, int R>
+__device__ __forceinline__ void pipe_tile(const KArgs &a, const FillDev &fd, int f, int32_t thr_eff, int64_t tile,
+                                          uint8_t *lds, uint32_t *s_wsum, uint64_t *s_excl) {
+    const ChopGeom<NT> q(fd, tile);
+    const uint32_t m10 = tile_mask10<NT, R>(fd, q, thr_eff, lds);
+    TileScan r = tile_totals<NT>(a, fd, q.lt, m10, s_wsum);
+    scan_back(a, fd, q.lt, r, s_excl, a.ticket + 4);
+    write_records(fd, r, q.p);
+    write_counts<true>(fd, q.lt, r);
+    write_runs<true>(fd, r, q.p);
+    if (threadIdx.x == 0 && fd.counts != nullptr &&
+        __hip_atomic_load(a.ticket + 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+        __hip_atomic_fetch_or(&fd.counts->status, DAQ_STATUS_INCOMPLETE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the counts, run table and chunk map go out as device-scope stores; each
+    // wave waits until its stores are done before the tile is counted (no
+    // cache write-back is needed for them)
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    lds_barrier();
+    if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(a.tile_pref + f, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int NT, int R>
+__global__ void __launch_bounds__(NT) k_pipe(KArgs a) {
+    __shared__ __align__(16) uint8_t s_lds[PipeLds<NT>::kBytes];
+    __shared__ uint32_t s_wsum[NT / 64];
+    __shared__ uint64_t s_excl;
+    __shared__ int64_t s_job;
+    __shared__ ChunkInfo s_ci;
+    __shared__ int64_t s_base[kLdsFills];
+    const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
+    const int64_t total = a.hdr ? a.hdr->total_tiles : a.total_tiles;
+    const bool lds_fills = nf <= kLdsFills;
+    if (lds_fills)
+        for (int i = threadIdx.x; i < nf; i += NT) s_base[i] = tile_base_at(a, i);
+    FillDev fd{};
+    int cur = -1;
+    int32_t thr_eff = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_job = pipe_next(a, nf, total, &s_ci);
+        lds_barrier();
+        const int64_t job = s_job;
+        if (job == kJobExit) break;
+        if (job >= 0) {
+            if (cur < 0 || job < fd.tile_base || job >= fd.tile_base + fd.n_tiles) {
+                int lo = 0, hi = nf - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if ((lds_fills ? s_base[mid] : tile_base_at(a, mid)) <= job) lo = mid;
+                    else hi = mid - 1;
+                }
+                fd = fill_at(a, lo);
+                thr_eff = clamp_thr(*gbl(a.thr_eff + lo));
+                cur = lo;
+            }
+            pipe_tile<NT, R>(a, fd, cur, thr_eff, job, s_lds, s_wsum, &s_excl);
+        } else {
+            const uint64_t id = (uint64_t)(kJobCopy - job);
+            const FillDev fc = fill_at(a, (int)(id >> 32));
+            const ChunkInfo ci = s_ci;
+            copy_chunk<NT, PipeCopyLayout, true>(fc, (int64_t)(uint32_t)id, ci, copy_view<PipeCopyLayout>(s_lds));
         }
         lds_barrier();
-        copy_runs<NT, CopyPassLayout>(fd, v, nrun, m, q0);
     }
 }
 
@@ -1616,7 +1878,7 @@ __global__ void __launch_bounds__(256) k_prepare(KArgs a) {
     const int64_t total = a.hdr ? a.hdr->total_tiles : a.total_tiles;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256)
         a.tile_state[i] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *a.ticket = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 8) a.ticket[threadIdx.x] = 0;  // dispenser, copy cursor, flags
     for (int f = blockIdx.x; f < nf; f += gridDim.x) {
         const FillDev fd = fill_at(a, f);
         const int64_t n = fd.n < (int64_t)fd.np ? fd.n : (int64_t)fd.np;
@@ -1654,6 +1916,7 @@ __global__ void __launch_bounds__(256) k_prepare(KArgs a) {
         }
         if (threadIdx.x == 0) {
             a.thr_eff[f] = (int64_t)fd.thr + (int64_t)s_ped;
+            if (a.tile_pref) a.tile_pref[f] = 0;  // finished tiles (pipe variant)
             if (fd.counts) {
                 fd.counts->n_islands = 0;
                 fd.counts->total_len = 0;
@@ -1760,6 +2023,13 @@ hipError_t launch_emit(const KArgs &a, int threads, int grid, int prefix_blocks,
     } else {
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_pipe(const KArgs &a, int threads, int grid, hipStream_t s) {
+    if (threads == 256) hipLaunchKernelGGL((k_pipe<256, DAQ_SCAN_ROWS>), dim3(grid), dim3(256), 0, s, a);
+    else if (threads == 512) hipLaunchKernelGGL((k_pipe<512, DAQ_SCAN_ROWS>), dim3(grid), dim3(512), 0, s, a);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -332,6 +332,10 @@ int ensure_parts(Scratch *sc, int parts) {
 
 int launch_main(const daq_ctx *ctx, Scratch *sc, const KArgs &a, const daq_schedule &s, int grid,
                 hipStream_t stream) {
+    if (s.variant == daqk::kVariantPipe) {
+        HIP_TRY(daqk::launch_pipe(a, s.threads, grid, stream));
+        return DAQ_OK;
+    }
     if (s.variant == daqk::kVariantSplit) {
         const int pb = std::max(1, std::min(a.hdr ? kPrefixBlocks : a.n_fills, kPrefixBlocks));
         const int parts = (a.table && s.parts > 1) ? std::min(s.parts, daqk::kMaxParts) : 1;
@@ -461,7 +465,8 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     int64_t total = 0, mask_total = 0, max_chunks = 0;
     std::vector<int64_t> base((size_t)n), moff((size_t)n, -1);
     std::vector<SplitLayout> lay((size_t)n);
-    const bool split = sc.variant == daqk::kVariantSplit;
+    // the pipe variant uses the split variant's run table and chunk map
+    const bool split = sc.variant == daqk::kVariantSplit || sc.variant == daqk::kVariantPipe;
     for (int32_t i = 0; i < n; i++) {
         base[(size_t)i] = total;
         total += tiles_of(fills[i], sc);
@@ -474,7 +479,8 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
         }
     }
     Scratch *s = scratch_for(ctx, stream);
-    int rc = ensure_scratch(s, total, n, mask_total);
+    // tile words double as per-fill words (pipe variant): at least one per fill
+    int rc = ensure_scratch(s, std::max<int64_t>(total, n), n, mask_total);
     if (rc) return rc;
     auto desc = [&](int32_t i) {
         FillDev d = make_desc(fills[i], outs[i], base[(size_t)i], sc);
@@ -738,7 +744,8 @@ int daq_ctx_set_schedule(daq_ctx *ctx, const daq_schedule *s) {
         s->parts > daqk::kMaxParts || (s->parts > 1 && s->variant != daqk::kVariantSplit))
         return DAQ_EINVAL;
     if (s->variant == daqk::kVariantStream && s->threads != daqk::kStreamThreads) return DAQ_EINVAL;
-    if (s->variant == daqk::kVariantSplit && s->threads == 128) return DAQ_EINVAL;
+    if ((s->variant == daqk::kVariantSplit || s->variant == daqk::kVariantPipe) && s->threads == 128)
+        return DAQ_EINVAL;
     ctx->sched = *s;
     return DAQ_OK;
 }
@@ -810,7 +817,9 @@ int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, 
     const bool calo = all_calorimeters(fills, n);
     const int V0 = daqk::kVariantReload, V1 = daqk::kVariantResident, V2 = daqk::kVariantStream;
     const int V3 = daqk::kVariantReload18, V4 = daqk::kVariantReload27, V5 = daqk::kVariantSplit;
-    const daq_schedule menu[] = {{256, 16, V5, 0}, {256, 16, V5, 2}, {256, 16, V5, 3}, {256, 16, V5, 4},
+    const int V6 = daqk::kVariantPipe;
+    const daq_schedule menu[] = {{512, 2, V6, 0},
+                                 {256, 16, V5, 0}, {256, 16, V5, 2}, {256, 16, V5, 3}, {256, 16, V5, 4},
                                  {256, 8, V5, 0},  {256, 8, V5, 2},  {512, 4, V5, 0},  {256, 4, V0, 0},
                                  {256, 8, V0, 0},  {512, 2, V0, 0},  {256, 2, V2, 0},  {256, 4, V3, 0},
                                  {256, 3, V4, 0},  {128, 8, V0, 0},  {256, 1, V1, 0}};

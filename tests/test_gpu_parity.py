@@ -25,7 +25,8 @@ from gpu_util import (assert_same, dev, log, make_fill, oracle_many, oracle_resu
 SCHEDULES = [(256, 2, 2, 0), (256, 1, 2, 0), (256, 0, 2, 0), (256, 4, 0, 0), (256, 1, 1, 0), (512, 2, 0, 0),
              (512, 1, 1, 0), (128, 8, 0, 0), (128, 2, 1, 0), (256, 0, 0, 0), (512, 0, 1, 0), (256, 4, 3, 0),
              (512, 2, 3, 0), (256, 3, 4, 0), (256, 8, 5, 0), (512, 2, 5, 0), (256, 0, 5, 0), (256, 16, 5, 2),
-             (256, 16, 5, 3), (512, 4, 5, 4), (256, 0, 5, 2)]
+             (256, 16, 5, 3), (512, 4, 5, 4), (256, 0, 5, 2), (256, 4, 6, 0), (512, 2, 6, 0), (256, 0, 6, 0),
+             (256, 1, 6, 0)]
 MODES = ["chop", "twopass", "batch"]
 DEFAULT = (256, 16, 5, 0)  # the library's default schedule
 
@@ -118,7 +119,7 @@ def test_batch_of_uneven_random_fills(ctx):
     ctx.set_schedule(*DEFAULT)
 
 
-@pytest.mark.parametrize("sched", [(256, 2, 2, 0), (256, 16, 5, 0), (256, 16, 5, 3)],
+@pytest.mark.parametrize("sched", [(256, 2, 2, 0), (256, 16, 5, 0), (256, 16, 5, 3), (256, 4, 6, 0)],
                          ids=lambda s: "t%d_w%d_v%d_p%d" % s)
 def test_graph_replays_match_eager(ctx, sched):
     """Replays of the captured graphs, with eager work and syncs between them."""
@@ -293,6 +294,30 @@ def test_workload_16_fills_batched(ctx):
     ctx.set_schedule(*DEFAULT)
 
 
+@pytest.mark.parametrize("sched", [(256, 4, 6, 0), (256, 8, 6, 0), (512, 2, 6, 0)],
+                         ids=lambda s: "t%d_w%d_v%d_p%d" % s)
+def test_workload_16_fills_pipe(ctx, sched):
+    """The 16-fill launch through the persistent scan-and-copy kernel, graphs replayed."""
+    specs = synth.config_c1()
+    xs = synth.render_many(specs)
+    ns = [s.n_samples for s in specs]
+    ps = [params(s.threshold, s.pre, s.post, s.ped_samples) for s in specs]
+    refs = oracle_many(xs, ns, ps)
+    fills = [make_fill(d, n, p) for d, n, p in zip(synth.to_device(xs), ns, ps)]
+    outs = [daq.alloc_out(f) for f in fills]
+    ctx.set_schedule(*sched)
+    ctx.set_graphs(True)
+    for rep in range(3):
+        for o in outs:
+            o.out.zero_()
+            o.islands.zero_()
+        log("pipe 16 fills sched=%s rep=%d" % (sched, rep))
+        run(ctx, "batch", fills, outs)
+        for i, (o, r) in enumerate(zip(outs, refs)):
+            assert_same(o, r, ctx="rep %d fill %d sched %s" % (rep, i, sched))
+    ctx.set_schedule(*DEFAULT)
+
+
 def test_workload_16_fills_per_fill(ctx):
     _workload(synth.config_c1(), "chop", ctx)
 
@@ -354,10 +379,12 @@ def test_workload_uneven_24_streams(ctx):
     _workload(synth.config_c2(), "batch", ctx)
 
 
-def test_workload_detector_stress(ctx):
+@pytest.mark.parametrize("sched", [DEFAULT, (256, 4, 6, 0)], ids=lambda s: "t%d_w%d_v%d_p%d" % s)
+def test_workload_detector_stress(ctx, sched):
     # four whole-detector fills: 96 calorimeter units of 54 x 560,000
-    ctx.set_schedule(*DEFAULT)
+    ctx.set_schedule(*sched)
     _workload(synth.config_c4(), "batch", ctx)
+    ctx.set_schedule(*DEFAULT)
 
 
 def test_autotune_candidates_agree(ctx, tmp_path):
