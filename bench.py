@@ -397,8 +397,9 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
                 "traffic": traffic,
-                "kernel": ("chop launch: one graph of k_prepare, k_scan_pass, k_prefix_pass, k_edge_pass, "
-                           "k_copy_pass" if sched[2] == 5 else "chop launch: one graph of k_prepare, k_chop"),
+                "kernel": {5: "chop launch: one graph of k_prepare, k_scan_pass, k_prefix_pass, k_edge_pass, k_copy_pass",
+                           6: "chop launch: one graph of k_prepare, k_pipe"}.get(
+                               sched[2], "chop launch: one graph of k_prepare, k_chop"),
                 "kernel_ms_mean": round(kmean, 4),
                 "kernel_launches_timed": len(step_ms),
                 "passes_without_prepare_ms_mean": round(float(np.mean(kern_ms)), 4) if kern_ms else None,

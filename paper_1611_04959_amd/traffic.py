@@ -26,7 +26,7 @@ from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(HERE, "csrc", "chop_kernels.hip")
-PASS_KERNELS = ("k_prepare", "k_scan_pass", "k_prefix_pass", "k_edge_pass", "k_copy_pass", "k_emit_pass", "k_chop")
+PASS_KERNELS = ("k_prepare", "k_scan_pass", "k_prefix_pass", "k_edge_pass", "k_copy_pass", "k_chop", "k_pipe")
 
 
 def kernel_sha() -> str:
