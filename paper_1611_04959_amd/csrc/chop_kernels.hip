@@ -1405,14 +1405,13 @@ __device__ __forceinline__ uint32_t tile_mask10(const FillDev &fd, const ChopGeo
     return m10;
 }
 
-// Scan pass, one tile: flags, dilation, mask bits, totals.
+// Scan pass, one tile: flags, dilation, mask bits, totals. The tile's word
+// in tile_state (zero before the launch) receives each wave's totals by an
+// atomic add, so the tile ends without a work-group barrier.
 template <int NT, int R>
 __device__ __forceinline__ void scan_pass_tile(const KArgs &a, const FillDev &fd, int32_t thr_eff, int64_t tile,
-                                               uint8_t *lds, uint32_t *s_wsum) {
-    constexpr int NW = NT / 64;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wid = tid >> 6;
+                                               uint8_t *lds) {
+    const int lane = threadIdx.x & 63;
     const ChopGeom<NT> q(fd, tile);
     const uint32_t m10 = tile_mask10<NT, R>(fd, q, thr_eff, lds);
     if (q.owner) {
@@ -1422,24 +1421,22 @@ __device__ __forceinline__ void scan_pass_tile(const KArgs &a, const FillDev &fd
     }
     const uint32_t mm = (m10 >> 1) & 0xFFu;
     const uint32_t rise = mm & ~(((mm << 1) | (m10 & 1u)) & 0xFFu);
-    // tile totals (island samples, islands begun in the tile)
+    // the wave's totals (island samples, islands begun)
     uint32_t mine = ((uint32_t)__popc(mm) << 16) | (uint32_t)__popc(rise);
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) mine += __shfl_xor(mine, d, 64);
-    if (lane == 0) s_wsum[wid] = mine;
-    lds_barrier();
-    if (tid == 0) {
-        uint32_t total = 0;
-#pragma unroll
-        for (int w = 0; w < NW; w++) total += s_wsum[w];
-        *gbl(a.tile_state + tile) = ((uint64_t)(total >> 16) << 31) | (uint64_t)(total & 0xFFFFu);
-    }
+    if (lane == 0 && mine != 0u)
+        atomicAdd(reinterpret_cast<unsigned long long *>(a.tile_state + tile),
+                  (unsigned long long)(((uint64_t)(mine >> 16) << 31) | (uint64_t)(mine & 0xFFFFu)));
 }
 
 template <int NT, int R>
 __global__ void __launch_bounds__(NT) k_scan_pass(KArgs a) {
-    __shared__ __align__(16) uint8_t s_lds[ChopLds<NT>::kBitsBytes];
-    __shared__ uint32_t s_wsum[NT / 64];
+    // two bitmaps, used by alternate tiles: a wave still reading one tile's
+    // bitmap never meets the next tile's writes, so tiles need no closing
+    // barrier (the next-but-one tile's writes come after a barrier every
+    // wave has passed)
+    __shared__ __align__(16) uint8_t s_lds[2][ChopLds<NT>::kBitsBytes];
     __shared__ int64_t s_base[kLdsFills];
     const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
     const int64_t total = a.hdr ? a.hdr->total_tiles : a.total_tiles;
@@ -1450,6 +1447,7 @@ __global__ void __launch_bounds__(NT) k_scan_pass(KArgs a) {
     FillDev fd{};
     int cur = -1;
     int32_t thr_eff = 0;
+    int buf = 0;
     const PartRange pr = part_range(a, nf, total);
     for (int64_t tile = pr.tile_lo + blockIdx.x; tile < pr.tile_hi; tile += gridDim.x) {
         if (cur < 0 || tile < fd.tile_base || tile >= fd.tile_base + fd.n_tiles) {
@@ -1463,8 +1461,8 @@ __global__ void __launch_bounds__(NT) k_scan_pass(KArgs a) {
             thr_eff = clamp_thr(*gbl(a.thr_eff + lo));
             cur = lo;
         }
-        scan_pass_tile<NT, R>(a, fd, thr_eff, tile, s_lds, s_wsum);
-        lds_barrier();
+        scan_pass_tile<NT, R>(a, fd, thr_eff, tile, s_lds[buf]);
+        buf ^= 1;
     }
 }
 

@@ -117,3 +117,20 @@ def test_server_struct_layouts():
     assert ctypes.sizeof(daq.daq_counts) == 24
     assert ctypes.sizeof(daq.daq_completion) == 8 + 8 + 24 + 48 + 8 + 4 + 4 + 24
     assert ctypes.sizeof(daq.daq_server_stats) == 8 * 8 + 8
+
+
+def test_header_constants_match_the_binding():
+    """Every #define DAQ_<NAME> <integer> of the header has the same value in the binding."""
+    text = open(HEADER).read()
+    found = re.findall(r"^#define (DAQ_[A-Z_0-9]+)\s+\(?(-?\d+)\)?", text, flags=re.M)
+    assert len(found) > 15
+    checked = 0
+    for name, value in found:
+        if hasattr(daq, name):
+            assert getattr(daq, name) == int(value), name
+            checked += 1
+    for name in ("DAQ_VARIANT_SPLIT", "DAQ_VARIANT_PIPE", "DAQ_STATUS_CAPACITY", "DAQ_STATUS_OUT_STRIDE",
+                 "DAQ_STATUS_INCOMPLETE", "DAQ_EINVAL"):
+        assert hasattr(daq, name), name
+    assert checked >= 10
+

@@ -5,6 +5,8 @@ Covers hand-derived fixtures, random small fills spanning several tiles with
 ragged tails, every schedule, the three entry forms (fused per fill, find +
 gather, batched launch), edge cases, and the benchmark workloads at full size.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -205,6 +207,16 @@ def test_capacity_and_out_stride_overflow(ctx):
         assert status == daq.DAQ_STATUS_OUT_STRIDE and total == ref.total_len > 1000
         np.testing.assert_array_equal(isl, ref.islands)
         np.testing.assert_array_equal(out, ref.out[:, :1000])
+
+
+def test_schedule_validation(ctx):
+    bad = [(128, 4, daq.DAQ_VARIANT_PIPE, 0), (256, 4, daq.DAQ_VARIANT_PIPE, 2), (256, 17, 5, 0),
+           (256, 4, 7, 0), (256, 4, daq.DAQ_VARIANT_SPLIT, 5), (512, 4, daq.DAQ_VARIANT_LDS, 0)]
+    lib = daq.load_library()
+    for sc in bad:
+        s = daq.daq_schedule(*sc)
+        assert lib.daq_ctx_set_schedule(ctx.handle, ctypes.byref(s)) == daq.DAQ_EINVAL, sc
+    ctx.set_schedule(*DEFAULT)
 
 
 def test_argument_errors(ctx):
