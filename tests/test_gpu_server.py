@@ -180,3 +180,24 @@ def test_admission_and_release_rules(ctx, workload):
         srv.release(t2)
         srv.release(t3)
         assert srv.stats().arena_in_use == 0
+
+
+def test_persistent_schedule_serves_the_same(workload):
+    """Workers inherit the context's schedule: the persistent kernel behind the server."""
+    specs, xs, xd, fills, refs = workload
+    C = synth.CHANNELS
+    c2 = daq.Context(0)
+    try:
+        c2.set_schedule(512, 2, daq.DAQ_VARIANT_PIPE)
+        need = sum(daq.slot_bytes(f) for f in fills)
+        arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+        with daq.Server(c2, arena, n_streams=2, max_batch=4) as srv:
+            log("server with the persistent schedule: %d fills" % len(fills))
+            for i, f in enumerate(fills):
+                assert srv.submit(f, tag=i) is not None
+            got = _drain(srv, len(fills))
+            for c in got.values():
+                _check(srv, c, refs[c.tag], C, "persistent %d" % c.tag)
+                srv.release(c.ticket)
+    finally:
+        c2.close()
