@@ -22,7 +22,7 @@ constexpr int kVariantResident = 1;  // rows kept in registers until written out
 constexpr int kVariantStream = 2;    // rows DMA'd into LDS; two work-groups per CU
 constexpr int kVariantReload18 = 3;  // as kVariantReload, 18 rows in flight per round (6 there)
 constexpr int kVariantReload27 = 4;  // as kVariantReload, 27 rows in flight per round
-constexpr int kVariantSplit = 5;     // scan pass (mask bits, tile totals), prefix pass, emit pass
+constexpr int kVariantSplit = 5;     // scan pass (mask bits, tile totals), prefix, edge and copy passes
 constexpr int kVariantPipe = 6;      // one persistent kernel: scan tiles and copy chunks from shared counters
 constexpr int kVariantLast = 6;
 // Guard bytes around each fill's island-mask bits (read as zero past the ends).

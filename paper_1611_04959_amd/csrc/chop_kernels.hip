@@ -5,7 +5,14 @@
 // array and packed island samples, all in integers.
 //
 // k_prepare  per fill: pedestals (Table 2 pedestal row) and the effective
-//            threshold thr + sum(ped); clears the look-back words.
+//            threshold thr + sum(ped); clears the look-back words and counts.
+// k_scan_pass, k_prefix_pass, k_edge_pass, k_copy_pass
+//            the split schedule (the default): a streaming scan that writes
+//            one island-mask bit per sample and tile totals, the tiles'
+//            prefixes, the island records and a run table, and a copy of
+//            the island samples in equal chunks of packed positions.
+// k_pipe     one persistent kernel: scan tiles (steps 1-4a below) and copy
+//            chunks of finished fills, taken from shared counters.
 // k_chop     the fused pass. Each thread of a work-group takes 8 consecutive
 //            samples (one 16-byte load per channel row); the work-group's
 //            groups cover a tile of the fill plus a halo of post + 1 samples
@@ -529,7 +536,7 @@ __device__ __forceinline__ uint4 blend8(const uint4 a, const uint4 b, int split)
                       (a.w & m3) | (b.w & ~m3));
 }
 
-// Chopped islands of one tile copied from the raw rows (emit pass). Run r
+// Chopped islands copied straight from the raw rows (no staging). Run r
 // moves tile samples [src_r, ...) to packed positions [dst_r, dst_{r+1})
 // (tile-relative; the last run ends at tile_m). A work item is one 16-byte
 // line of one channel's packed row. A line inside one run, or across the
@@ -1312,14 +1319,14 @@ __global__ void __launch_bounds__(NT) k_chop(KArgs a) {
     }
 }
 
-// ---- variant 5: scan pass, prefix pass, emit pass -----------------------------------
+// ---- variant 5: scan pass, prefix pass, edge pass, copy pass ------------------------
 //
 // The scan pass streams the raw rows once and keeps nothing: per tile it
 // writes the island-mask bits of the samples it owns and the tile's totals.
 // A prefix pass turns the totals into each tile's exclusive prefix (and the
-// fill's counts); the emit pass writes the island records and copies only the
-// island samples. No tile waits for another, so the streaming pass keeps as
-// many loads in flight as the CU holds.
+// fill's counts); the edge pass writes the island records and a run table;
+// the copy pass copies only the island samples. No tile waits for another,
+// so the streaming pass keeps as many loads in flight as the CU holds.
 
 // Fills [lo, hi) and their tiles [tile_lo, tile_hi) of the launch's part of
 // the batch (the whole batch when parts <= 1).
