@@ -145,13 +145,18 @@ __device__ __forceinline__ uint4 load16(const int16_t *p) {
     return make_uint4(v.x, v.y, v.z, v.w);
 }
 
+// One 16-byte line of a packed output row. The packed rows are not read
+// again on the device, so the store is non-temporal: the line goes out to HBM
+// now, while the write-out is bound by its load chains, instead of lingering
+// dirty in the caches and being written back during the next launch's
+// streaming scan (where it costs scan bandwidth: 162 against 180 us).
 __device__ __forceinline__ void store16(int16_t *p, const uint4 v) {
     u32x4 w;
     w.x = v.x;
     w.y = v.y;
     w.z = v.z;
     w.w = v.w;
-    *(DAQ_GLOBAL u32x4 *)p = w;
+    __builtin_nontemporal_store(w, (DAQ_GLOBAL u32x4 *)p);
 }
 
 // Flags of 8 samples starting at p (all C rows read, nothing kept); R rows
