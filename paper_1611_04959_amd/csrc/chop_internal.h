@@ -77,7 +77,7 @@ static_assert(sizeof(FillDev) % 16 == 0, "descriptors are read as 16-byte words"
 // replayed for any batch that fits the scratch it was captured with.
 struct BatchHdr {
     int32_t n_fills;
-    int32_t pad;
+    int32_t stream_loads;  // 1: the scan reads raw rows non-temporally (batches larger than the caches)
     int64_t total_tiles;
     int64_t copy_slots;  // split variant: n_fills x chunks of the longest fill
     int64_t pad2;
@@ -86,9 +86,9 @@ static_assert(sizeof(BatchHdr) % 16 == 0, "the descriptor table follows the head
 
 struct KArgs {
     const FillDev *table;  // device table of n_fills entries, or null: use `one`
-    const BatchHdr *hdr;   // device header, or null: use the two fields below
+    const BatchHdr *hdr;   // device header, or null: use the three fields below
     int32_t n_fills;
-    int32_t pad;
+    int32_t stream_loads;
     int64_t total_tiles;
     uint64_t *tile_state;  // one look-back word per tile (split variant: tile totals)
     uint32_t *ticket;      // 16 words: tile dispenser; pipe variant: copy cursor, give-up flag

@@ -112,6 +112,11 @@ __device__ __forceinline__ FillDev fill_at(const KArgs &a, int f) {
     return a.one;
 }
 
+// Whether the launch reads its raw rows with non-temporal loads.
+__device__ __forceinline__ bool stream_loads(const KArgs &a) {
+    return (a.hdr ? a.hdr->stream_loads : a.stream_loads) != 0;
+}
+
 __device__ __forceinline__ int64_t tile_base_at(const KArgs &a, int f) {
     return a.table ? gbl(a.table + f)->tile_base : a.one.tile_base;
 }
@@ -145,10 +150,12 @@ __device__ __forceinline__ uint4 load16(const int16_t *p) {
     return make_uint4(v.x, v.y, v.z, v.w);
 }
 
-// A 16-byte chunk of a raw row on the streaming read: non-temporal, since the
-// summing pass uses each chunk once (its halo neighbours aside) and the whole
-// batch is several times the size of the caches (150 against 162 us for the
-// 16-fill scan).
+// A 16-byte chunk of a raw row on the streaming read of a batch larger than
+// the caches: non-temporal, since the summing pass uses each chunk once (its
+// halo neighbours aside) and nothing of the batch would stay cached for the
+// write-out anyway (150 against 162 us for the 16-fill scan). Smaller
+// launches read normally, so that their rows are still cached when the
+// island samples are read again.
 __device__ __forceinline__ uint4 load16_stream(const int16_t *p) {
     const u32x4 v = __builtin_nontemporal_load((const DAQ_GLOBAL u32x4 *)p);
     return make_uint4(v.x, v.y, v.z, v.w);
@@ -169,19 +176,20 @@ __device__ __forceinline__ void store16(int16_t *p, const uint4 v) {
 }
 
 // Flags of 8 samples starting at p (all C rows read, nothing kept); R rows
-// are in flight per round.
-template <int R>
+// are in flight per round. STREAM: non-temporal loads.
+template <int R, bool STREAM = false>
 __device__ uint32_t group_flags(const int16_t *p, int64_t stride, int C, int32_t thr_eff, int64_t valid) {
+    auto ld = [](const int16_t *q) { return STREAM ? load16_stream(q) : load16(q); };
     int32_t s[kVec] = {0, 0, 0, 0, 0, 0, 0, 0};
     int c = 0;
     for (; c + R <= C; c += R) {
         uint4 v[R];
 #pragma unroll
-        for (int u = 0; u < R; u++) v[u] = load16_stream(p + (int64_t)(c + u) * stride);
+        for (int u = 0; u < R; u++) v[u] = ld(p + (int64_t)(c + u) * stride);
 #pragma unroll
         for (int u = 0; u < R; u++) add8(s, v[u]);
     }
-    for (; c < C; c++) add8(s, load16_stream(p + (int64_t)c * stride));
+    for (; c < C; c++) add8(s, ld(p + (int64_t)c * stride));
     return flags8(s, thr_eff, valid);
 }
 
@@ -932,11 +940,13 @@ struct ChopGeom {
 // halo groups of wide windows loaded apart; bitmap zero padding; barrier.
 template <int NT, int R>
 __device__ __forceinline__ void chop_flags(const FillDev &fd, const ChopGeom<NT> &q, int32_t thr_eff,
-                                           uint8_t *s_bits) {
+                                           uint8_t *s_bits, bool stream = false) {
     const int tid = threadIdx.x;
     const int64_t N = fd.n;
     uint32_t fb = 0;
-    if (q.p >= 0 && q.p < N) fb = group_flags<R>(fd.raw + q.p, fd.stride, fd.C, thr_eff, N - q.p);
+    if (q.p >= 0 && q.p < N)
+        fb = stream ? group_flags<R, true>(fd.raw + q.p, fd.stride, fd.C, thr_eff, N - q.p)
+                    : group_flags<R, false>(fd.raw + q.p, fd.stride, fd.C, thr_eff, N - q.p);
     s_bits[q.g] = (uint8_t)fb;
     if (fd.wide) {
         for (int h = tid; h < fd.gl + fd.gr; h += NT) {
@@ -1368,14 +1378,14 @@ __device__ __forceinline__ PartRange part_range(const KArgs &a, int nf, int64_t 
 // threads that own no samples).
 template <int NT, int R>
 __device__ __forceinline__ uint32_t tile_mask10(const FillDev &fd, const ChopGeom<NT> &q, int32_t thr_eff,
-                                                uint8_t *lds) {
+                                                uint8_t *lds, bool stream) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
     const int64_t N = fd.n;
     uint8_t *s_bits = lds;
     uint32_t *s_pc = reinterpret_cast<uint32_t *>(lds + ChopLds<NT>::kWords * 8);
-    chop_flags<NT, R>(fd, q, thr_eff, s_bits);
+    chop_flags<NT, R>(fd, q, thr_eff, s_bits, stream);
     const int Wn = (q.G + 7) >> 3;
     const uint64_t *words = reinterpret_cast<const uint64_t *>(s_bits);
     // windows of at most 55 samples: the flags around a group fit one 64-bit
@@ -1434,7 +1444,7 @@ __device__ __forceinline__ void scan_pass_tile(const KArgs &a, const FillDev &fd
                                                uint8_t *lds) {
     const int lane = threadIdx.x & 63;
     const ChopGeom<NT> q(fd, tile);
-    const uint32_t m10 = tile_mask10<NT, R>(fd, q, thr_eff, lds);
+    const uint32_t m10 = tile_mask10<NT, R>(fd, q, thr_eff, lds, stream_loads(a));
     if (q.owner) {
         // the owned samples' mask byte: t0 is a multiple of 8
         const int64_t byte = (q.t0 >> 3) + (q.g - fd.gl);
@@ -1822,7 +1832,7 @@ template <int NT, int R>
 __device__ __forceinline__ void pipe_tile(const KArgs &a, const FillDev &fd, int f, int32_t thr_eff, int64_t tile,
                                           uint8_t *lds, uint32_t *s_wsum, uint64_t *s_excl) {
     const ChopGeom<NT> q(fd, tile);
-    const uint32_t m10 = tile_mask10<NT, R>(fd, q, thr_eff, lds);
+    const uint32_t m10 = tile_mask10<NT, R>(fd, q, thr_eff, lds, stream_loads(a));
     TileScan r = tile_totals<NT>(a, fd, q.lt, m10, s_wsum);
     scan_back(a, fd, q.lt, r, s_excl, a.ticket + 4);
     write_records(fd, r, q.p);

@@ -41,6 +41,10 @@ int hip_fail(hipError_t e) {
     } while (0)
 
 constexpr int kRing = 4;          // pinned staging slots per stream
+// Launches reading more raw bytes than this stream them with non-temporal
+// loads; smaller ones keep their rows cached for the island write-out (the
+// last-level cache holds 256 MB).
+constexpr int64_t kStreamLoadBytes = 128ll << 20;
 constexpr int kPrepareBlocks = 1024;
 constexpr int kPrefixBlocks = 256;
 
@@ -467,9 +471,11 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     std::vector<SplitLayout> lay((size_t)n);
     // the pipe variant uses the split variant's run table and chunk map
     const bool split = sc.variant == daqk::kVariantSplit || sc.variant == daqk::kVariantPipe;
+    int64_t raw_bytes = 0;
     for (int32_t i = 0; i < n; i++) {
         base[(size_t)i] = total;
         total += tiles_of(fills[i], sc);
+        raw_bytes += 2 * (int64_t)fills[i].n_channels * fills[i].n_samples;
         if (split) {
             moff[(size_t)i] = mask_total;
             lay[(size_t)i] = split_layout_of(fills[i], sc);
@@ -496,6 +502,7 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     a.tile_pref = s->tile_pref;
     a.n_fills = n;
     a.total_tiles = total;
+    a.stream_loads = raw_bytes > kStreamLoadBytes ? 1 : 0;
     a.copy_slots = split ? max_chunks * n : 0;
     if (n == 1 && !force_table) {
         a.one = desc(0);
@@ -508,7 +515,7 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     BatchHdr *h = reinterpret_cast<BatchHdr *>(s->ring_host[rs]);
     FillDev *tab = reinterpret_cast<FillDev *>(h + 1);
     h->n_fills = n;
-    h->pad = 0;
+    h->stream_loads = a.stream_loads;
     h->total_tiles = total;
     h->copy_slots = a.copy_slots;
     h->pad2 = 0;
