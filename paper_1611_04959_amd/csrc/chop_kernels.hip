@@ -1578,52 +1578,74 @@ __device__ __forceinline__ void write_runs(const FillDev &fd, const TileScan &r,
     }
 }
 
-// Edge pass, one tile: island edges from the mask bits, the island records
-// (capacity-limited), the fill's run table (start, offset of every island)
-// and, for every multiple k of kCopyChunk among the tile's packed positions,
-// the island holding packed position k. Thread j takes the tile's owned
-// samples t0 + 8j .. t0 + 8j + 7.
-template <int NT>
-__device__ __forceinline__ void edge_pass_tile(const KArgs &a, const FillDev &fd, int64_t tile, uint32_t *s_wsum) {
-    constexpr int NW = NT / 64;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wid = tid >> 6;
+// Edge pass, one tile per wave: island edges from the mask bits, the island
+// records (capacity-limited), the fill's run table (start, offset of every
+// island) and, for every multiple k of kCopyChunk among the tile's packed
+// positions, the island holding packed position k. Lane l takes the tile's
+// owned mask bytes 8l .. 8l + 7 (64 samples); a tile owns at most 512 bytes.
+// Only wave-level scans: no barrier, and a work-group handles NT / 64 tiles
+// at once.
+__device__ __forceinline__ void edge_wave_tile(const KArgs &a, const FillDev &fd, int64_t tile, int lane) {
     const int64_t lt = tile - fd.tile_base;
     const int64_t t0 = lt * fd.tout;
-    const int own = (int)(fd.tout / kVec);  // owned groups
-    const int64_t p = t0 + (int64_t)tid * kVec;
+    const int own = (int)(fd.tout / kVec);  // owned mask bytes
     const uint8_t *mb = fd.mbits + (t0 >> 3);
-    const uint64_t pref = *gbl(a.tile_pref + tile);
-    uint32_t mm = 0, prv = 0, nxt = 0;
-    if (tid < own) {
-        mm = *gbl(mb + tid);
-        prv = (*gbl(mb + tid - 1) >> 7) & 1u;  // a zero guard byte before the fill
-        nxt = *gbl(mb + tid + 1) & 1u;         // a zero guard byte after the fill
+    const int b0 = lane * 8;
+    const int nb = own - b0 < 0 ? 0 : (own - b0 < 8 ? own - b0 : 8);  // this lane's bytes
+    uint64_t m = 0;
+    uint32_t prv = 0, nxt = 0;
+    if (nb > 0) {
+        for (int k = 0; k < nb; k++) m |= (uint64_t)*gbl(mb + b0 + k) << (8 * k);
+        prv = (*gbl(mb + b0 - 1) >> 7) & 1u;   // a zero guard byte before the fill
+        nxt = *gbl(mb + b0 + nb) & 1u;         // a zero guard byte after the fill
     }
-    TileScan r;
-    r.mm = mm;
-    r.rise = mm & ~(((mm << 1) | prv) & 0xFFu);
-    r.fall = mm & ~((mm >> 1) | (nxt << 7));
-    const uint32_t mine = ((uint32_t)__popc(r.mm) << 16) | (uint32_t)__popc(r.rise);
-    const uint32_t inc = wave_incl_scan_u32(mine, lane);
-    if (lane == 63) s_wsum[wid] = inc;
-    lds_barrier();
-    uint32_t before = 0;
-#pragma unroll
-    for (int w = 0; w < NW; w++) before += (w < wid) ? s_wsum[w] : 0u;
-    const uint32_t excl = before + inc - mine;
-    r.th_m = (int)(excl >> 16);
-    r.th_i = (int)(excl & 0xFFFFu);
-    r.m_before = (int64_t)((pref >> 31) & kField);
-    r.i_before = (int64_t)(pref & kField);
-    write_records(fd, r, p);
-    write_runs(fd, r, p);
+    const uint64_t rise = m & ~((m << 1) | (uint64_t)prv);
+    const uint64_t fall = nb > 0 ? (m & ~((m >> 1) | ((uint64_t)nxt << (8 * nb - 1)))) : 0ull;
+    const uint32_t cm = (uint32_t)__popcll(m), ci = (uint32_t)__popcll(rise);
+    const uint32_t mine = (cm << 16) | ci;
+    const uint32_t excl = wave_incl_scan_u32(mine, lane) - mine;
+    const uint64_t pref = *gbl(a.tile_pref + tile);
+    const int64_t mbase = (int64_t)((pref >> 31) & kField) + (int64_t)(excl >> 16);
+    const int64_t ibase = (int64_t)(pref & kField) + (int64_t)(excl & 0xFFFFu);
+    const int64_t p = t0 + (int64_t)b0 * 8;  // this lane's first sample
+    DAQ_GLOBAL daq_island *isl = gbl(fd.isl);
+    DAQ_GLOBAL int32_t *runs = gbl(fd.runs);
+    const bool copy = fd.out != nullptr;
+    for (uint64_t r = rise; r; r &= r - 1) {
+        const int k = __ffsll((unsigned long long)r) - 1;
+        const uint64_t below = (1ull << k) - 1ull;
+        const int64_t idx = ibase + __popcll(rise & below);
+        const int64_t off = mbase + __popcll(m & below);
+        if (idx < fd.cap) {
+            isl[idx].start = p + k;
+            isl[idx].offset = off;
+        }
+        if (copy) {
+            runs[2 * idx] = (int32_t)(p + k);
+            runs[2 * idx + 1] = (int32_t)off;
+        }
+    }
+    for (uint64_t f = fall; f; f &= f - 1) {
+        const int k = __ffsll((unsigned long long)f) - 1;
+        const uint64_t upto = k == 63 ? ~0ull : ((2ull << k) - 1ull);
+        const int64_t idx = ibase + __popcll(rise & upto) - 1;
+        if (idx >= 0 && idx < fd.cap) isl[idx].stop = p + k + 1;
+    }
+    if (!copy || cm == 0) return;
+    // at most one multiple of the chunk size among this lane's packed positions
+    const int64_t q = (mbase + kCopyChunk - 1) / kCopyChunk * kCopyChunk;
+    if (q < mbase + cm) {
+        uint64_t bits = m;
+        for (int64_t skip = q - mbase; skip > 0; skip--) bits &= bits - 1;  // drop the lowest set bits
+        const int b = __ffsll((unsigned long long)bits) - 1;
+        const uint64_t upto = b == 63 ? ~0ull : ((2ull << b) - 1ull);
+        *gbl(fd.cmap + q / kCopyChunk) = (int32_t)(ibase + __popcll(rise & upto) - 1);
+    }
 }
 
 template <int NT>
 __global__ void __launch_bounds__(NT) k_edge_pass(KArgs a) {
-    __shared__ uint32_t s_wsum[NT / 64];
+    constexpr int NW = NT / 64;
     __shared__ int64_t s_base[kLdsFills];
     const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
     const int64_t total = a.hdr ? a.hdr->total_tiles : a.total_tiles;
@@ -1631,10 +1653,13 @@ __global__ void __launch_bounds__(NT) k_edge_pass(KArgs a) {
     if (lds_fills)
         for (int i = threadIdx.x; i < nf; i += NT) s_base[i] = tile_base_at(a, i);
     lds_barrier();
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     FillDev fd{};
     int cur = -1;
     const PartRange pr = part_range(a, nf, total);
-    for (int64_t tile = pr.tile_lo + blockIdx.x; tile < pr.tile_hi; tile += gridDim.x) {
+    for (int64_t tile = pr.tile_lo + (int64_t)blockIdx.x * NW + wid; tile < pr.tile_hi;
+         tile += (int64_t)gridDim.x * NW) {
         if (cur < 0 || tile < fd.tile_base || tile >= fd.tile_base + fd.n_tiles) {
             int lo = 0, hi = nf - 1;
             while (lo < hi) {
@@ -1645,8 +1670,7 @@ __global__ void __launch_bounds__(NT) k_edge_pass(KArgs a) {
             fd = fill_at(a, lo);
             cur = lo;
         }
-        edge_pass_tile<NT>(a, fd, tile, s_wsum);
-        lds_barrier();
+        edge_wave_tile(a, fd, tile, lane);
     }
 }
 
