@@ -944,9 +944,14 @@ __device__ __forceinline__ void chop_flags(const FillDev &fd, const ChopGeom<NT>
     const int tid = threadIdx.x;
     const int64_t N = fd.n;
     uint32_t fb = 0;
+    // waves holding halo groups read normally, so that the neighbouring
+    // tile's loads of the same lines can still find them cached
+    const int w = tid >> 6;
+    const bool halo_wave = !fd.wide && (w == 0 || w == NT / 64 - 1);
+    const bool nt = stream && !halo_wave;
     if (q.p >= 0 && q.p < N)
-        fb = stream ? group_flags<R, true>(fd.raw + q.p, fd.stride, fd.C, thr_eff, N - q.p)
-                    : group_flags<R, false>(fd.raw + q.p, fd.stride, fd.C, thr_eff, N - q.p);
+        fb = nt ? group_flags<R, true>(fd.raw + q.p, fd.stride, fd.C, thr_eff, N - q.p)
+                : group_flags<R, false>(fd.raw + q.p, fd.stride, fd.C, thr_eff, N - q.p);
     s_bits[q.g] = (uint8_t)fb;
     if (fd.wide) {
         for (int h = tid; h < fd.gl + fd.gr; h += NT) {
