@@ -72,6 +72,14 @@ def _bind(path):
                              ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                              _i32p, _i64p, ctypes.c_int64, _i64p, _i16p, ctypes.c_int64]
     lib.orc_chop.restype = ctypes.c_int64
+    lib.orc_q_decimate.argtypes = [_i64p, ctypes.c_int64, ctypes.c_int32, _i64p]
+    lib.orc_q_decimate.restype = None
+    lib.orc_q_accumulate.argtypes = [_i16p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _i32p, _i32p,
+                                     ctypes.c_int64]
+    lib.orc_q_accumulate.restype = None
+    lib.orc_qmethod.argtypes = [_i16p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                ctypes.c_int32, _i32p, _i64p, _i32p, ctypes.c_int64]
+    lib.orc_qmethod.restype = ctypes.c_int
     return lib
 
 
@@ -179,3 +187,44 @@ def chop(x, n_samples=None, ped_samples=100, threshold=-200, pre=8, post=24,
     tl = int(total[0])
     return ChopResult(ped, rec[:min(n, cap)].copy(), int(n), tl,
                       out[:, :tl].copy() if gather else None)
+
+
+Q_DECIMATION = 32  # Table 2: 17.5k decimation threads for 560k samples
+
+
+def q_decimate(S, D=Q_DECIMATION):
+    """Table 2 decimation row: int64[ceil(N / D)] block sums of the calorimeter sum."""
+    S = np.ascontiguousarray(S, np.int64)
+    nb = (len(S) + D - 1) // D
+    Q = np.zeros(max(nb, 1), np.int64)
+    _load().orc_q_decimate(_ptr(S, _i64p), len(S), int(D), _ptr(Q, _i64p))
+    return Q[:nb]
+
+
+def q_accumulate(x, ped, acc, n_samples=None):
+    """Table 2 fill-by-fill row: adds x[c][t] - ped[c] to acc[c][t] in place (int32, wraps)."""
+    x, C, N, stride = _as_fill(x, n_samples)
+    ped = np.ascontiguousarray(ped, np.int32)
+    if acc.dtype != np.int32 or acc.ndim != 2 or acc.shape[0] != C or acc.shape[1] < N:
+        raise ValueError("acc must be int32 [channels, >= n_samples]")
+    if not acc.flags.c_contiguous:
+        raise ValueError("acc must be contiguous")
+    _load().orc_q_accumulate(_ptr(x, _i16p), C, N, stride, _ptr(ped, _i32p), _ptr(acc, _i32p), acc.shape[1])
+    return acc
+
+
+def qmethod(x, n_samples=None, ped_samples=100, acc=None, D=Q_DECIMATION):
+    """Q-method for one fill: (ped, Q); acc (if given) is updated in place."""
+    x, C, N, stride = _as_fill(x, n_samples)
+    ped = np.zeros(C, np.int32)
+    nb = (N + D - 1) // D
+    Q = np.zeros(max(nb, 1), np.int64)
+    if acc is not None and (acc.dtype != np.int32 or acc.ndim != 2 or acc.shape[0] != C
+                            or acc.shape[1] < N or not acc.flags.c_contiguous):
+        raise ValueError("acc must be contiguous int32 [channels, >= n_samples]")
+    rc = _load().orc_qmethod(_ptr(x, _i16p), C, N, stride, int(ped_samples), int(D), _ptr(ped, _i32p),
+                             _ptr(Q, _i64p), _ptr(acc, _i32p) if acc is not None else ctypes.cast(None, _i32p),
+                             acc.shape[1] if acc is not None else 0)
+    if rc != 0:
+        raise MemoryError("oracle scratch allocation failed")
+    return ped, Q[:nb].copy()

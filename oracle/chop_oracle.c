@@ -40,6 +40,22 @@
  *     of the lengths of the earlier islands, islands in increasing start;
  *   - gathered samples are the raw int16 values, not pedestal-subtracted.
  *
+ * The Q-method (Section 3, Q-method paragraph; Table 2, the decimation and
+ * fill-by-fill rows) integrates instead of chopping:
+ *
+ *   7. decimated sum Q[b]     = the pedestal-subtracted calorimeter sum S[t]
+ *      summed over consecutive blocks of D samples, b = t / D (Table 2,
+ *      decimation row: 17.5k threads for 560k samples, so D = 32); the last
+ *      block holds the N mod D leftover samples when D does not divide N;
+ *   8. fill-by-fill sum       = every channel's pedestal-subtracted waveform
+ *      added sample by sample to a per-channel accumulator that persists
+ *      across fills (Table 2, fill-by-fill row: 54 x 560k threads).
+ *
+ * Readings where the paper is silent: the pedestals are those of step 1; the
+ * accumulator is int32 and wraps modulo 2^32 (exact while fewer than 2^31 /
+ * 65535 = 32768 fills of arbitrary int16 data, or 524288 fills of 12-bit
+ * data, have been added).
+ *
  * Layout: x is channel-major, x[c * stride + t], 0 <= t < N.
  */
 #include <stdint.h>
@@ -195,4 +211,50 @@ int64_t orc_chop(const int16_t *x, int32_t C, int64_t N, int64_t stride,
     free(F);
     free(M);
     return count;
+}
+
+/* Step 7, Table 2 decimation row: block sums of the calorimeter sum over D
+ * samples; Q must hold ceil(N / D) values. */
+void orc_q_decimate(const int64_t *S, int64_t N, int32_t D, int64_t *Q)
+{
+    int64_t nb = (N + D - 1) / D;
+    for (int64_t b = 0; b < nb; b++)
+        Q[b] = 0;
+    for (int64_t t = 0; t < N; t++)
+        Q[t / D] += S[t];
+}
+
+/* Step 8, Table 2 fill-by-fill row: acc[c][t] += x[c][t] - ped[c] for every
+ * channel and sample of the fill, in int32 arithmetic modulo 2^32. */
+void orc_q_accumulate(const int16_t *x, int32_t C, int64_t N, int64_t stride,
+                      const int32_t *ped, int32_t *acc, int64_t acc_stride)
+{
+    for (int32_t c = 0; c < C; c++) {
+        for (int64_t t = 0; t < N; t++) {
+            int64_t v = (int64_t)x[(int64_t)c * stride + t] - ped[c];
+            uint32_t a = (uint32_t)acc[(int64_t)c * acc_stride + t];
+            acc[(int64_t)c * acc_stride + t] = (int32_t)(a + (uint32_t)v);
+        }
+    }
+}
+
+/* Steps 1, 2, 7 and 8 in order for one fill. Q (ceil(N / D) values) and acc
+ * may each be NULL. Returns 0, or -1 when scratch memory cannot be
+ * allocated. */
+int orc_qmethod(const int16_t *x, int32_t C, int64_t N, int64_t stride,
+                int32_t Np, int32_t D, int32_t *ped, int64_t *Q, int32_t *acc,
+                int64_t acc_stride)
+{
+    orc_pedestals(x, C, N, stride, Np, ped);
+    if (Q != NULL) {
+        int64_t *S = (int64_t *)malloc((size_t)(N > 0 ? N : 1) * sizeof(int64_t));
+        if (!S)
+            return -1;
+        orc_calo_sum(x, C, N, stride, ped, S);
+        orc_q_decimate(S, N, D, Q);
+        free(S);
+    }
+    if (acc != NULL)
+        orc_q_accumulate(x, C, N, stride, ped, acc, acc_stride);
+    return 0;
 }
