@@ -209,6 +209,40 @@ int daq_chop_fill(daq_ctx *ctx, const daq_fill *fill, const daq_fill_out *out,
 int daq_process_batch(daq_ctx *ctx, const daq_fill *fills,
                       const daq_fill_out *outs, int32_t n, void *stream);
 
+/* ---- Q-method -------------------------------------------------------------
+ * The second output stream of the GPU (Section 3, Q-method paragraph; Table 2,
+ * the decimation and fill-by-fill rows): instead of chopping, the detector
+ * current is integrated. With S[t] the pedestal-subtracted calorimeter sum of
+ * the T-method (pedestals as there: the mean of the first min(Np, N) samples
+ * of each channel, rounded half up):
+ *   qsum[b]  = sum of S[t] over t in [32 b, 32 b + 32), t < N  (the decimated
+ *              sum: 17.5k bins for 560k samples);
+ *   acc[c][t] += x[c][t] - ped[c] for every channel and t < N (the
+ *              fill-by-fill sum of waveforms), int32, modulo 2^32 (exact
+ *              while fewer than 32768 fills of any int16 data, or 524288
+ *              fills of 12-bit data, have been added).
+ * threshold, pre and post of the fill are not used. */
+#define DAQ_Q_DECIMATION 32  /* samples per decimated bin                     */
+
+typedef struct daq_q_out {
+    int64_t *qsum;       /* ceil(n_samples / 32) bins, or NULL; 8-byte aligned */
+    int32_t *acc;        /* n_channels rows of acc_stride int32, or NULL;
+                            16-byte aligned; elements >= n_samples of a row
+                            are not touched                                  */
+    int64_t acc_stride;  /* elements per accumulator row: >= n_samples and a
+                            multiple of 4 when acc is set                     */
+    int32_t *ped;        /* n_channels pedestals written, or NULL             */
+} daq_q_out;             /* 32 bytes, device pointers                          */
+
+/* The Q-method for n fills in one launch (a pedestal kernel, then one pass
+ * that reads every raw sample once and updates qsum and acc). The arrays are
+ * host arrays of n entries, copied before the call returns; n = 0 is a
+ * no-op. Fills of one call must not share accumulator memory (DAQ_EINVAL):
+ * calls on one stream accumulate in order. Errors as for daq_process_batch,
+ * and DAQ_EALIGN for misaligned qsum or acc. */
+int daq_qmethod_batch(daq_ctx *ctx, const daq_fill *fills,
+                      const daq_q_out *outs, int32_t n, void *stream);
+
 /* Schedule of the fused kernel used by daq_chop_fill / daq_process_batch.
  * EINVAL for values outside the documented sets. */
 int daq_ctx_set_schedule(daq_ctx *ctx, const daq_schedule *s);

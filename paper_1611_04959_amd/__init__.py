@@ -58,6 +58,11 @@ class daq_fill_out(ctypes.Structure):
                 ("out", ctypes.c_void_p), ("out_stride", ctypes.c_int64)]
 
 
+class daq_q_out(ctypes.Structure):
+    _fields_ = [("qsum", ctypes.c_void_p), ("acc", ctypes.c_void_p), ("acc_stride", ctypes.c_int64),
+                ("ped", ctypes.c_void_p)]
+
+
 class daq_schedule(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("parts", ctypes.c_int32)]
@@ -125,6 +130,8 @@ def load_library():
         "daq_gather_islands": ([vp, ctypes.POINTER(daq_fill), vp, i64, vp, vp, i64, vp], ctypes.c_int),
         "daq_chop_fill": ([vp, ctypes.POINTER(daq_fill), ctypes.POINTER(daq_fill_out), vp], ctypes.c_int),
         "daq_process_batch": ([vp, ctypes.POINTER(daq_fill), ctypes.POINTER(daq_fill_out), i32, vp],
+                              ctypes.c_int),
+        "daq_qmethod_batch": ([vp, ctypes.POINTER(daq_fill), ctypes.POINTER(daq_q_out), i32, vp],
                               ctypes.c_int),
         "daq_ctx_set_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
         "daq_ctx_get_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
@@ -235,6 +242,32 @@ def alloc_out(fill: Fill, capacity: Optional[int] = None, gather: bool = True,
     return FillOut(isl, counts, ped, out)
 
 
+DAQ_Q_DECIMATION = 32
+
+
+@dataclasses.dataclass
+class QOut:
+    """Device buffers of one fill's Q-method results (any may be None)."""
+    qsum: object = None         # torch.int64 [ceil(N / 32)]
+    acc: object = None          # torch.int32 [C, acc_stride] (acc_stride % 4 == 0), updated in place
+    ped: object = None          # torch.int32 [C]
+
+    def c_struct(self) -> daq_q_out:
+        ast = int(self.acc.stride(0)) if self.acc is not None else 0
+        return daq_q_out(_ptr(self.qsum), _ptr(self.acc), ast, _ptr(self.ped))
+
+
+def alloc_q_out(fill: Fill, acc: bool = True, qsum: bool = True, device=None) -> QOut:
+    """Q-method buffers for one fill; the accumulator starts at zero."""
+    import torch
+    dev = device or fill.raw.device
+    C = int(fill.raw.shape[0])
+    nb = (int(fill.n_samples) + DAQ_Q_DECIMATION - 1) // DAQ_Q_DECIMATION
+    q = torch.zeros(max(nb, 1), dtype=torch.int64, device=dev) if qsum else None
+    a = torch.zeros((C, max(padded(fill.n_samples), 8)), dtype=torch.int32, device=dev) if acc else None
+    return QOut(q, a, torch.zeros(C, dtype=torch.int32, device=dev))
+
+
 class Context:
     """A daq_ctx on one HIP device."""
 
@@ -300,6 +333,18 @@ class Context:
         fa, oa, n = self._arrays(fills, outs)
         _check(self._lib.daq_process_batch(self.handle, fa, oa, n, _stream_handle(stream)),
                "daq_process_batch")
+
+    def daq_qmethod_batch(self, fills: Sequence[Fill], qouts: Sequence[QOut], stream=None):
+        if len(fills) != len(qouts):
+            raise ValueError("fills and qouts differ in length")
+        n = len(fills)
+        fa = (daq_fill * max(n, 1))()
+        qa = (daq_q_out * max(n, 1))()
+        for i, (f, q) in enumerate(zip(fills, qouts)):
+            fa[i] = f.c_struct()
+            qa[i] = q.c_struct()
+        _check(self._lib.daq_qmethod_batch(self.handle, fa, qa, n, _stream_handle(stream)),
+               "daq_qmethod_batch")
 
     def daq_autotune(self, fills: Sequence[Fill], outs: Sequence[FillOut], stream=None,
                      cache_path: Optional[str] = None) -> daq_schedule:

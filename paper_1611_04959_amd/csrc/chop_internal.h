@@ -70,6 +70,10 @@ struct FillDev {
                         // (room for the worst-case island count)
     int32_t *cmap;      // split variant: island holding packed position
                         // k * kCopyChunk, for every such position < total_len
+    int64_t *qsum;      // Q-method: decimated sums, or null
+    int32_t *acc;       // Q-method: fill-by-fill accumulator rows, or null
+    int64_t acc_stride;
+    int64_t pad2;
 };
 static_assert(sizeof(FillDev) % 16 == 0, "descriptors are read as 16-byte words");
 
@@ -144,6 +148,7 @@ hipError_t launch_chop(const KArgs &a, int threads, int variant, int grid, hipSt
 hipError_t launch_scan(const KArgs &a, int threads, int grid, hipStream_t s);
 hipError_t launch_emit(const KArgs &a, int threads, int grid, int prefix_blocks, hipStream_t s);
 hipError_t launch_pipe(const KArgs &a, int threads, int grid, hipStream_t s);
+hipError_t launch_q(const KArgs &a, int threads, int grid, hipStream_t s);
 // Most fill groups a split launch is cut into (one HIP stream each).
 #ifndef DAQ_MAX_PARTS
 #define DAQ_MAX_PARTS 4

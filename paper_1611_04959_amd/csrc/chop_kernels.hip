@@ -1925,6 +1925,113 @@ __global__ void __launch_bounds__(NT) k_pipe(KArgs a) {
     }
 }
 
+// ---- Q-method: decimated calorimeter sum and fill-by-fill waveform sum -----------
+//
+// Section 3, Q-method paragraph; Table 2, decimation and fill-by-fill rows.
+// Tiles of NT x 8 samples (no halo: nothing crosses a tile), grid-stride.
+// Thread j takes samples p = t0 + 8 j .. p + 7 of every channel row: the raw
+// 16-byte chunk is added to the thread's eight column sums and, when the
+// fill has an accumulator, to the channel's eight accumulator words minus
+// the channel pedestal (one 32-byte read-modify-write). The pedestal-
+// subtracted column sums of four consecutive threads make one 32-sample bin.
+
+constexpr int kQBin = 32;  // samples per decimated bin (Table 2: 560k / 17.5k)
+
+__device__ __forceinline__ void store16_i32(int32_t *p, const uint4 v, bool stream) {
+    u32x4 w;
+    w.x = v.x;
+    w.y = v.y;
+    w.z = v.z;
+    w.w = v.w;
+    if (stream) __builtin_nontemporal_store(w, (DAQ_GLOBAL u32x4 *)p);
+    else *(DAQ_GLOBAL u32x4 *)p = w;
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_q_pass(KArgs a) {
+    static_assert((NT * kVec) % kQBin == 0 && kQBin % kVec == 0, "bins never cross a tile");
+    constexpr int kGroupsPerBin = kQBin / kVec;
+    __shared__ int64_t s_base[kLdsFills];
+    const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
+    const int64_t total = a.hdr ? a.hdr->total_tiles : a.total_tiles;
+    const bool stream = stream_loads(a);
+    const bool lds_fills = nf <= kLdsFills;
+    if (lds_fills)
+        for (int i = threadIdx.x; i < nf; i += NT) s_base[i] = tile_base_at(a, i);
+    lds_barrier();
+    const int tid = threadIdx.x;
+    FillDev fd{};
+    int cur = -1;
+    int64_t ped_total = 0;
+    for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        if (cur < 0 || tile < fd.tile_base || tile >= fd.tile_base + fd.n_tiles) {
+            int lo = 0, hi = nf - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if ((lds_fills ? s_base[mid] : tile_base_at(a, mid)) <= tile) lo = mid;
+                else hi = mid - 1;
+            }
+            fd = fill_at(a, lo);
+            ped_total = *gbl(a.thr_eff + lo) - (int64_t)fd.thr;  // thr + sum of pedestals
+            cur = lo;
+        }
+        const int64_t p = (tile - fd.tile_base) * fd.tout + (int64_t)tid * kVec;
+        const int64_t valid = fd.n - p;  // samples of this thread's group inside the fill
+        int64_t gsum = 0;
+        if (valid > 0) {
+            const int nv = valid < kVec ? (int)valid : kVec;
+            int32_t s[kVec] = {0, 0, 0, 0, 0, 0, 0, 0};
+            const int16_t *xr = fd.raw + p;
+            int32_t *ar = fd.acc != nullptr ? fd.acc + p : nullptr;
+            // one channel row: the sums, and the accumulator update with the
+            // raw chunk v already loaded
+            auto update = [&](int c, const uint4 v) {
+                add8(s, v);
+                if (ar == nullptr) return;
+                const int32_t pc = *gbl(fd.ped + c);
+                int32_t *row = ar + (int64_t)c * fd.acc_stride;
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+                uint32_t d[kVec];
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    d[2 * k] = (uint32_t)((int32_t)(int16_t)(w[k] & 0xFFFFu) - pc);
+                    d[2 * k + 1] = (uint32_t)((int32_t)(int16_t)(w[k] >> 16) - pc);
+                }
+                if (nv == kVec) {
+                    const u32x4 a0 = *(const DAQ_GLOBAL u32x4 *)row;
+                    const u32x4 a1 = *(const DAQ_GLOBAL u32x4 *)(row + 4);
+                    store16_i32(row, make_uint4(a0.x + d[0], a0.y + d[1], a0.z + d[2], a0.w + d[3]), stream);
+                    store16_i32(row + 4, make_uint4(a1.x + d[4], a1.y + d[5], a1.z + d[6], a1.w + d[7]), stream);
+                } else {
+                    for (int k = 0; k < nv; k++) gbl(row)[k] = (int32_t)((uint32_t)gbl(row)[k] + d[k]);
+                }
+            };
+            constexpr int R = 4;  // raw rows in flight
+            int c = 0;
+            for (; c + R <= fd.C; c += R) {
+                uint4 v[R];
+#pragma unroll
+                for (int u = 0; u < R; u++) {
+                    const int16_t *q = xr + (int64_t)(c + u) * fd.stride;
+                    v[u] = stream ? load16_stream(q) : load16(q);
+                }
+#pragma unroll
+                for (int u = 0; u < R; u++) update(c + u, v[u]);
+            }
+            for (; c < fd.C; c++) {
+                const int16_t *q = xr + (int64_t)c * fd.stride;
+                update(c, stream ? load16_stream(q) : load16(q));
+            }
+#pragma unroll
+            for (int k = 0; k < kVec; k++) gsum += k < nv ? (int64_t)s[k] - ped_total : 0;
+        }
+        // one bin = kGroupsPerBin consecutive threads (within one wave)
+#pragma unroll
+        for (int d = 1; d < kGroupsPerBin; d <<= 1) gsum += __shfl_xor(gsum, d, 64);
+        if (fd.qsum != nullptr && valid > 0 && (tid % kGroupsPerBin) == 0) *gbl(fd.qsum + p / kQBin) = gsum;
+    }
+}
+
 // Pedestals (Table 2 pedestal row), effective thresholds, cleared look-back
 // words and counts. A block handles whole fills; its threads take
 // (channel, 8-sample chunk) pairs of the pedestal window with 16-byte loads.
@@ -2087,6 +2194,13 @@ hipError_t launch_emit(const KArgs &a, int threads, int grid, int prefix_blocks,
 hipError_t launch_pipe(const KArgs &a, int threads, int grid, hipStream_t s) {
     if (threads == 256) hipLaunchKernelGGL((k_pipe<256, DAQ_SCAN_ROWS>), dim3(grid), dim3(256), 0, s, a);
     else if (threads == 512) hipLaunchKernelGGL((k_pipe<512, DAQ_SCAN_ROWS>), dim3(grid), dim3(512), 0, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_q(const KArgs &a, int threads, int grid, hipStream_t s) {
+    if (threads == 256) hipLaunchKernelGGL((k_q_pass<256>), dim3(grid), dim3(256), 0, s, a);
+    else if (threads == 512) hipLaunchKernelGGL((k_q_pass<512>), dim3(grid), dim3(512), 0, s, a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

@@ -80,6 +80,8 @@ struct Scratch {
     uint64_t *tile_pref = nullptr;  // split variant: tile prefixes (tile_cap)
     uint8_t *mask = nullptr;        // split variant: island-mask bits of all fills
     int64_t mask_cap = 0;
+    int32_t *q_ped = nullptr;       // Q-method: pedestals of fills that have no ped output
+    int64_t q_ped_cap = 0;
     // split variant with fill groups: streams of groups 1.., fork/join events
     hipStream_t part_stream[daqk::kMaxParts] = {};
     hipEvent_t ev_fork = nullptr;
@@ -169,6 +171,7 @@ void free_scratch(Scratch *s) {
     (void)hipFree(s->digest);
     (void)hipFree(s->tile_pref);
     (void)hipFree(s->mask);
+    (void)hipFree(s->q_ped);
     for (int i = 0; i < kRing; i++) {
         if (s->ring_ev[i]) (void)hipEventDestroy(s->ring_ev[i]);
         if (s->ring_host[i]) (void)hipHostFree(s->ring_host[i]);
@@ -737,6 +740,147 @@ int daq_gather_islands(daq_ctx *ctx, const daq_fill *fill, const daq_island *d_i
 
 int daq_chop_fill(daq_ctx *ctx, const daq_fill *fill, const daq_fill_out *out, void *stream) {
     return run_fused(ctx, fill, out, 1, (hipStream_t)stream, false);
+}
+
+namespace {
+
+int check_q_out(const daq_fill &f, const daq_q_out &o) {
+    if (o.acc) {
+        if (o.acc_stride < f.n_samples || (o.acc_stride % 4) != 0) return DAQ_EINVAL;
+        if (!aligned16(o.acc)) return DAQ_EALIGN;
+    }
+    if (o.qsum && ((uintptr_t)o.qsum & 7u) != 0) return DAQ_EALIGN;
+    return DAQ_OK;
+}
+
+// Accumulators of one call must not overlap: each fill adds to its own rows.
+bool q_acc_overlap(const daq_fill *fills, const daq_q_out *outs, int32_t n) {
+    std::vector<std::pair<uintptr_t, uintptr_t>> iv;
+    for (int32_t i = 0; i < n; i++) {
+        const daq_q_out &o = outs[i];
+        if (!o.acc || fills[i].n_samples == 0) continue;
+        const uintptr_t lo = (uintptr_t)o.acc;
+        const uintptr_t hi = lo + (uintptr_t)(((int64_t)fills[i].n_channels - 1) * o.acc_stride +
+                                               fills[i].n_samples) * sizeof(int32_t);
+        iv.emplace_back(lo, hi);
+    }
+    std::sort(iv.begin(), iv.end());
+    for (size_t k = 1; k < iv.size(); k++)
+        if (iv[k].first < iv[k - 1].second) return true;
+    return false;
+}
+
+// The Q-method over n fills: k_prepare (pedestals, thr = 0 so the effective
+// threshold is the pedestal sum), then k_q_pass over tiles of 8 x threads
+// samples. Plain launches; the descriptors go through the staging ring.
+int run_qmethod(daq_ctx *ctx, const daq_fill *fills, const daq_q_out *outs, int32_t n, hipStream_t stream) {
+    if (!ctx || n < 0 || (n > 0 && (!fills || !outs))) return DAQ_EINVAL;
+    for (int32_t i = 0; i < n; i++) {
+        int rc = check_fill(&fills[i]);
+        if (rc) return rc;
+        rc = check_q_out(fills[i], outs[i]);
+        if (rc) return rc;
+    }
+    if (q_acc_overlap(fills, outs, n)) return DAQ_EINVAL;
+    if (n == 0) return DAQ_OK;
+    DeviceGuard guard(ctx->device);
+    const int threads = ctx->sched.threads == 512 ? 512 : 256;
+    const int64_t T = (int64_t)threads * daqk::kVec;  // samples per tile, no halo
+    int64_t total = 0, raw_bytes = 0, ped_need = 0;
+    std::vector<int64_t> base((size_t)n), poff((size_t)n, -1);
+    for (int32_t i = 0; i < n; i++) {
+        base[(size_t)i] = total;
+        total += (fills[i].n_samples + T - 1) / T;
+        raw_bytes += 2 * (int64_t)fills[i].n_channels * fills[i].n_samples;
+        if (!outs[i].ped) {
+            poff[(size_t)i] = ped_need;
+            ped_need += fills[i].n_channels;
+        }
+    }
+    Scratch *s = scratch_for(ctx, stream);
+    int rc = ensure_scratch(s, std::max<int64_t>(total, n), n, 0);
+    if (rc) return rc;
+    if (ped_need > s->q_ped_cap) {
+        HIP_TRY(hipStreamSynchronize(stream));
+        (void)hipFree(s->q_ped);
+        s->q_ped = nullptr;
+        s->q_ped_cap = 0;
+        const int64_t cap = std::max<int64_t>(ped_need + ped_need / 2, 4096);
+        HIP_TRY(hipMalloc(&s->q_ped, (size_t)cap * sizeof(int32_t)));
+        s->q_ped_cap = cap;
+    }
+    auto desc = [&](int32_t i) {
+        const daq_fill &f = fills[i];
+        const daq_q_out &o = outs[i];
+        FillDev d{};
+        d.raw = f.raw;
+        d.n = f.n_samples;
+        d.stride = f.row_stride;
+        d.C = f.n_channels;
+        d.np = f.ped_samples;
+        d.tout = T;
+        d.tile_base = base[(size_t)i];
+        d.n_tiles = (f.n_samples + T - 1) / T;
+        d.ped = o.ped ? o.ped : s->q_ped + poff[(size_t)i];
+        d.qsum = o.qsum;
+        d.acc = o.acc;
+        d.acc_stride = o.acc ? o.acc_stride : 0;
+        return d;
+    };
+    KArgs a{};
+    a.tile_state = s->tile_state;
+    a.ticket = s->ticket;
+    a.thr_eff = s->thr_eff;
+    a.tile_pref = s->tile_pref;
+    a.n_fills = n;
+    a.total_tiles = total;
+    a.stream_loads = raw_bytes > kStreamLoadBytes ? 1 : 0;
+    if (n == 1) {
+        a.one = desc(0);
+    } else {
+        const int rs = s->ring_pos;
+        s->ring_pos = (s->ring_pos + 1) % kRing;
+        if (s->ring_used[rs]) HIP_TRY(hipEventSynchronize(s->ring_ev[rs]));
+        BatchHdr *h = reinterpret_cast<BatchHdr *>(s->ring_host[rs]);
+        FillDev *tab = reinterpret_cast<FillDev *>(h + 1);
+        h->n_fills = n;
+        h->stream_loads = a.stream_loads;
+        h->total_tiles = total;
+        h->copy_slots = 0;
+        h->pad2 = 0;
+        for (int32_t i = 0; i < n; i++) tab[i] = desc(i);
+        const size_t bytes = sizeof(BatchHdr) + (size_t)n * sizeof(FillDev);
+        const uint8_t *img = reinterpret_cast<const uint8_t *>(h);
+        if (s->last_desc.size() != bytes || std::memcmp(s->last_desc.data(), img, bytes) != 0) {
+            HIP_TRY(hipMemcpyAsync(s->hdr, h, bytes, hipMemcpyHostToDevice, stream));
+            HIP_TRY(hipEventRecord(s->ring_ev[rs], stream));
+            s->ring_used[rs] = true;
+            s->last_desc.assign(img, img + bytes);
+        }
+        a.table = s->table;
+        a.hdr = s->hdr;
+    }
+    int prep_blocks = (int)std::min<int64_t>(kPrepareBlocks, std::max<int64_t>(1, (total + 2047) / 2048));
+    prep_blocks = std::max(prep_blocks, std::min(n, kPrepareBlocks));
+    prep_blocks = std::min(prep_blocks, std::max(n, 64));
+    HIP_TRY(daqk::launch_prepare(a, prep_blocks, stream));
+    if (total == 0) return DAQ_OK;
+    const int wgs = ctx->sched.wgs_per_cu > 0 ? ctx->sched.wgs_per_cu : 8;
+    const int grid = (int)std::min<int64_t>((int64_t)wgs * ctx->n_cu, total);
+    size_t slot = 0;
+    if (ctx->timing) {
+        rc = timing_begin(ctx, stream, &slot);
+        if (rc) return rc;
+    }
+    HIP_TRY(daqk::launch_q(a, threads, grid, stream));
+    if (ctx->timing) return timing_end(ctx, stream, slot);
+    return DAQ_OK;
+}
+
+}  // namespace
+
+int daq_qmethod_batch(daq_ctx *ctx, const daq_fill *fills, const daq_q_out *outs, int32_t n, void *stream) {
+    return run_qmethod(ctx, fills, outs, n, (hipStream_t)stream);
 }
 
 int daq_process_batch(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int32_t n,
