@@ -149,6 +149,51 @@ def arrivals(rate, seconds, rng, burst_x=5.0, burst_s=0.080, duty=0.10):
     return out
 
 
+def q_bench(daq, ctx, xs, fills, specs, steps, warmup):
+    """The Q-method on the same 16 fills: decimated sums and fill-by-fill accumulators
+    (one daq_qmethod_batch call per step, every fill adding into its own accumulator)."""
+    import numpy as np
+    import torch
+    qs = [daq.alloc_q_out(f) for f in fills]
+    for _ in range(warmup):
+        ctx.daq_qmethod_batch(fills, qs)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        ctx.daq_qmethod_batch(fills, qs)
+    e1.record()
+    torch.cuda.synchronize()
+    kt = ctx.kernel_times_ms()
+    ctx.set_timing(False)
+    ms = e0.elapsed_time(e1) / steps
+    kms = float(np.mean(kt)) if kt else ms
+    raw = sum(s.raw_bytes for s in specs)
+    acc_bytes = sum(2 * 4 * s.n_samples * x.shape[0] for s, x in zip(specs, xs))   # read + write
+    q_bytes = sum(8 * ((s.n_samples + 31) // 32) for s in specs)
+    alg = raw + acc_bytes + q_bytes
+    parity = None
+    try:
+        import oracle
+        N = specs[0].n_samples
+        ped, Q = oracle.qmethod(xs[0], N, ped_samples=specs[0].ped_samples)
+        k = warmup + steps
+        want = (k * (xs[0][:, :N].astype(np.int64) - ped[:, None].astype(np.int64))) % 2**32
+        got = qs[0].acc[:, :N].cpu().numpy().astype(np.int64) % 2**32
+        parity = bool(np.array_equal(qs[0].qsum.cpu().numpy(), Q) and np.array_equal(want, got))
+    except ImportError:
+        pass
+    return {"workload": "Q-method on the same %d fills: decimated sum (bins of 32) and an int32 "
+                        "fill-by-fill accumulator per fill, one call per step" % len(specs),
+            "steps": steps, "ms_per_step": round(ms, 4), "raw_gbs": round(raw / ms / 1e6, 1),
+            "kernel_ms_mean": round(kms, 4),
+            "roofline": {"bound": "hbm", "achieved": round(alg / kms / 1e6, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(alg / kms / 1e6 / HBM_PEAK_GBS, 4),
+                         "kernel": "k_q_pass", "algorithmic_bytes_per_launch": alg},
+            "parity_fill0": parity}
+
+
 def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch=16):
     """Serving loop on 24 calorimeter streams of plain-workload fills.
 
@@ -258,6 +303,7 @@ def main():
                     help="serving loop at the nominal arrival rate (0 = skip)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch line")
     ap.add_argument("--no-pipelined", action="store_true", help="skip the two-stream batched line")
+    ap.add_argument("--no-qmethod", action="store_true", help="skip the Q-method line")
     ap.add_argument("--stress", action="store_true",
                     help="also time the whole-detector stress batch (96 calorimeter fills, 5.8 GB)")
     args = ap.parse_args()
@@ -443,6 +489,13 @@ def main():
     ceil = ceiling()
     log("ceiling: device copy %.0f GB/s" % ceil["copy_gbs"])
 
+    # ---- the Q-method on the same fills ---------------------------------------------------
+    qmethod = None
+    if not args.no_qmethod:
+        log("Q-method on the %d fills" % len(specs))
+        qmethod = q_bench(daq, ctx, xs, fills, specs, steps=max(10, args.steps // 2), warmup=3)
+        log("Q-method: %.1f GB/s raw, %.0f GB/s algorithmic" % (qmethod["raw_gbs"], qmethod["roofline"]["achieved"]))
+
     # ---- the other batch shapes: uneven batch, whole-detector stress -----------------
     others = {}
     if not args.no_uneven:
@@ -511,6 +564,7 @@ def main():
         "parity_fill0": parity,
         "roofline": roofline,
         "hbm_ceiling": ceil,
+        "qmethod": qmethod,
         "other_batches": others,
         "serving": serving,
         "cpu_baseline": cpu,
