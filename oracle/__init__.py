@@ -80,6 +80,8 @@ def _bind(path):
     lib.orc_qmethod.argtypes = [_i16p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                 ctypes.c_int32, _i32p, _i64p, _i32p, ctypes.c_int64]
     lib.orc_qmethod.restype = ctypes.c_int
+    lib.orc_unpack12.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _i16p, ctypes.c_int64]
+    lib.orc_unpack12.restype = None
     return lib
 
 
@@ -228,3 +230,20 @@ def qmethod(x, n_samples=None, ped_samples=100, acc=None, D=Q_DECIMATION):
     if rc != 0:
         raise MemoryError("oracle scratch allocation failed")
     return ped, Q[:nb].copy()
+
+
+def packed12_row_bytes(n: int) -> int:
+    """Bytes of one channel row of n samples in the 12-bit packing (two samples per three bytes)."""
+    return (3 * int(n) + 1) // 2
+
+
+def unpack12(packed, n_samples, out_stride=None):
+    """Ingest: uint8 [C, row_bytes] 12-bit packed rows -> int16 [C, out_stride] (zero beyond n)."""
+    packed = np.ascontiguousarray(packed, np.uint8)
+    C, row_bytes = packed.shape
+    if row_bytes < packed12_row_bytes(n_samples):
+        raise ValueError("packed rows too short for n_samples")
+    ost = int(n_samples) if out_stride is None else int(out_stride)
+    out = np.zeros((C, max(ost, 1)), np.int16)
+    _load().orc_unpack12(_ptr(packed, _u8p), row_bytes, C, int(n_samples), _ptr(out, _i16p), out.shape[1])
+    return out[:, :ost]

@@ -56,6 +56,14 @@
  * 65535 = 32768 fills of arbitrary int16 data, or 524288 fills of 12-bit
  * data, have been added).
  *
+ * Ingest (Section 3: 12-bit 800 MSPS digitizers, whose words the frontend
+ * unpacks before the GPU thread copies a fill in): a channel row of N 12-bit
+ * samples is packed two samples to three bytes, little-endian: for samples
+ * a = x[2k], b = x[2k + 1], byte 3k = a & 0xFF, byte 3k + 1 = (a >> 8) |
+ * (b & 0xF) << 4, byte 3k + 2 = b >> 4; an odd last sample leaves the high
+ * nibble of its second byte zero and has no third byte. Unpacked samples are
+ * the 12-bit values as int16 (0 .. 4095).
+ *
  * Layout: x is channel-major, x[c * stride + t], 0 <= t < N.
  */
 #include <stdint.h>
@@ -257,4 +265,27 @@ int orc_qmethod(const int16_t *x, int32_t C, int64_t N, int64_t stride,
     if (acc != NULL)
         orc_q_accumulate(x, C, N, stride, ped, acc, acc_stride);
     return 0;
+}
+
+/* Ingest: one channel row of n samples unpacked from its 12-bit packing
+ * (ceil(3 n / 2) bytes). */
+void orc_unpack12_row(const uint8_t *in, int64_t n, int16_t *out)
+{
+    for (int64_t t = 0; t < n; t++) {
+        int64_t k = t / 2;
+        const uint8_t *p = in + 3 * k;
+        if (t % 2 == 0)
+            out[t] = (int16_t)(p[0] | ((p[1] & 0x0F) << 8));
+        else
+            out[t] = (int16_t)((p[1] >> 4) | (p[2] << 4));
+    }
+}
+
+/* Ingest for a fill: C rows, in_stride bytes apart, into rows of out_stride
+ * elements. */
+void orc_unpack12(const uint8_t *in, int64_t in_stride, int32_t C, int64_t n,
+                  int16_t *out, int64_t out_stride)
+{
+    for (int32_t c = 0; c < C; c++)
+        orc_unpack12_row(in + (int64_t)c * in_stride, n, out + (int64_t)c * out_stride);
 }
