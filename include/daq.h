@@ -243,6 +243,22 @@ typedef struct daq_q_out {
 int daq_qmethod_batch(daq_ctx *ctx, const daq_fill *fills,
                       const daq_q_out *outs, int32_t n, void *stream);
 
+/* ---- 12-bit ingest ---------------------------------------------------------
+ * The digitizers deliver 12-bit samples (Section 3); the frontend unpacks them
+ * before a fill is copied to the GPU. Here the packed words can be copied
+ * instead (a quarter fewer bytes over PCIe) and unpacked on the device. A
+ * channel row of N samples is packed two samples to three bytes,
+ * little-endian: for a = x[2k], b = x[2k + 1], byte 3k = a & 0xFF, byte
+ * 3k + 1 = (a >> 8) | (b & 0xF) << 4, byte 3k + 2 = b >> 4; an odd last sample
+ * has no third byte. Row c starts at d_packed + c * packed_stride (bytes,
+ * packed_stride >= ceil(3 N / 2), a multiple of 4; d_packed 4-byte aligned).
+ * Samples t < N of row c are written to d_raw[c * row_stride + t] as int16
+ * 0 .. 4095 (d_raw 16-byte aligned, row_stride >= N and a multiple of 8);
+ * elements >= N are not touched. Asynchronous on `stream`. */
+int daq_unpack12(daq_ctx *ctx, const uint8_t *d_packed, int64_t packed_stride,
+                 int32_t n_channels, int64_t n_samples, int16_t *d_raw,
+                 int64_t row_stride, void *stream);
+
 /* Schedule of the fused kernel used by daq_chop_fill / daq_process_batch.
  * EINVAL for values outside the documented sets. */
 int daq_ctx_set_schedule(daq_ctx *ctx, const daq_schedule *s);

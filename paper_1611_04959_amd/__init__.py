@@ -133,6 +133,7 @@ def load_library():
                               ctypes.c_int),
         "daq_qmethod_batch": ([vp, ctypes.POINTER(daq_fill), ctypes.POINTER(daq_q_out), i32, vp],
                               ctypes.c_int),
+        "daq_unpack12": ([vp, vp, i64, i32, i64, vp, i64, vp], ctypes.c_int),
         "daq_ctx_set_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
         "daq_ctx_get_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
         "daq_ctx_set_graphs": ([vp, ctypes.c_int], ctypes.c_int),
@@ -345,6 +346,12 @@ class Context:
             qa[i] = q.c_struct()
         _check(self._lib.daq_qmethod_batch(self.handle, fa, qa, n, _stream_handle(stream)),
                "daq_qmethod_batch")
+
+    def daq_unpack12(self, packed, n_samples: int, raw, stream=None):
+        """packed: uint8 [C, packed_stride] on the device; raw: int16 [C, row_stride] (written)."""
+        _check(self._lib.daq_unpack12(self.handle, packed.data_ptr(), int(packed.stride(0)), int(packed.shape[0]),
+                                      int(n_samples), raw.data_ptr(), int(raw.stride(0)), _stream_handle(stream)),
+               "daq_unpack12")
 
     def daq_autotune(self, fills: Sequence[Fill], outs: Sequence[FillOut], stream=None,
                      cache_path: Optional[str] = None) -> daq_schedule:

@@ -149,6 +149,8 @@ hipError_t launch_scan(const KArgs &a, int threads, int grid, hipStream_t s);
 hipError_t launch_emit(const KArgs &a, int threads, int grid, int prefix_blocks, hipStream_t s);
 hipError_t launch_pipe(const KArgs &a, int threads, int grid, hipStream_t s);
 hipError_t launch_q(const KArgs &a, int threads, int grid, hipStream_t s);
+hipError_t launch_unpack12(const uint8_t *in, int64_t in_stride, int32_t C, int64_t n, int16_t *out,
+                           int64_t out_stride, int grid, hipStream_t s);
 // Most fill groups a split launch is cut into (one HIP stream each).
 #ifndef DAQ_MAX_PARTS
 #define DAQ_MAX_PARTS 4

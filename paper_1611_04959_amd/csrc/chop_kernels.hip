@@ -2032,6 +2032,46 @@ __global__ void __launch_bounds__(NT) k_q_pass(KArgs a) {
     }
 }
 
+// ---- 12-bit ingest ------------------------------------------------------------------
+//
+// Digitizer words, two 12-bit samples to three bytes (little-endian), into
+// int16 rows. A work item is 8 samples of one row: 12 packed bytes (three
+// aligned 32-bit words) in, one 16-byte store out; the last group of a row
+// with fewer than 8 samples goes byte by byte.
+__global__ void __launch_bounds__(256) k_unpack12(const uint8_t *in, int64_t in_stride, int32_t C, int64_t n,
+                                                  int16_t *out, int64_t out_stride) {
+    const int64_t groups = (n + kVec - 1) / kVec;
+    const int64_t items = groups * C;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < items; i += (int64_t)gridDim.x * 256) {
+        const int64_t c = i / groups;
+        const int64_t g = i - c * groups;
+        const uint8_t *row = in + c * in_stride;
+        int16_t *orow = out + c * out_stride + g * kVec;
+        const int64_t t0 = g * kVec;
+        if (t0 + kVec <= n) {
+            const uint32_t *w = reinterpret_cast<const uint32_t *>(row + 12 * g);
+            const uint32_t w0 = *gbl(w), w1 = *gbl(w + 1), w2 = *gbl(w + 2);
+            const uint32_t s0 = w0 & 0xFFFu, s1 = (w0 >> 12) & 0xFFFu, s2 = ((w0 >> 24) | (w1 << 8)) & 0xFFFu,
+                           s3 = (w1 >> 4) & 0xFFFu, s4 = (w1 >> 16) & 0xFFFu,
+                           s5 = ((w1 >> 28) | (w2 << 4)) & 0xFFFu, s6 = (w2 >> 8) & 0xFFFu,
+                           s7 = (w2 >> 20) & 0xFFFu;
+            u32x4 o;
+            o.x = s0 | (s1 << 16);
+            o.y = s2 | (s3 << 16);
+            o.z = s4 | (s5 << 16);
+            o.w = s6 | (s7 << 16);
+            *(DAQ_GLOBAL u32x4 *)orow = o;
+        } else {
+            for (int64_t t = t0; t < n; t++) {
+                const uint8_t *p = row + 3 * (t >> 1);
+                const uint32_t v = (t & 1) ? ((uint32_t)*gbl(p + 1) >> 4) | ((uint32_t)*gbl(p + 2) << 4)
+                                           : (uint32_t)*gbl(p) | (((uint32_t)*gbl(p + 1) & 0xFu) << 8);
+                *gbl(orow + (t - t0)) = (int16_t)v;
+            }
+        }
+    }
+}
+
 // Pedestals (Table 2 pedestal row), effective thresholds, cleared look-back
 // words and counts. A block handles whole fills; its threads take
 // (channel, 8-sample chunk) pairs of the pedestal window with 16-byte loads.
@@ -2202,6 +2242,12 @@ hipError_t launch_q(const KArgs &a, int threads, int grid, hipStream_t s) {
     if (threads == 256) hipLaunchKernelGGL((k_q_pass<256>), dim3(grid), dim3(256), 0, s, a);
     else if (threads == 512) hipLaunchKernelGGL((k_q_pass<512>), dim3(grid), dim3(512), 0, s, a);
     else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack12(const uint8_t *in, int64_t in_stride, int32_t C, int64_t n, int16_t *out,
+                           int64_t out_stride, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_unpack12, dim3(grid), dim3(256), 0, s, in, in_stride, C, n, out, out_stride);
     return hipGetLastError();
 }
 

@@ -879,6 +879,24 @@ int run_qmethod(daq_ctx *ctx, const daq_fill *fills, const daq_q_out *outs, int3
 
 }  // namespace
 
+int daq_unpack12(daq_ctx *ctx, const uint8_t *d_packed, int64_t packed_stride, int32_t n_channels,
+                 int64_t n_samples, int16_t *d_raw, int64_t row_stride, void *stream) {
+    if (!ctx || n_channels < 1 || n_samples < 0) return DAQ_EINVAL;
+    if (n_samples > DAQ_MAX_SAMPLES || n_channels > DAQ_MAX_CHANNELS) return DAQ_ERANGE;
+    if (n_samples == 0) return DAQ_OK;
+    if (!d_packed || !d_raw || packed_stride < (3 * n_samples + 1) / 2 || row_stride < n_samples)
+        return DAQ_EINVAL;
+    if (((uintptr_t)d_packed & 3u) != 0 || (packed_stride % 4) != 0 || !aligned16(d_raw) ||
+        (row_stride % daqk::kVec) != 0)
+        return DAQ_EALIGN;
+    DeviceGuard guard(ctx->device);
+    const int64_t items = (n_samples + daqk::kVec - 1) / daqk::kVec * n_channels;
+    const int64_t grid = std::min<int64_t>((items + 255) / 256, (int64_t)16 * ctx->n_cu);
+    HIP_TRY(daqk::launch_unpack12(d_packed, packed_stride, n_channels, n_samples, d_raw, row_stride,
+                                  (int)std::max<int64_t>(grid, 1), (hipStream_t)stream));
+    return DAQ_OK;
+}
+
 int daq_qmethod_batch(daq_ctx *ctx, const daq_fill *fills, const daq_q_out *outs, int32_t n, void *stream) {
     return run_qmethod(ctx, fills, outs, n, (hipStream_t)stream);
 }
