@@ -194,6 +194,68 @@ def q_bench(daq, ctx, xs, fills, specs, steps, warmup):
             "parity_fill0": parity}
 
 
+def ingest12_bench(daq, ctx, xs, specs, steps):
+    """12-bit ingest: the 16 fills as packed digitizer words (two samples to three bytes),
+    unpacked on the device; and host-to-device copies of packed and int16 rows from
+    pinned memory, which bound a host-fed DAQ."""
+    import numpy as np
+    import torch
+    N = specs[0].n_samples
+    C = xs[0].shape[0]
+    nb = (3 * N + 1) // 2
+    pst = (nb + 3) // 4 * 4
+    packed = []
+    for x in xs:
+        v = x[:, :N].astype(np.uint32) & 0xFFF
+        if N % 2:
+            v = np.concatenate([v, np.zeros((C, 1), np.uint32)], axis=1)
+        a, b = v[:, 0::2], v[:, 1::2]
+        trip = np.stack([a & 0xFF, (a >> 8) | ((b & 0xF) << 4), b >> 4], axis=2).reshape(C, -1)
+        p = np.zeros((C, pst), np.uint8)
+        p[:, :nb] = trip[:, :nb]
+        packed.append(p)
+    dp = [torch.from_numpy(p).cuda() for p in packed]
+    raws = [torch.empty((C, x.shape[1]), dtype=torch.int16, device="cuda") for x in xs]
+    for p, r in zip(dp, raws):
+        ctx.daq_unpack12(p, N, r)
+    torch.cuda.synchronize()
+    exact = all(np.array_equal(r[:, :N].cpu().numpy(), x[:, :N]) for r, x in zip(raws[:2], xs[:2]))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        for p, r in zip(dp, raws):
+            ctx.daq_unpack12(p, N, r)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    samples = len(xs) * C * N
+    alg = samples * 3.5   # 1.5 bytes read, 2 written per sample
+    # host-to-device copies from pinned memory (one fill, repeated)
+    hp = torch.from_numpy(packed[0]).pin_memory()
+    hr = torch.from_numpy(np.ascontiguousarray(xs[0])).pin_memory()
+    rates = {}
+    for name, h in (("packed", hp), ("int16", hr)):
+        d = torch.empty_like(h, device="cuda")
+        d.copy_(h, non_blocking=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(20):
+            d.copy_(h, non_blocking=True)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 20 / 1e3
+        rates[name] = {"gbs": round(h.numel() * h.element_size() / t / 1e9, 1),
+                       "msamples_per_s": round(C * N / t / 1e6, 1)}
+    del dp, raws
+    return {"workload": "the %d fills as 12-bit words (%.1f MB packed), unpacked on the device" %
+                        (len(xs), sum(p.nbytes for p in packed) / 1e6),
+            "ms_per_step": round(ms, 4), "raw_gbs": round(samples * 2 / ms / 1e6, 1),
+            "roofline": {"bound": "hbm", "achieved": round(alg / ms / 1e6, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4),
+                         "kernel": "k_unpack12 (16 calls)", "algorithmic_bytes_per_step": int(alg)},
+            "h2d_pinned": rates, "exact": exact}
+
+
 def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch=16):
     """Serving loop on 24 calorimeter streams of plain-workload fills.
 
@@ -304,6 +366,7 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch line")
     ap.add_argument("--no-pipelined", action="store_true", help="skip the two-stream batched line")
     ap.add_argument("--no-qmethod", action="store_true", help="skip the Q-method line")
+    ap.add_argument("--no-ingest", action="store_true", help="skip the 12-bit ingest line")
     ap.add_argument("--stress", action="store_true",
                     help="also time the whole-detector stress batch (96 calorimeter fills, 5.8 GB)")
     args = ap.parse_args()
@@ -496,6 +559,12 @@ def main():
         qmethod = q_bench(daq, ctx, xs, fills, specs, steps=max(10, args.steps // 2), warmup=3)
         log("Q-method: %.1f GB/s raw, %.0f GB/s algorithmic" % (qmethod["raw_gbs"], qmethod["roofline"]["achieved"]))
 
+    ingest = None
+    if not args.no_ingest:
+        log("12-bit ingest of the %d fills" % len(specs))
+        ingest = ingest12_bench(daq, ctx, xs, specs, steps=max(10, args.steps // 5))
+        log("12-bit ingest: unpack %.0f GB/s of int16 samples" % ingest["raw_gbs"])
+
     # ---- the other batch shapes: uneven batch, whole-detector stress -----------------
     others = {}
     if not args.no_uneven:
@@ -565,6 +634,7 @@ def main():
         "roofline": roofline,
         "hbm_ceiling": ceil,
         "qmethod": qmethod,
+        "ingest12": ingest,
         "other_batches": others,
         "serving": serving,
         "cpu_baseline": cpu,
