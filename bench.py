@@ -284,7 +284,7 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
     arena = torch.empty(int(budget_gb * 1e9), dtype=torch.uint8, device="cuda")
     srv = daq.Server(ctx, arena, n_streams=n_streams, max_batch=max_batch)
 
-    def run(times, host=None, dur=5.0, depth=96):
+    def run(times, host=None, dur=5.0, depth=96, packed=False):
         """Open loop: offers fills at `times` (s). Closed loop (times None):
         keeps `depth` fills submitted and unfinished for `dur` seconds."""
         pending = []          # (arrival_ns, stream) not yet admitted
@@ -305,7 +305,12 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
                     n_off += 1
             while pending:
                 a_ns, st = pending[0]
-                t = srv.submit(fills[st], tag=st, host_raw=None if host is None else host[st % len(host)])
+                if host is None:
+                    t = srv.submit(fills[st], tag=st)
+                elif packed:
+                    t = srv.submit(fills[st], tag=st, host_packed12=host[st % len(host)])
+                else:
+                    t = srv.submit(fills[st], tag=st, host_raw=host[st % len(host)])
                 if t is None:
                     break
                 arr_ns[t] = a_ns
@@ -339,6 +344,21 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
         log("serving: host-fed ingest at the nominal rate, then saturated")
         ingest = {"nominal": run(arrivals(rate, 5.0, rng), host=host),
                   "saturation": run(None, host=host, depth=32)}
+        N = specs[0].n_samples
+        if all(0 <= int(x.min()) and int(x.max()) <= 4095 for x in xs[:8]):
+            pst = daq.packed12_stride(N)
+            hp = []
+            for x in xs[:8]:
+                v = x[:, :N].astype(np.uint32) & 0xFFF
+                if N % 2:
+                    v = np.concatenate([v, np.zeros((v.shape[0], 1), np.uint32)], axis=1)
+                a, b = v[:, 0::2], v[:, 1::2]
+                trip = np.stack([a & 0xFF, (a >> 8) | ((b & 0xF) << 4), b >> 4], axis=2).reshape(v.shape[0], -1)
+                p = np.zeros((x.shape[0], pst), np.uint8)
+                p[:, :(3 * N + 1) // 2] = trip[:, :(3 * N + 1) // 2]
+                hp.append(torch.from_numpy(p).pin_memory())
+            log("serving: host-fed 12-bit words, saturated")
+            ingest["saturation_packed12"] = run(None, host=hp, depth=32, packed=True)
     except RuntimeError as e:  # pinned memory unavailable
         log("ingest skipped: %s" % e)
     srv.close()

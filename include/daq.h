@@ -306,8 +306,9 @@ int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs,
  * Slot of one fill in the arena, in this order, each part aligned to 256
  * bytes: counts (one daq_counts), ped (C int32), islands (capacity =
  * daq_max_islands(N, pre, post) records), out (C rows of out_stride = N
- * rounded up to a multiple of 8), and for DAQ_SUBMIT_HOST_RAW the raw rows
- * (C x row_stride int16).
+ * rounded up to a multiple of 8), for DAQ_SUBMIT_HOST_RAW the raw rows
+ * (C x row_stride int16), and for DAQ_SUBMIT_HOST_PACKED12 the raw rows and
+ * the packed words (C x daq_packed12_stride(N) bytes).
  *
  * daq_submit_fill, daq_poll, daq_release and daq_server_get_stats may be
  * called from any host thread. */
@@ -318,6 +319,19 @@ typedef struct daq_server daq_server;
                                  the worker's stream before the launch; the
                                  host buffer may be reused once the fill's
                                  completion is returned by daq_poll          */
+#define DAQ_SUBMIT_HOST_PACKED12 2 /* fill->raw is host memory holding the
+                                 fill's rows as 12-bit words (the packing of
+                                 daq_unpack12), row c at byte
+                                 c * daq_packed12_stride(n_samples); the
+                                 server copies the words into the slot and
+                                 unpacks them on the device before the launch
+                                 (a quarter fewer bytes over PCIe); the host
+                                 buffer may be reused once the completion is
+                                 returned. Not combined with HOST_RAW         */
+
+/* Bytes per channel row of a DAQ_SUBMIT_HOST_PACKED12 fill:
+ * ceil(3 n_samples / 2) rounded up to a multiple of 4. */
+int64_t daq_packed12_stride(int64_t n_samples);
 
 /* One finished fill, as returned by daq_poll. */
 typedef struct daq_completion {

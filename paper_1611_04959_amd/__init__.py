@@ -89,6 +89,7 @@ class daq_server_stats(ctypes.Structure):
 
 
 DAQ_SUBMIT_HOST_RAW = 1
+DAQ_SUBMIT_HOST_PACKED12 = 2
 
 
 class DaqError(RuntimeError):
@@ -134,6 +135,7 @@ def load_library():
         "daq_qmethod_batch": ([vp, ctypes.POINTER(daq_fill), ctypes.POINTER(daq_q_out), i32, vp],
                               ctypes.c_int),
         "daq_unpack12": ([vp, vp, i64, i32, i64, vp, i64, vp], ctypes.c_int),
+        "daq_packed12_stride": ([i64], i64),
         "daq_ctx_set_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
         "daq_ctx_get_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
         "daq_ctx_set_graphs": ([vp, ctypes.c_int], ctypes.c_int),
@@ -399,14 +401,19 @@ __all__: List[str] = ["Context", "Fill", "FillOut", "alloc_out", "daq_max_island
                       "version", "DaqError", "padded", "daq_schedule"]
 
 
-def slot_bytes(fill: Fill, host_raw: bool = False) -> int:
+def slot_bytes(fill: Fill, host_raw: bool = False, host_packed12: bool = False) -> int:
     """Arena bytes one fill's slot takes in a Server (daq_server_slot_bytes)."""
     lib = load_library()
     b = ctypes.c_uint64(0)
     f = fill.c_struct()
-    _check(lib.daq_server_slot_bytes(ctypes.byref(f), DAQ_SUBMIT_HOST_RAW if host_raw else 0,
-                                     ctypes.byref(b)), "daq_server_slot_bytes")
+    flags = (DAQ_SUBMIT_HOST_RAW if host_raw else 0) | (DAQ_SUBMIT_HOST_PACKED12 if host_packed12 else 0)
+    _check(lib.daq_server_slot_bytes(ctypes.byref(f), flags, ctypes.byref(b)), "daq_server_slot_bytes")
     return int(b.value)
+
+
+def packed12_stride(n_samples: int) -> int:
+    """Bytes per channel row of a fill submitted as 12-bit words (daq_packed12_stride)."""
+    return int(load_library().daq_packed12_stride(int(n_samples)))
 
 
 @dataclasses.dataclass
@@ -467,14 +474,27 @@ class Server:
     def __exit__(self, *exc):
         self.close()
 
-    def submit(self, fill: Fill, tag: int = 0, host_raw=None) -> Optional[int]:
+    def submit(self, fill: Fill, tag: int = 0, host_raw=None, host_packed12=None) -> Optional[int]:
         """Admits a fill; returns its ticket, or None when the budget is full now.
 
         With ``host_raw`` (a CPU int16 [C, row_stride] tensor, pinned for
         speed) the samples are copied into the arena by the server and
-        ``fill.raw`` is only used for its shape."""
+        ``fill.raw`` is only used for its shape. With ``host_packed12`` (a
+        CPU uint8 [C, packed12_stride(N)] tensor of 12-bit words) the words
+        are copied and unpacked on the device; ``fill.raw`` gives the shape
+        (channels, row stride)."""
         f = fill.c_struct()
         flags = 0
+        if host_packed12 is not None:
+            if host_raw is not None:
+                raise ValueError("host_raw and host_packed12 exclude each other")
+            N = int(fill.n_samples)
+            if (host_packed12.dim() != 2 or host_packed12.is_cuda or host_packed12.dtype.itemsize != 1
+                    or host_packed12.shape[0] != f.n_channels
+                    or host_packed12.stride(0) != packed12_stride(N) or host_packed12.stride(1) != 1):
+                raise ValueError("host_packed12 must be a CPU uint8 [C, packed12_stride(N)] tensor")
+            f.raw = host_packed12.data_ptr()
+            flags = DAQ_SUBMIT_HOST_PACKED12
         if host_raw is not None:
             if host_raw.dim() != 2 or host_raw.stride(1) != 1 or host_raw.is_cuda:
                 raise ValueError("host_raw must be a 2-D CPU tensor with contiguous rows")

@@ -879,6 +879,11 @@ int run_qmethod(daq_ctx *ctx, const daq_fill *fills, const daq_q_out *outs, int3
 
 }  // namespace
 
+int64_t daq_packed12_stride(int64_t n_samples) {
+    if (n_samples < 0) return -1;
+    return ((3 * n_samples + 1) / 2 + 3) / 4 * 4;
+}
+
 int daq_unpack12(daq_ctx *ctx, const uint8_t *d_packed, int64_t packed_stride, int32_t n_channels,
                  int64_t n_samples, int16_t *d_raw, int64_t row_stride, void *stream) {
     if (!ctx || n_channels < 1 || n_samples < 0) return DAQ_EINVAL;

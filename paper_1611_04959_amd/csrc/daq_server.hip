@@ -44,13 +44,14 @@ uint64_t up(uint64_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 // Parts of one slot, as byte offsets from the slot's start.
 struct SlotLayout {
-    uint64_t counts = 0, ped = 0, islands = 0, out = 0, raw = 0, bytes = 0;
+    uint64_t counts = 0, ped = 0, islands = 0, out = 0, raw = 0, packed = 0, bytes = 0;
     int64_t capacity = 0, out_stride = 0;
 };
 
 int check_submit_fill(const daq_fill *f, int32_t flags) {
     if (!f || f->reserved != 0) return DAQ_EINVAL;
-    if (flags & ~DAQ_SUBMIT_HOST_RAW) return DAQ_EINVAL;
+    if (flags & ~(DAQ_SUBMIT_HOST_RAW | DAQ_SUBMIT_HOST_PACKED12)) return DAQ_EINVAL;
+    if ((flags & DAQ_SUBMIT_HOST_RAW) && (flags & DAQ_SUBMIT_HOST_PACKED12)) return DAQ_EINVAL;
     if (f->n_samples < 0 || f->row_stride < f->n_samples) return DAQ_EINVAL;
     if (f->n_samples > DAQ_MAX_SAMPLES) return DAQ_ERANGE;
     if (f->n_channels < 1 || f->ped_samples < 1 || f->pre < 0 || f->post < 0) return DAQ_EINVAL;
@@ -59,7 +60,8 @@ int check_submit_fill(const daq_fill *f, int32_t flags) {
     if (f->row_stride > DAQ_MAX_SAMPLES + 8) return DAQ_ERANGE;
     if (f->n_samples > 0 && !f->raw) return DAQ_EINVAL;
     if (f->row_stride % 8 != 0) return DAQ_EALIGN;
-    if (!(flags & DAQ_SUBMIT_HOST_RAW) && ((uintptr_t)f->raw & 15u) != 0) return DAQ_EALIGN;
+    if (!(flags & (DAQ_SUBMIT_HOST_RAW | DAQ_SUBMIT_HOST_PACKED12)) && ((uintptr_t)f->raw & 15u) != 0)
+        return DAQ_EALIGN;
     return DAQ_OK;
 }
 
@@ -78,7 +80,9 @@ SlotLayout layout_of(const daq_fill &f, int32_t flags) {
     L.out = o;
     o += up(C * (uint64_t)L.out_stride * sizeof(int16_t));
     L.raw = o;
-    if (flags & DAQ_SUBMIT_HOST_RAW) o += up(C * (uint64_t)f.row_stride * sizeof(int16_t));
+    if (flags & (DAQ_SUBMIT_HOST_RAW | DAQ_SUBMIT_HOST_PACKED12)) o += up(C * (uint64_t)f.row_stride * sizeof(int16_t));
+    L.packed = o;
+    if (flags & DAQ_SUBMIT_HOST_PACKED12) o += up(C * (uint64_t)daq_packed12_stride(f.n_samples));
     L.bytes = o;
     return L;
 }
@@ -103,6 +107,8 @@ struct Job {
     int32_t flags = 0;
     daq_fill fill{};        // raw: device rows the kernels read
     const int16_t *host_raw = nullptr;
+    const uint8_t *host_packed = nullptr;  // 12-bit words, rows daq_packed12_stride(N) bytes apart
+    uint8_t *dev_packed = nullptr;         // their place in the slot
     daq_fill_out out{};
     uint64_t offset = 0;    // slot offset in the arena
     int64_t t_submit = 0;
@@ -173,6 +179,15 @@ void worker_loop(daq_server *srv, Worker *w) {
                 const size_t bytes = (size_t)j->fill.n_channels * (size_t)j->fill.row_stride * sizeof(int16_t);
                 he = hipMemcpyAsync(const_cast<int16_t *>(j->fill.raw), j->host_raw, bytes,
                                     hipMemcpyHostToDevice, w->stream);
+            }
+            if (j->host_packed && he == hipSuccess && j->fill.n_samples > 0) {
+                const int64_t pst = daq_packed12_stride(j->fill.n_samples);
+                he = hipMemcpyAsync(j->dev_packed, j->host_packed, (size_t)j->fill.n_channels * (size_t)pst,
+                                    hipMemcpyHostToDevice, w->stream);
+                if (he == hipSuccess &&
+                    daq_unpack12(w->ctx, j->dev_packed, pst, j->fill.n_channels, j->fill.n_samples,
+                                 const_cast<int16_t *>(j->fill.raw), j->fill.row_stride, w->stream) != DAQ_OK)
+                    he = hipErrorUnknown;
             }
         }
         const int64_t t_launch = now_ns();
@@ -305,6 +320,11 @@ int daq_submit_fill(daq_server *srv, const daq_fill *fill, int32_t flags, uint64
     j->fill = *fill;
     if (flags & DAQ_SUBMIT_HOST_RAW) {
         j->host_raw = fill->raw;
+        j->fill.raw = reinterpret_cast<const int16_t *>(base + L.raw);
+    }
+    if (flags & DAQ_SUBMIT_HOST_PACKED12) {
+        j->host_packed = reinterpret_cast<const uint8_t *>(fill->raw);
+        j->dev_packed = base + L.packed;
         j->fill.raw = reinterpret_cast<const int16_t *>(base + L.raw);
     }
     j->out.counts = reinterpret_cast<daq_counts *>(base + L.counts);

@@ -92,7 +92,21 @@ def test_server_slot_bytes_layout():
     assert lib.daq_server_slot_bytes(ctypes.byref(f), 0, ctypes.byref(b)) == daq.DAQ_EINVAL
     f = daq.daq_fill(0x1000, 10, 16, 1, 100, -200, 8, 24, 0)
     assert lib.daq_server_slot_bytes(ctypes.byref(f), 4, ctypes.byref(b)) == daq.DAQ_EINVAL  # unknown flag
+    assert lib.daq_server_slot_bytes(ctypes.byref(f), 3, ctypes.byref(b)) == daq.DAQ_EINVAL  # both host forms
     assert lib.daq_server_slot_bytes(ctypes.byref(f), 0, None) == daq.DAQ_EINVAL
+    # 12-bit words: the raw rows and the packed rows
+    f = daq.daq_fill(0x1000, 560_000, 560_000, 54, 100, -200, 8, 24, 0)
+    assert lib.daq_server_slot_bytes(ctypes.byref(f), daq.DAQ_SUBMIT_HOST_PACKED12, ctypes.byref(b)) == daq.DAQ_OK
+    cap = (560_000 - 1) // 34 + 1
+    assert b.value == (up(32) + up(4 * 54) + up(24 * cap) + up(2 * 54 * 560_000) + up(2 * 54 * 560_000)
+                       + up(54 * 840_000))
+
+
+def test_packed12_stride():
+    lib = daq.load_library()
+    for n, want in ((0, 0), (1, 4), (2, 4), (3, 8), (8, 12), (9, 16), (560_000, 840_000)):
+        assert lib.daq_packed12_stride(n) == want
+    assert lib.daq_packed12_stride(-1) == -1
 
 
 def test_server_calls_reject_null_handles_without_touching_a_gpu():

@@ -154,6 +154,35 @@ def test_host_fed_fills_match(ctx, workload):
             srv.release(c.ticket)
 
 
+def test_host_packed12_fills_match(ctx, workload):
+    """Fills submitted as 12-bit words: copied, unpacked on the device, chopped."""
+    specs, xs, xd, fills, refs = workload
+    if min(int(x.min()) for x in xs[:3]) < 0 or max(int(x.max()) for x in xs[:3]) > 4095:
+        pytest.skip("test fills are not 12-bit")
+    host = []
+    for x, s in zip(xs[:3], specs[:3]):
+        N = s.n_samples
+        pst = daq.packed12_stride(N)
+        v = x[:, :N].astype(np.uint32) & 0xFFF
+        if N % 2:
+            v = np.concatenate([v, np.zeros((v.shape[0], 1), np.uint32)], axis=1)
+        a, b = v[:, 0::2], v[:, 1::2]
+        trip = np.stack([a & 0xFF, (a >> 8) | ((b & 0xF) << 4), b >> 4], axis=2).reshape(v.shape[0], -1)
+        p = np.zeros((x.shape[0], pst), np.uint8)
+        nb = (3 * N + 1) // 2
+        p[:, :nb] = trip[:, :nb]
+        host.append(torch.from_numpy(p).pin_memory())
+    need = sum(daq.slot_bytes(f, host_packed12=True) for f in fills[:3])
+    arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+    with daq.Server(ctx, arena, n_streams=2, max_batch=2) as srv:
+        for i in range(3):
+            assert srv.submit(fills[i], tag=i, host_packed12=host[i]) is not None
+        got = _drain(srv, 3)
+        for c in got.values():
+            _check(srv, c, refs[c.tag], synth.CHANNELS, "host-packed %d" % c.tag)
+            srv.release(c.ticket)
+
+
 def test_admission_and_release_rules(ctx, workload):
     specs, xs, xd, fills, refs = workload
     f = fills[0]
