@@ -82,6 +82,12 @@ def _bind(path):
     lib.orc_qmethod.restype = ctypes.c_int
     lib.orc_unpack12.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _i16p, ctypes.c_int64]
     lib.orc_unpack12.restype = None
+    _u32p = ctypes.POINTER(ctypes.c_uint32)
+    lib.orc_z_compress.argtypes = [_i16p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _u32p, _u32p,
+                                   ctypes.c_int64]
+    lib.orc_z_compress.restype = ctypes.c_int64
+    lib.orc_z_decompress.argtypes = [_u32p, _u32p, ctypes.c_int32, ctypes.c_int64, _i16p, ctypes.c_int64]
+    lib.orc_z_decompress.restype = None
     return lib
 
 
@@ -247,3 +253,31 @@ def unpack12(packed, n_samples, out_stride=None):
     out = np.zeros((C, max(ost, 1)), np.int16)
     _load().orc_unpack12(_ptr(packed, _u8p), row_bytes, C, int(n_samples), _ptr(out, _i16p), out.shape[1])
     return out[:, :ost]
+
+
+Z_BLOCK = 64  # samples per compressed block
+
+
+def z_compress(x, L=None):
+    """Compression of C rows (int16 [C, >= L]): (hdr uint32 [C * ceil(L / 64)], words uint32 [n])."""
+    x = np.ascontiguousarray(x, np.int16)
+    C = x.shape[0]
+    L = x.shape[1] if L is None else int(L)
+    nb = (L + Z_BLOCK - 1) // Z_BLOCK
+    hdr = np.zeros(max(C * nb, 1), np.uint32)
+    cap = C * nb * 34 + 1                       # at most 17 bits per difference
+    words = np.zeros(cap, np.uint32)
+    u32 = ctypes.POINTER(ctypes.c_uint32)
+    n = _load().orc_z_compress(_ptr(x, _i16p), C, L, x.shape[1], _ptr(hdr, u32), _ptr(words, u32), cap)
+    return hdr[:C * nb].copy(), words[:n].copy()
+
+
+def z_decompress(hdr, words, C, L):
+    """Inverse of z_compress: int16 [C, L]."""
+    hdr = np.ascontiguousarray(hdr, np.uint32)
+    words = np.ascontiguousarray(words if len(words) else np.zeros(1, np.uint32), np.uint32)
+    out = np.zeros((C, max(L, 1)), np.int16)
+    u32 = ctypes.POINTER(ctypes.c_uint32)
+    _load().orc_z_decompress(_ptr(hdr if len(hdr) else np.zeros(1, np.uint32), u32), _ptr(words, u32), C, int(L),
+                             _ptr(out, _i16p), out.shape[1])
+    return out[:, :L]

@@ -64,6 +64,18 @@
  * nibble of its second byte zero and has no third byte. Unpacked samples are
  * the 12-bit values as int16 (0 .. 4095).
  *
+ * Compression of the chopped islands (Section 3: the frontend's MFE thread
+ * compresses the data losslessly before the event builder; the algorithm is
+ * not named, this one is the reading taken): each channel's packed row of L
+ * samples is cut into blocks of 64 (the last may be shorter); block b (rows
+ * in order, blocks of a row in order) keeps its first sample and the
+ * zigzag-coded differences z = (r << 1) ^ (r >> 31) of consecutive samples,
+ * r = v[i] - v[i-1], each in w bits, w the bit length of the block's largest
+ * z (0 when all are 0). Header word b = (uint16) first | w << 16; the
+ * differences of block b are a little-endian bit stream (z_i at bits
+ * (i-1) w .. i w - 1) in ceil((n - 1) w / 32) 32-bit words, the blocks'
+ * words back to back.
+ *
  * Layout: x is channel-major, x[c * stride + t], 0 <= t < N.
  */
 #include <stdint.h>
@@ -288,4 +300,79 @@ void orc_unpack12(const uint8_t *in, int64_t in_stride, int32_t C, int64_t n,
 {
     for (int32_t c = 0; c < C; c++)
         orc_unpack12_row(in + (int64_t)c * in_stride, n, out + (int64_t)c * out_stride);
+}
+
+/* Compression: block headers and payload words of C rows of L samples.
+ * Returns the number of payload words; words beyond cap are not written. */
+int64_t orc_z_compress(const int16_t *x, int32_t C, int64_t L, int64_t stride,
+                       uint32_t *hdr, uint32_t *words, int64_t cap)
+{
+    const int64_t B = 64;
+    int64_t nb = (L + B - 1) / B;
+    int64_t pos = 0;                      /* word offset of the next block */
+    for (int32_t c = 0; c < C; c++) {
+        const int16_t *row = x + (int64_t)c * stride;
+        for (int64_t k = 0; k < nb; k++) {
+            int64_t t0 = k * B;
+            int64_t n = (L - t0 < B) ? L - t0 : B;
+            uint32_t zmax = 0;
+            for (int64_t i = 1; i < n; i++) {
+                int32_t r = (int32_t)row[t0 + i] - (int32_t)row[t0 + i - 1];
+                uint32_t z = ((uint32_t)r << 1) ^ (uint32_t)(r >> 31);
+                if (z > zmax)
+                    zmax = z;
+            }
+            uint32_t w = 0;
+            while (w < 32 && (zmax >> w) != 0)
+                w++;
+            hdr[(int64_t)c * nb + k] = (uint32_t)(uint16_t)row[t0] | (w << 16);
+            int64_t nw = ((n - 1) * (int64_t)w + 31) / 32;
+            for (int64_t j = 0; j < nw; j++)
+                if (pos + j < cap)
+                    words[pos + j] = 0;
+            for (int64_t i = 1; i < n; i++) {
+                int32_t r = (int32_t)row[t0 + i] - (int32_t)row[t0 + i - 1];
+                uint32_t z = ((uint32_t)r << 1) ^ (uint32_t)(r >> 31);
+                for (uint32_t bit = 0; bit < w; bit++) {
+                    int64_t at = (i - 1) * (int64_t)w + bit;
+                    int64_t wi = pos + at / 32;
+                    if (((z >> bit) & 1u) && wi < cap)
+                        words[wi] |= 1u << (at % 32);
+                }
+            }
+            pos += nw;
+        }
+    }
+    return pos;
+}
+
+/* Decompression of orc_z_compress's output into C rows of L samples. */
+void orc_z_decompress(const uint32_t *hdr, const uint32_t *words, int32_t C,
+                      int64_t L, int16_t *out, int64_t stride)
+{
+    const int64_t B = 64;
+    int64_t nb = (L + B - 1) / B;
+    int64_t pos = 0;
+    for (int32_t c = 0; c < C; c++) {
+        int16_t *row = out + (int64_t)c * stride;
+        for (int64_t k = 0; k < nb; k++) {
+            int64_t t0 = k * B;
+            int64_t n = (L - t0 < B) ? L - t0 : B;
+            uint32_t h = hdr[(int64_t)c * nb + k];
+            uint32_t w = h >> 16;
+            int32_t v = (int16_t)(h & 0xFFFFu);
+            row[t0] = (int16_t)v;
+            for (int64_t i = 1; i < n; i++) {
+                uint32_t z = 0;
+                for (uint32_t bit = 0; bit < w; bit++) {
+                    int64_t at = (i - 1) * (int64_t)w + bit;
+                    z |= ((words[pos + at / 32] >> (at % 32)) & 1u) << bit;
+                }
+                int32_t r = (int32_t)(z >> 1) ^ -(int32_t)(z & 1u);
+                v += r;
+                row[t0 + i] = (int16_t)v;
+            }
+            pos += ((n - 1) * (int64_t)w + 31) / 32;
+        }
+    }
 }
