@@ -259,6 +259,56 @@ int daq_unpack12(daq_ctx *ctx, const uint8_t *d_packed, int64_t packed_stride,
                  int32_t n_channels, int64_t n_samples, int16_t *d_raw,
                  int64_t row_stride, void *stream);
 
+/* ---- Island compression --------------------------------------------------
+ * Section 3: the frontend compresses the chopped data without loss before it
+ * goes to the event builder (the paper does not name the code). This one is
+ * a per-block delta code. Each of a fill's n_channels packed rows holds L
+ * samples, L = min(max(total_len, 0), max_len) with total_len read from the
+ * fill's daq_counts on the device, so a call can follow daq_chop_fill or
+ * daq_process_batch on the same stream. A row is cut into blocks of 64
+ * samples (the last one may be short); block b = c * nb + k, nb = ceil(L /
+ * 64), covers samples 64 k .. of row c. For a block of n samples x[0..n):
+ *   z[i] = zigzag(x[i] - x[i - 1]) = (r << 1) ^ (r >> 31) on the int32
+ *          difference r, for 1 <= i < n (0 <= z < 2^17);
+ *   w    = bit length of max z (0 when n = 1 or all z are 0), at most 17;
+ *   hdr[b] = (uint16_t)x[0] | w << 16;
+ *   payload: ceil((n - 1) w / 32) uint32 words; z[i] occupies bits
+ *          (i - 1) w .. (i - 1) w + w - 1 of it, bit j of the payload being
+ *          bit j % 32 of its word j / 32 (a little-endian bit stream).
+ * The payloads follow each other in block order: block b's starts at word
+ * offsets[b], and *n_words is the stream's length in words (the caller reads
+ * nb back from total_len). Decoding needs only hdr and words. */
+#define DAQ_Z_BLOCK 64       /* samples per compressed block                */
+#define DAQ_Z_MAX_WIDTH 17   /* widest difference code, bits                 */
+
+typedef struct daq_z_fill {
+    const int16_t *packed;     /* n_channels rows of stride int16 (16-byte
+                                  aligned; a daq_fill_out.out)                */
+    int64_t stride;            /* elements per row: >= max_len, % 8 == 0     */
+    const daq_counts *counts;  /* the fill's counts (8-byte aligned)          */
+    int64_t max_len;           /* samples a row holds at most, >= 0           */
+    uint32_t *hdr;             /* n_channels * ceil(max_len / 64) words       */
+    int64_t *offsets;          /* as many int64, or NULL                     */
+    uint32_t *words;           /* words_cap words                            */
+    int64_t words_cap;         /* words past it are not written; the stream
+                                  never needs more than 34 per block         */
+    int64_t *n_words;          /* one int64: the stream's words (may exceed
+                                  words_cap: then the stream is cut short)   */
+    int32_t n_channels;
+    int32_t reserved;          /* 0                                          */
+} daq_z_fill;                  /* 80 bytes, device pointers                   */
+
+/* Compress n fills (host array, copied before the call returns; n = 0 is a
+ * no-op), asynchronously on `stream`: a size pass, a scan and a pack pass
+ * over all of them. The context keeps per-stream scratch of 8 bytes per 8
+ * blocks of max_len, grown (synchronously) on first need. DAQ_EINVAL for a
+ * null pointer, a negative size, stride < max_len or reserved != 0;
+ * DAQ_ERANGE past DAQ_MAX_CHANNELS / DAQ_MAX_SAMPLES; DAQ_EALIGN for packed
+ * or stride as stated above, or another pointer not aligned to its type.
+ * Fills of one call must not share outputs. */
+int daq_compress_batch(daq_ctx *ctx, const daq_z_fill *fills, int32_t n,
+                       void *stream);
+
 /* Schedule of the fused kernel used by daq_chop_fill / daq_process_batch.
  * EINVAL for values outside the documented sets. */
 int daq_ctx_set_schedule(daq_ctx *ctx, const daq_schedule *s);

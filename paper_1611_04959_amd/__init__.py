@@ -63,6 +63,13 @@ class daq_q_out(ctypes.Structure):
                 ("ped", ctypes.c_void_p)]
 
 
+class daq_z_fill(ctypes.Structure):
+    _fields_ = [("packed", ctypes.c_void_p), ("stride", ctypes.c_int64), ("counts", ctypes.c_void_p),
+                ("max_len", ctypes.c_int64), ("hdr", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("words", ctypes.c_void_p), ("words_cap", ctypes.c_int64), ("n_words", ctypes.c_void_p),
+                ("n_channels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class daq_schedule(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("parts", ctypes.c_int32)]
@@ -135,6 +142,7 @@ def load_library():
         "daq_qmethod_batch": ([vp, ctypes.POINTER(daq_fill), ctypes.POINTER(daq_q_out), i32, vp],
                               ctypes.c_int),
         "daq_unpack12": ([vp, vp, i64, i32, i64, vp, i64, vp], ctypes.c_int),
+        "daq_compress_batch": ([vp, ctypes.POINTER(daq_z_fill), i32, vp], ctypes.c_int),
         "daq_packed12_stride": ([i64], i64),
         "daq_ctx_set_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
         "daq_ctx_get_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
@@ -271,6 +279,47 @@ def alloc_q_out(fill: Fill, acc: bool = True, qsum: bool = True, device=None) ->
     return QOut(q, a, torch.zeros(C, dtype=torch.int32, device=dev))
 
 
+DAQ_Z_BLOCK = 64
+DAQ_Z_MAX_WIDTH = 17
+
+
+@dataclasses.dataclass
+class ZOut:
+    """Device buffers of one fill's compressed stream."""
+    hdr: object                 # torch.int32 [C * ceil(max_len / 64)] (uint32 bit patterns)
+    offsets: object             # torch.int64 [same], or None
+    words: object               # torch.int32 [words_cap] (uint32 bit patterns)
+    n_words: object             # torch.int64 [1]
+
+    def host(self, n_channels: int, total_len: int):
+        """(hdr, offsets, words) of a finished call as numpy uint32 / int64 arrays."""
+        import numpy as np
+        nb = (int(total_len) + DAQ_Z_BLOCK - 1) // DAQ_Z_BLOCK * int(n_channels)
+        nw = int(self.n_words.item())
+        hdr = self.hdr[:nb].cpu().numpy().view(np.uint32)
+        offs = self.offsets[:nb].cpu().numpy() if self.offsets is not None else None
+        words = self.words[:min(nw, int(self.words.numel()))].cpu().numpy().view(np.uint32)
+        return hdr, offs, words
+
+
+def z_words_bound(n_channels: int, max_len: int) -> int:
+    """Words a stream of n_channels rows of at most max_len samples can need."""
+    nb = (int(max_len) + DAQ_Z_BLOCK - 1) // DAQ_Z_BLOCK
+    return int(n_channels) * nb * 34
+
+
+def alloc_z_out(n_channels: int, max_len: int, words_cap: Optional[int] = None, offsets: bool = True,
+                device=None) -> ZOut:
+    """Buffers for one fill's stream; the default words_cap never cuts it short."""
+    import torch
+    nb = (int(max_len) + DAQ_Z_BLOCK - 1) // DAQ_Z_BLOCK * int(n_channels)
+    cap = z_words_bound(n_channels, max_len) if words_cap is None else int(words_cap)
+    return ZOut(torch.zeros(max(nb, 1), dtype=torch.int32, device=device),
+                torch.zeros(max(nb, 1), dtype=torch.int64, device=device) if offsets else None,
+                torch.zeros(max(cap, 1), dtype=torch.int32, device=device),
+                torch.zeros(1, dtype=torch.int64, device=device))
+
+
 class Context:
     """A daq_ctx on one HIP device."""
 
@@ -355,6 +404,21 @@ class Context:
                                       int(n_samples), raw.data_ptr(), int(raw.stride(0)), _stream_handle(stream)),
                "daq_unpack12")
 
+    def daq_compress_batch(self, outs: Sequence[FillOut], zouts: Sequence[ZOut], max_len: Optional[int] = None,
+                           words_cap: Optional[Sequence[int]] = None, stream=None):
+        """Compress the packed rows of each chopped fill (outs[i].out, total_len from outs[i].counts)."""
+        if len(outs) != len(zouts):
+            raise ValueError("outs and zouts differ in length")
+        n = len(outs)
+        za = (daq_z_fill * max(n, 1))()
+        for i, (o, z) in enumerate(zip(outs, zouts)):
+            ml = int(o.out.shape[1]) if max_len is None else int(max_len)
+            cap = int(z.words.numel()) if words_cap is None else int(words_cap[i])
+            za[i] = daq_z_fill(o.out.data_ptr(), int(o.out.stride(0)), o.counts.data_ptr(), ml, z.hdr.data_ptr(),
+                               _ptr(z.offsets), z.words.data_ptr(), cap, z.n_words.data_ptr(),
+                               int(o.out.shape[0]), 0)
+        _check(self._lib.daq_compress_batch(self.handle, za, n, _stream_handle(stream)), "daq_compress_batch")
+
     def daq_autotune(self, fills: Sequence[Fill], outs: Sequence[FillOut], stream=None,
                      cache_path: Optional[str] = None) -> daq_schedule:
         fa, oa, n = self._arrays(fills, outs)
@@ -397,7 +461,7 @@ def version() -> str:
     return load_library().daq_version().decode()
 
 
-__all__: List[str] = ["Context", "Fill", "FillOut", "alloc_out", "daq_max_islands", "load_library",
+__all__: List[str] = ["Context", "Fill", "FillOut", "alloc_out", "ZOut", "alloc_z_out", "z_words_bound", "daq_max_islands", "load_library",
                       "version", "DaqError", "padded", "daq_schedule"]
 
 

@@ -158,4 +158,27 @@ hipError_t launch_unpack12(const uint8_t *in, int64_t in_stride, int32_t C, int6
 constexpr int kMaxParts = DAQ_MAX_PARTS;
 hipError_t launch_gather(const GatherArgs &g, int grid, hipStream_t s);
 
+// Island compression: one fill's packed rows and where its stream goes.
+struct ZFillDev {
+    const int16_t *packed;
+    int64_t stride;            // elements between packed rows
+    const daq_counts *counts;  // total_len: samples per row to compress
+    int64_t max_len;           // rows hold at most this many samples
+    uint32_t *hdr;             // C * ceil(L / 64) block headers
+    int64_t *offsets;          // C * ceil(L / 64) payload word offsets, or null
+    int64_t *gofs;             // scratch: one word per group of 8 blocks of a row
+    uint32_t *words;
+    int64_t cap;               // words that fit
+    int64_t *n_words;          // payload words of the whole stream
+    int32_t C;
+    int32_t pad;
+};
+// Fills per launch (the descriptors travel as kernel arguments).
+constexpr int kZMaxFills = 16;
+struct ZArgs {
+    ZFillDev f[kZMaxFills];
+    int32_t n;
+};
+hipError_t launch_z(const ZArgs &a, int grid, hipStream_t s);
+
 }  // namespace daqk

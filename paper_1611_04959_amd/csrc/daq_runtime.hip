@@ -82,6 +82,8 @@ struct Scratch {
     int64_t mask_cap = 0;
     int32_t *q_ped = nullptr;       // Q-method: pedestals of fills that have no ped output
     int64_t q_ped_cap = 0;
+    int64_t *z_gofs = nullptr;      // compression: payload offsets of block groups
+    int64_t z_gofs_cap = 0;
     // split variant with fill groups: streams of groups 1.., fork/join events
     hipStream_t part_stream[daqk::kMaxParts] = {};
     hipEvent_t ev_fork = nullptr;
@@ -172,6 +174,7 @@ void free_scratch(Scratch *s) {
     (void)hipFree(s->tile_pref);
     (void)hipFree(s->mask);
     (void)hipFree(s->q_ped);
+    (void)hipFree(s->z_gofs);
     for (int i = 0; i < kRing; i++) {
         if (s->ring_ev[i]) (void)hipEventDestroy(s->ring_ev[i]);
         if (s->ring_host[i]) (void)hipHostFree(s->ring_host[i]);
@@ -899,6 +902,82 @@ int daq_unpack12(daq_ctx *ctx, const uint8_t *d_packed, int64_t packed_stride, i
     const int64_t grid = std::min<int64_t>((items + 255) / 256, (int64_t)16 * ctx->n_cu);
     HIP_TRY(daqk::launch_unpack12(d_packed, packed_stride, n_channels, n_samples, d_raw, row_stride,
                                   (int)std::max<int64_t>(grid, 1), (hipStream_t)stream));
+    return DAQ_OK;
+}
+
+namespace {
+
+bool aligned_to(const void *p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
+// Block groups (8 blocks of one row) of a fill whose rows hold max_len samples.
+int64_t z_groups(const daq_z_fill &z) {
+    const int64_t nb = (z.max_len + DAQ_Z_BLOCK - 1) / DAQ_Z_BLOCK;
+    return (nb + 7) / 8 * z.n_channels;
+}
+
+int check_z_fill(const daq_z_fill &z) {
+    if (!z.packed || !z.counts || !z.hdr || !z.n_words || z.stride < 0 || z.max_len < 0 || z.words_cap < 0 ||
+        z.n_channels < 1 || z.reserved != 0 || (z.words_cap > 0 && !z.words))
+        return DAQ_EINVAL;
+    if (z.n_channels > DAQ_MAX_CHANNELS || z.max_len > DAQ_MAX_SAMPLES) return DAQ_ERANGE;
+    if (z.stride < z.max_len) return DAQ_EINVAL;
+    if (!aligned16(z.packed) || (z.stride % daqk::kVec) != 0) return DAQ_EALIGN;
+    if (!aligned_to(z.counts, 8) || !aligned_to(z.hdr, 4) || !aligned_to(z.offsets, 8) ||
+        !aligned_to(z.words, 4) || !aligned_to(z.n_words, 8))
+        return DAQ_EALIGN;
+    return DAQ_OK;
+}
+
+}  // namespace
+
+int daq_compress_batch(daq_ctx *ctx, const daq_z_fill *fills, int32_t n, void *stream_) {
+    if (!ctx || n < 0 || (n > 0 && !fills)) return DAQ_EINVAL;
+    if (n == 0) return DAQ_OK;
+    const hipStream_t stream = (hipStream_t)stream_;
+    int64_t need = 0;
+    for (int32_t i = 0; i < n; i++) {
+        const int rc = check_z_fill(fills[i]);
+        if (rc) return rc;
+        need += z_groups(fills[i]);
+    }
+    DeviceGuard guard(ctx->device);
+    Scratch *s = scratch_for(ctx, stream);
+    if (need > s->z_gofs_cap) {
+        HIP_TRY(hipStreamSynchronize(stream));
+        (void)hipFree(s->z_gofs);
+        s->z_gofs = nullptr;
+        s->z_gofs_cap = 0;
+        const int64_t cap = std::max<int64_t>(need + need / 2, 4096);
+        HIP_TRY(hipMalloc(&s->z_gofs, (size_t)cap * sizeof(int64_t)));
+        s->z_gofs_cap = cap;
+    }
+    int64_t at = 0;
+    for (int32_t i0 = 0; i0 < n; i0 += daqk::kZMaxFills) {
+        daqk::ZArgs a{};
+        a.n = std::min<int32_t>(n - i0, daqk::kZMaxFills);
+        int64_t part_most = 1;
+        for (int32_t j = 0; j < a.n; j++) {
+            const daq_z_fill &z = fills[i0 + j];
+            daqk::ZFillDev &d = a.f[j];
+            d.packed = z.packed;
+            d.stride = z.stride;
+            d.counts = z.counts;
+            d.max_len = z.max_len;
+            d.hdr = z.hdr;
+            d.offsets = z.offsets;
+            d.gofs = s->z_gofs + at;
+            d.words = z.words;
+            d.cap = z.words_cap;
+            d.n_words = z.n_words;
+            d.C = z.n_channels;
+            at += z_groups(z);
+            part_most = std::max(part_most, z_groups(z));
+        }
+        // Resident work-groups of four waves: 8 per CU, shared by the fills.
+        const int64_t wide = std::max<int64_t>(1, (int64_t)8 * ctx->n_cu / a.n);
+        const int grid = (int)std::min<int64_t>(wide, (part_most + 3) / 4);
+        HIP_TRY(daqk::launch_z(a, std::max(grid, 1), stream));
+    }
     return DAQ_OK;
 }
 
