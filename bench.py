@@ -12,9 +12,12 @@ the library's autotuner). Inputs are resident in HBM before timing starts.
 Printed (one JSON line): raw ADC GB/s (value) and its fraction of the HBM
 peak, p50/p99 fill latency for the batched and the plain per-fill forms, the
 fused kernel's roofline figures timed live with HIP events over the timed
-region, and the CPU oracle's throughput on a bounded sample.
+region; lines for the Q-method, the 12-bit ingest and the compression of the
+chopped fills on the same data; and the CPU oracle's throughput on a bounded
+sample, after the oracle has checked the first fill of every line.
 """
 import argparse
+import dataclasses
 import concurrent.futures as cf
 import hashlib
 import json
@@ -26,6 +29,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Fill-0 results of each line, checked against the CPU oracle in the oracle
+# leg at the end: (kind, dict that receives "parity_fill0", payload).
+PENDING = []
 METRIC = "raw ADC GB/s island-chopped & % HBM peak; p99 fill latency, batched vs plain"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "chop_16fills_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1611_04959_amd", "csrc", "chop_kernels.hip")
@@ -105,17 +111,6 @@ def batch_bench(daq, synth, specs, what, steps=20, warmup=3):
     ms = (time.perf_counter() - t0) * 1e3 / steps
     kern = ctx.kernel_times_ms()
     ctx.set_timing(False)
-    parity = None
-    try:
-        import oracle
-        ref = oracle.chop(xs[0], n_samples=specs[0].n_samples, ped_samples=specs[0].ped_samples,
-                          threshold=specs[0].threshold, pre=specs[0].pre, post=specs[0].post)
-        isl, n, total, st, ped, out = outs[0].host()
-        parity = bool(n == ref.n_islands and total == ref.total_len and st == 0 and
-                      np.array_equal(isl, ref.islands) and np.array_equal(ped, ref.ped) and
-                      np.array_equal(out, ref.out))
-    except ImportError:
-        pass
     tot = sum(int(o.counts[1].item()) for o in outs)
     ctx.close()
     res = {"workload": what, "fills": len(specs), "raw_gb": round(raw / 1e9, 3),
@@ -125,7 +120,8 @@ def batch_bench(daq, synth, specs, what, steps=20, warmup=3):
            "occupancy": round(tot / sum(sp.n_samples for sp in specs), 4),
            "schedule": {"threads": best.threads, "wgs_per_cu": best.wgs_per_cu, "variant": best.variant,
                         "parts": best.parts},
-           "steps": steps, "parity_fill0": parity}
+           "steps": steps, "parity_fill0": None}
+    PENDING.append(("chop", res, (xs[0], specs[0], outs[0].host())))
     del xd, fills, outs
     torch.cuda.empty_cache()
     return res
@@ -173,25 +169,144 @@ def q_bench(daq, ctx, xs, fills, specs, steps, warmup):
     acc_bytes = sum(2 * 4 * s.n_samples * x.shape[0] for s, x in zip(specs, xs))   # read + write
     q_bytes = sum(8 * ((s.n_samples + 31) // 32) for s in specs)
     alg = raw + acc_bytes + q_bytes
-    parity = None
-    try:
-        import oracle
-        N = specs[0].n_samples
-        ped, Q = oracle.qmethod(xs[0], N, ped_samples=specs[0].ped_samples)
-        k = warmup + steps
-        want = (k * (xs[0][:, :N].astype(np.int64) - ped[:, None].astype(np.int64))) % 2**32
-        got = qs[0].acc[:, :N].cpu().numpy().astype(np.int64) % 2**32
-        parity = bool(np.array_equal(qs[0].qsum.cpu().numpy(), Q) and np.array_equal(want, got))
-    except ImportError:
-        pass
-    return {"workload": "Q-method on the same %d fills: decimated sum (bins of 32) and an int32 "
-                        "fill-by-fill accumulator per fill, one call per step" % len(specs),
-            "steps": steps, "ms_per_step": round(ms, 4), "raw_gbs": round(raw / ms / 1e6, 1),
-            "kernel_ms_mean": round(kms, 4),
-            "roofline": {"bound": "hbm", "achieved": round(alg / kms / 1e6, 1), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(alg / kms / 1e6 / HBM_PEAK_GBS, 4),
-                         "kernel": "k_q_pass", "algorithmic_bytes_per_launch": alg},
-            "parity_fill0": parity}
+    res = {}
+    PENDING.append(("qmethod", res, (xs[0], specs[0], warmup + steps, qs[0].qsum.cpu().numpy(),
+                                     qs[0].acc[:, :specs[0].n_samples].cpu().numpy())))
+    res.update({"workload": "Q-method on the same %d fills: decimated sum (bins of 32) and an int32 "
+                            "fill-by-fill accumulator per fill, one call per step" % len(specs),
+                "steps": steps, "ms_per_step": round(ms, 4), "raw_gbs": round(raw / ms / 1e6, 1),
+                "kernel_ms_mean": round(kms, 4),
+                "roofline": {"bound": "hbm", "achieved": round(alg / kms / 1e6, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(alg / kms / 1e6 / HBM_PEAK_GBS, 4),
+                             "kernel": "k_q_pass", "algorithmic_bytes_per_launch": alg},
+                "parity_fill0": None})
+    return res
+
+
+def oracle_check(oracle, kind, payload) -> bool:
+    """Fill 0 of one line against the oracle: the chop (records, pedestals, packed rows),
+    the Q-method after k calls (sums; accumulator modulo 2^32) or the compressed stream."""
+    import numpy as np
+
+    def chop(x, sp):
+        return oracle.chop(x, n_samples=sp.n_samples, ped_samples=sp.ped_samples, threshold=sp.threshold,
+                           pre=sp.pre, post=sp.post)
+
+    if kind == "chop":
+        x, sp, (isl, n, total, st, ped, out) = payload
+        ref = chop(x, sp)
+        return bool(n == ref.n_islands and total == ref.total_len and st == 0 and
+                    np.array_equal(isl, ref.islands) and np.array_equal(ped, ref.ped) and
+                    np.array_equal(out, ref.out))
+    if kind == "qmethod":
+        x, sp, k, qsum, acc = payload
+        N = sp.n_samples
+        ped, Q = oracle.qmethod(x, N, ped_samples=sp.ped_samples)
+        want = (k * (x[:, :N].astype(np.int64) - ped[:, None].astype(np.int64))) % 2**32
+        return bool(np.array_equal(qsum, Q) and np.array_equal(want, acc.astype(np.int64) % 2**32))
+    if kind == "fig2":
+        x, x0, sp, thrs, found, truth = payload
+        want = [[chop(h, dataclasses.replace(sp, threshold=t)).n_islands for t in thrs] for h in (x, x0)]
+        return want == [list(found), list(truth)]
+    if kind == "compress":
+        x, sp, hdr, words = payload
+        ref = chop(x, sp)
+        hdr_ref, words_ref = oracle.z_compress(ref.out, ref.total_len)
+        return bool(np.array_equal(hdr, hdr_ref) and np.array_equal(words, words_ref))
+    raise ValueError(kind)
+
+
+def z_bench(daq, ctx, outs, x0, spec0, steps, warmup=3):
+    """Lossless compression of the 16 chopped fills (per-block delta, zigzag and bit
+    width), one daq_compress_batch call per step over the packed rows of the last launch."""
+    import numpy as np
+    import torch
+    C = int(outs[0].out.shape[0])
+    zouts = [daq.alloc_z_out(C, int(o.out.shape[1]), device="cuda") for o in outs]
+    for _ in range(warmup):
+        ctx.daq_compress_batch(outs, zouts)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        ctx.daq_compress_batch(outs, zouts)
+    e1.record()
+    torch.cuda.synchronize()
+    kt = ctx.kernel_times_ms()
+    ctx.set_timing(False)
+    ms = e0.elapsed_time(e1) / steps
+    kms = float(np.mean(kt)) if kt else ms
+    tot = [int(o.counts[1].item()) for o in outs]
+    packed = sum(2 * C * t for t in tot)
+    blocks = sum(C * ((t + 63) // 64) for t in tot)
+    n_words = sum(int(z.n_words.item()) for z in zouts)
+    alg = packed + 12 * blocks + 4 * n_words          # samples read; headers, offsets, payload written
+    stream_bytes = 4 * blocks + 4 * n_words           # what leaves the frontend: headers and payload
+    res = {}
+    hdr0, _, words0 = zouts[0].host(C, tot[0])
+    PENDING.append(("compress", res, (x0, spec0, hdr0, words0)))
+    res.update({"workload": "lossless compression of the %d chopped fills' packed rows (blocks of 64: "
+                            "first sample, bit width, zigzag deltas), one call per step" % len(outs),
+                "steps": steps, "ms_per_step": round(ms, 4), "packed_gbs": round(packed / ms / 1e6, 1),
+                "kernel_ms_mean": round(kms, 4), "ratio": round(packed / stream_bytes, 3),
+                "bits_per_sample": round(8 * stream_bytes / (packed / 2), 3),
+                "roofline": {"bound": "hbm", "achieved": round(alg / kms / 1e6, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(alg / kms / 1e6 / HBM_PEAK_GBS, 4),
+                             "kernel": "one call: k_z_size, k_z_pack",
+                             "algorithmic_bytes_per_launch": alg},
+                "parity_fill0": None})
+    return res
+
+
+FIG2_KS = [0.5, 1, 2, 3, 4, 6, 10, 20]
+
+
+def fig2_bench(daq, synth, ctx, n_fills=16):
+    """A Figure 2 analog: islands found against true islands at thresholds k sigma below
+    each fill's baseline, for 16 fills at the nominal rate. Truth is the same chop of the
+    noiseless rendering (the generator's noise is counter-based: the pulses stay put).
+    The baselines come from the device's Q-method sums; the whole sweep (noisy and
+    noiseless, every threshold) is one batched launch over shared raw rows."""
+    import numpy as np
+    import torch
+    specs = [synth.FillSpec(seed=synth.fill_seed("fig2", 0, i)) for i in range(n_fills)]
+    N = specs[0].n_samples
+    sigma = 3.0 * float(np.sqrt(synth.CHANNELS))
+    xs = synth.render_many(specs)
+    x0s = [synth.render(sp, noise_sigma=0.0) for sp in specs]
+    xd, x0d = synth.to_device(xs), synth.to_device(x0s)
+    base = [daq.Fill(d, N, ped_samples=sp.ped_samples) for d, sp in zip(xd, specs)]
+    qs = [daq.alloc_q_out(f, acc=False) for f in base]
+    ctx.daq_qmethod_batch(base, qs)
+    torch.cuda.synchronize()
+    b = [int(np.median(q.qsum.cpu().numpy()[:N // daq.DAQ_Q_DECIMATION]) // daq.DAQ_Q_DECIMATION) for q in qs]
+    thr = [[int(bi - k * sigma) for k in FIG2_KS] for bi in b]
+    fills, outs = [], []
+    for raws in (xd, x0d):
+        for i, d in enumerate(raws):
+            for t in thr[i]:
+                fills.append(daq.Fill(d, N, threshold=t, pre=8, post=24, ped_samples=100))
+                outs.append(daq.alloc_out(fills[-1]))
+    ctx.daq_process_batch(fills, outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.daq_process_batch(fills, outs)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    counts = np.array([int(o.counts[0].item()) for o in outs]).reshape(2, n_fills, len(FIG2_KS))
+    found, truth = counts[0].sum(0), counts[1].sum(0)
+    res = {"workload": "Figure 2 analog: %d fills x 54 ch x 560,000 at the nominal rate, thresholds k sigma "
+                       "below each fill's baseline (sigma = %.1f ADC, the summed noise), islands found vs "
+                       "the same chop of the noiseless rendering; one launch of %d entries"
+                       % (n_fills, sigma, len(fills)),
+           "k_sigma": FIG2_KS, "found": found.tolist(), "truth": truth.tolist(),
+           "ratio": [round(float(f) / max(float(t), 1.0), 4) for f, t in zip(found, truth)],
+           "ms_per_sweep": round(ms, 3), "parity_fill0": None}
+    PENDING.append(("fig2", res, (xs[0], x0s[0], specs[0], thr[0], counts[0][0].tolist(), counts[1][0].tolist())))
+    del xd, x0d, fills, outs, base, qs
+    torch.cuda.empty_cache()
+    return res
 
 
 def ingest12_bench(daq, ctx, xs, specs, steps):
@@ -387,6 +502,8 @@ def main():
     ap.add_argument("--no-pipelined", action="store_true", help="skip the two-stream batched line")
     ap.add_argument("--no-qmethod", action="store_true", help="skip the Q-method line")
     ap.add_argument("--no-ingest", action="store_true", help="skip the 12-bit ingest line")
+    ap.add_argument("--no-compress", action="store_true", help="skip the compression line")
+    ap.add_argument("--no-fig2", action="store_true", help="skip the Figure 2 analog")
     ap.add_argument("--stress", action="store_true",
                     help="also time the whole-detector stress batch (96 calorimeter fills, 5.8 GB)")
     args = ap.parse_args()
@@ -500,17 +617,8 @@ def main():
     tot = [int(c[1]) for c in counts]
     status = [int(c[2]) & 0xFFFFFFFF for c in counts]
     assert all(s == 0 for s in status), status
-    parity = None
-    try:
-        import oracle
-        ref = oracle.chop(xs[0], n_samples=N, ped_samples=specs[0].ped_samples,
-                          threshold=specs[0].threshold, pre=specs[0].pre, post=specs[0].post)
-        isl, n, total, st, ped, out = outs[0].host()
-        parity = bool(n == ref.n_islands and total == ref.total_len and
-                      np.array_equal(isl, ref.islands) and np.array_equal(ped, ref.ped) and
-                      np.array_equal(out, ref.out))
-    except ImportError:
-        parity = None
+    main_check = {}
+    PENDING.append(("chop", main_check, (xs[0], specs[0], outs[0].host())))
 
     # ---- roofline of the fused kernel -------------------------------------------
     alg_bytes = sum(2 * C * s.n_samples for s in specs) + sum(2 * C * t for t in tot) \
@@ -585,6 +693,18 @@ def main():
         ingest = ingest12_bench(daq, ctx, xs, specs, steps=max(10, args.steps // 5))
         log("12-bit ingest: unpack %.0f GB/s of int16 samples" % ingest["raw_gbs"])
 
+    compress = None
+    if not args.no_compress:
+        log("compression of the %d chopped fills" % len(specs))
+        compress = z_bench(daq, ctx, outs, xs[0], specs[0], steps=max(10, args.steps // 2))
+        log("compression: %.0f GB/s of packed samples, ratio %.2f" % (compress["packed_gbs"], compress["ratio"]))
+
+    fig2 = None
+    if not args.no_fig2:
+        log("Figure 2 analog: threshold sweep, found vs true islands")
+        fig2 = fig2_bench(daq, synth, ctx)
+        log("Figure 2 analog: found/true %s at k = %s" % (fig2["ratio"], FIG2_KS))
+
     # ---- the other batch shapes: uneven batch, whole-detector stress -----------------
     others = {}
     if not args.no_uneven:
@@ -606,11 +726,14 @@ def main():
         serving["schedule"] = ps
         ctx.set_schedule(*sched)
 
-    # ---- CPU oracle on a bounded sample --------------------------------------------------
+    # ---- CPU oracle: parity of every line's first fill, then its rate on a bounded sample ----
     cpu = None
     if args.cpu_seconds > 0:
         try:
             import oracle
+            log("oracle checks of %d lines" % len(PENDING))
+            for kind, into, payload in PENDING:
+                into["parity_fill0"] = oracle_check(oracle, kind, payload)
             cores = min(os.cpu_count() or 1, 16)
             log("CPU oracle baseline on %d threads for ~%.0f s" % (cores, args.cpu_seconds))
             done = 0
@@ -650,11 +773,13 @@ def main():
         "plain": plain,
         "islands_per_fill": round(float(np.mean(n_isl)), 1),
         "occupancy": round(sum(tot) / (N * len(specs)), 4),
-        "parity_fill0": parity,
+        "parity_fill0": main_check.get("parity_fill0"),
         "roofline": roofline,
         "hbm_ceiling": ceil,
         "qmethod": qmethod,
         "ingest12": ingest,
+        "compress": compress,
+        "fig2_analog": fig2,
         "other_batches": others,
         "serving": serving,
         "cpu_baseline": cpu,

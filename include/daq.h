@@ -299,9 +299,10 @@ typedef struct daq_z_fill {
 } daq_z_fill;                  /* 80 bytes, device pointers                   */
 
 /* Compress n fills (host array, copied before the call returns; n = 0 is a
- * no-op), asynchronously on `stream`: a size pass, a scan and a pack pass
- * over all of them. The context keeps per-stream scratch of 8 bytes per 8
- * blocks of max_len, grown (synchronously) on first need. DAQ_EINVAL for a
+ * no-op), asynchronously on `stream`: a size pass and a pack pass over up to
+ * 16 fills at a time. The context keeps per-stream scratch of 8 bytes per
+ * wave of a launch (at most 128 KB), allocated (synchronously) on first
+ * need. DAQ_EINVAL for a
  * null pointer, a negative size, stride < max_len or reserved != 0;
  * DAQ_ERANGE past DAQ_MAX_CHANNELS / DAQ_MAX_SAMPLES; DAQ_EALIGN for packed
  * or stride as stated above, or another pointer not aligned to its type.

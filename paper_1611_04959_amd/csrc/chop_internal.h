@@ -166,15 +166,19 @@ struct ZFillDev {
     int64_t max_len;           // rows hold at most this many samples
     uint32_t *hdr;             // C * ceil(L / 64) block headers
     int64_t *offsets;          // C * ceil(L / 64) payload word offsets, or null
-    int64_t *gofs;             // scratch: one word per group of 8 blocks of a row
+    int64_t *gofs;             // scratch: payload words of each wave of the grid
     uint32_t *words;
     int64_t cap;               // words that fit
     int64_t *n_words;          // payload words of the whole stream
     int32_t C;
     int32_t pad;
 };
-// Fills per launch (the descriptors travel as kernel arguments).
+// Fills per launch (the descriptors travel as kernel arguments), waves per
+// work-group, work-groups per fill (each wave of the pack pass sums the
+// payload sizes of the waves before it: at most kZMaxGrid * kZWaves).
 constexpr int kZMaxFills = 16;
+constexpr int kZWaves = 4;
+constexpr int kZMaxGrid = 256;
 struct ZArgs {
     ZFillDev f[kZMaxFills];
     int32_t n;

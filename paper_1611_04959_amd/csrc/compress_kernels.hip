@@ -8,25 +8,34 @@
 // differences of consecutive samples as a little-endian bit stream of w bits
 // each, the blocks' payloads back to back.
 //
-// A wave takes a group of 8 consecutive blocks of one row: lane l holds the
-// 8 samples 8 l .. 8 l + 7 of the group (one 16-byte load), so block j of the
-// group is lanes 8 j .. 8 j + 7. Three kernels, each over up to kZMaxFills
-// fills (blockIdx.y): the size pass (block headers, group payload sizes), an
-// exclusive scan of the group sizes (one work-group per fill), and the pack
-// pass (block offsets; each wave ORs its codes into the group's contiguous
-// payload in LDS, then stores it with coalesced writes).
+// A wave takes groups of 8 consecutive blocks of one row: lane l holds the 8
+// samples 8 l .. 8 l + 7 of a group (one 16-byte load), so block j of the
+// group is lanes 8 j .. 8 j + 7. The groups of a fill are cut into one
+// contiguous range per wave of the grid (fill = blockIdx.y). Two kernels:
+// the size pass writes the block headers and each wave's payload words; the
+// pack pass starts each wave at the sum of the sizes of the waves before it,
+// walks its groups in order, ORs each lane's codes into the group's payload
+// in LDS (a 64-bit bit writer per lane, one atomic per 32 bits) and stores
+// the payload with coalesced writes. Every wave touches only its own LDS, so
+// there are no work-group barriers.
 #include "chop_internal.h"
 
 namespace daqk {
 namespace {
 
-constexpr int kZBlock = 64;              // samples per block
-constexpr int kZGroup = 8;               // blocks per wave
-constexpr int kZMaxWords = 34;           // ceil(63 * 17 / 32): the widest block's payload
+constexpr int kZBlock = 64;     // samples per block
+constexpr int kZGroup = 8;      // blocks per wave
+constexpr int kZMaxWords = 34;  // ceil(63 * 17 / 32): the widest block's payload
 constexpr int kZGroupWords = kZGroup * kZMaxWords;
-constexpr int kZWaves = 4;               // waves per work-group of the size and pack passes
-constexpr int kZScanThreads = 1024;
-constexpr int kZScanPer = 8;             // consecutive sizes per scan thread and round
+// Groups a wave loads before it uses them, in the size and the pack pass.
+#ifndef DAQ_Z_UNROLL
+#define DAQ_Z_UNROLL 8
+#endif
+#ifndef DAQ_Z_PACK_UNROLL
+#define DAQ_Z_PACK_UNROLL 1
+#endif
+constexpr int kZUnroll = DAQ_Z_UNROLL;
+constexpr int kZPackUnroll = DAQ_Z_PACK_UNROLL;
 
 struct ZGeom {
     int64_t L;       // samples per row
@@ -46,180 +55,225 @@ __device__ __forceinline__ ZGeom z_geom(const ZFillDev &f) {
     return g;
 }
 
-// What a lane knows of its block after reading group gi.
-struct ZLane {
-    uint32_t z[kVec];  // zigzag codes of its 8 samples (0 where there is none)
-    int16_t first;     // the block's first sample
-    int64_t b;         // the block's index in the fill (valid when n > 0)
-    int n;             // samples in the block (0: no such block)
-    uint32_t w;        // the block's bit width
-    int64_t nw;        // the block's payload words
-};
+// The contiguous range of groups of wave v of W.
+__device__ __forceinline__ void z_range(const ZGeom &g, int64_t v, int64_t W, int64_t *lo, int64_t *hi) {
+    *lo = g.groups * v / W;
+    *hi = g.groups * (v + 1) / W;
+}
 
 __device__ __forceinline__ uint32_t zigzag(int32_t r) { return ((uint32_t)r << 1) ^ (uint32_t)(r >> 31); }
 
-__device__ __forceinline__ void z_read(const ZFillDev &f, const ZGeom &g, int64_t gi, int lane, ZLane &o) {
-    const int64_t c = gi / g.gpr;
-    const int64_t kb0 = (gi - c * g.gpr) * kZGroup;  // first block of the group in its row
-    const int j = lane >> 3, sub = lane & 7;
-    const int64_t kb = kb0 + j;
-    const int64_t t0 = kb * kZBlock + sub * kVec;     // first sample of the lane
-    int32_t s[kVec];
-    if (t0 < g.L) {
-        const int4 q = *reinterpret_cast<const int4 *>(f.packed + c * f.stride + t0);
-        const int16_t *h = reinterpret_cast<const int16_t *>(&q);
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
 #pragma unroll
-        for (int e = 0; e < kVec; e++) s[e] = h[e];
-    } else {
-#pragma unroll
-        for (int e = 0; e < kVec; e++) s[e] = 0;
+    for (int d = 1; d < 64; d <<= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Where a group sits: its row and its index in the row (wave-uniform).
+struct ZAt {
+    int64_t c, gr;
+};
+
+// The lane's 8 samples of the group at `at` (zeros past the row's end).
+__device__ __forceinline__ int4 z_load(const ZFillDev &f, const ZGeom &g, ZAt at, int lane) {
+    const int64_t t0 = at.gr * (kZGroup * kZBlock) + lane * kVec;
+    if (t0 >= g.L) return make_int4(0, 0, 0, 0);
+    return *reinterpret_cast<const int4 *>(f.packed + at.c * f.stride + t0);
+}
+
+__device__ __forceinline__ void z_next(const ZGeom &g, ZAt &at) {
+    if (++at.gr == g.gpr) {
+        at.gr = 0;
+        at.c++;
     }
-    const int32_t prev = __shfl_up(s[kVec - 1], 1, 64);
-    o.n = kb < g.nb ? (int)(g.L - kb * kZBlock < kZBlock ? g.L - kb * kZBlock : kZBlock) : 0;
-    o.b = c * g.nb + kb;
-    o.first = (int16_t)__shfl(s[0], lane & ~7, 64);
-    uint32_t zmax = 0;
+}
+
+// Lane-to-lane moves within rows of 16 lanes (DPP): the value of lane l - 1
+// (lanes 16 k keep their own), and an OR over the 8 lanes of a block. The
+// moves keep the lane's own value as the fallback, which stops the compiler
+// from folding them into the arithmetic that uses them: a row shift folded
+// into a reverse subtract gave wrong differences on gfx950.
+__device__ __forceinline__ int32_t dpp_prev(int32_t v) { return __builtin_amdgcn_update_dpp(v, v, 0x111, 0xF, 0xF, false); }
+__device__ __forceinline__ uint32_t or8(uint32_t m) {
+    m |= (uint32_t)__builtin_amdgcn_update_dpp((int)m, (int)m, 0xB1, 0xF, 0xF, false);   // lanes 1 0 3 2
+    m |= (uint32_t)__builtin_amdgcn_update_dpp((int)m, (int)m, 0x4E, 0xF, 0xF, false);   // lanes 2 3 0 1
+    m |= (uint32_t)__builtin_amdgcn_update_dpp((int)m, (int)m, 0x141, 0xF, 0xF, false);  // 7 - i within 8
+    return m;
+}
+
+// Samples in the lane's block (lane >> 3 of the group at `at`): 0 past the row.
+__device__ __forceinline__ int z_block_len(const ZGeom &g, ZAt at, int lane) {
+    const int64_t left = g.L - (at.gr * kZGroup + (lane >> 3)) * kZBlock;
+    return left <= 0 ? 0 : (left < kZBlock ? (int)left : kZBlock);
+}
+
+// Zigzag codes of the lane's 8 samples, sample i = 8 sub + e of its block of
+// n samples; 0 where there is no code (i = 0 or i >= n). kFull: n = 64.
+template <bool kFull>
+__device__ __forceinline__ void z_codes(int4 q, int sub, int n, uint32_t z[kVec]) {
+    const int16_t *h = reinterpret_cast<const int16_t *>(&q);
+    int32_t s[kVec];
+#pragma unroll
+    for (int e = 0; e < kVec; e++) s[e] = h[e];
+    // lanes 16 k have no previous lane in their DPP row: they start a block
+    const int32_t prev = dpp_prev(s[kVec - 1]);
 #pragma unroll
     for (int e = 0; e < kVec; e++) {
-        const int i = sub * kVec + e;  // index in the block
-        const int32_t before = e ? s[e - 1] : prev;
-        o.z[e] = (i >= 1 && i < o.n) ? zigzag(s[e] - before) : 0u;
-        zmax = o.z[e] > zmax ? o.z[e] : zmax;
+        const uint32_t zz = zigzag(s[e] - (e ? s[e - 1] : prev));
+        const int i = sub * kVec + e;
+        if (kFull)
+            z[e] = (e == 0 && sub == 0) ? 0u : zz;
+        else
+            z[e] = (i >= 1 && i < n) ? zz : 0u;
     }
+}
+
+__device__ __forceinline__ uint32_t z_width(const uint32_t z[kVec]) {
+    uint32_t m = 0;
 #pragma unroll
-    for (int d = 1; d < 8; d <<= 1) {
-        const uint32_t u = __shfl_xor(zmax, d, 64);
-        zmax = u > zmax ? u : zmax;
-    }
-    o.w = zmax ? 32u - (uint32_t)__clz(zmax) : 0u;
-    o.nw = o.n > 0 ? ((int64_t)(o.n - 1) * o.w + 31) / 32 : 0;
+    for (int e = 0; e < kVec; e++) m |= z[e];
+    m = or8(m);  // the bit length of the OR is that of the largest code
+    return m ? 32u - (uint32_t)__clz(m) : 0u;
+}
+
+__device__ __forceinline__ uint32_t z_words(int n, uint32_t w) {
+    return n > 0 ? ((uint32_t)(n - 1) * w + 31u) >> 5 : 0u;
 }
 
 __global__ void __launch_bounds__(kZWaves * 64) k_z_size(ZArgs a) {
     const ZFillDev &f = a.f[blockIdx.y];
     const ZGeom g = z_geom(f);
-    const int lane = threadIdx.x & 63;
-    const int64_t waves = (int64_t)gridDim.x * kZWaves;
-    for (int64_t gi = (int64_t)blockIdx.x * kZWaves + (threadIdx.x >> 6); gi < g.groups; gi += waves) {
-        ZLane o;
-        z_read(f, g, gi, lane, o);
-        if ((lane & 7) == 0 && o.n > 0) f.hdr[o.b] = (uint32_t)(uint16_t)o.first | (o.w << 16);
-        int64_t tot = o.nw;  // the same on the 8 lanes of a block: sum over blocks
+    const int lane = threadIdx.x & 63, sub = lane & 7;
+    const int64_t W = (int64_t)gridDim.x * kZWaves;
+    const int64_t v = (int64_t)blockIdx.x * kZWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int64_t lo, hi;
+    z_range(g, v, W, &lo, &hi);
+    ZAt at;
+    at.c = g.gpr ? lo / g.gpr : 0;
+    at.gr = lo - at.c * g.gpr;
+    int64_t mine = 0;  // payload words of the lane's blocks (on each block's first lane)
+    for (int64_t g0 = lo; g0 < hi; g0 += kZUnroll) {
+        int4 q[kZUnroll];
+        ZAt ats[kZUnroll];
 #pragma unroll
-        for (int d = 8; d < 64; d <<= 1) tot += __shfl_xor(tot, d, 64);
-        if (lane == 0) f.gofs[gi] = tot;
+        for (int u = 0; u < kZUnroll; u++) {
+            ats[u] = at;
+            q[u] = g0 + u < hi ? z_load(f, g, at, lane) : make_int4(0, 0, 0, 0);
+            z_next(g, at);
+        }
+#pragma unroll
+        for (int u = 0; u < kZUnroll; u++) {
+            if (g0 + u >= hi) break;
+            const bool full = (ats[u].gr + 1) * (kZGroup * kZBlock) <= g.L;
+            const int n = full ? kZBlock : z_block_len(g, ats[u], lane);
+            uint32_t z[kVec];
+            if (full)
+                z_codes<true>(q[u], sub, n, z);
+            else
+                z_codes<false>(q[u], sub, n, z);
+            const uint32_t w = z_width(z);
+            if (sub == 0 && n > 0) {
+                f.hdr[ats[u].c * g.nb + ats[u].gr * kZGroup + (lane >> 3)] = ((uint32_t)q[u].x & 0xFFFFu) | (w << 16);
+                mine += z_words(n, w);
+            }
+        }
     }
+    const int64_t tot = wave_sum_i64(mine);
+    if (lane == 0) f.gofs[v] = tot;
 }
 
-// Exclusive scan of fill blockIdx.y's group sizes in place, in rounds of
-// kZScanThreads * kZScanPer sizes staged through LDS; the total goes to
-// *n_words.
-__global__ void __launch_bounds__(kZScanThreads) k_z_scan(ZArgs a) {
-    constexpr int kRound = kZScanThreads * kZScanPer;
-    __shared__ int64_t s_v[kRound];
-    __shared__ int64_t s_w[kZScanThreads / 64];
-    const ZFillDev &f = a.f[blockIdx.y];
-    const ZGeom g = z_geom(f);
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    int64_t carry = 0;
-    for (int64_t base = 0; base < g.groups; base += kRound) {
-        for (int j = tid; j < kRound; j += kZScanThreads) s_v[j] = base + j < g.groups ? f.gofs[base + j] : 0;
-        __syncthreads();
-        int64_t v[kZScanPer], mine = 0;
-#pragma unroll
-        for (int j = 0; j < kZScanPer; j++) {
-            v[j] = s_v[tid * kZScanPer + j];
-            mine += v[j];
-        }
-        int64_t inc = mine;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int64_t u = __shfl_up(inc, d, 64);
-            if (lane >= d) inc += u;
-        }
-        if (lane == 63) s_w[wid] = inc;
-        __syncthreads();
-        int64_t before = carry, all = carry;
-        for (int w = 0; w < kZScanThreads / 64; w++) {
-            before += w < wid ? s_w[w] : 0;
-            all += s_w[w];
-        }
-        int64_t run = before + inc - mine;
-#pragma unroll
-        for (int j = 0; j < kZScanPer; j++) {
-            s_v[tid * kZScanPer + j] = run;
-            run += v[j];
-        }
-        __syncthreads();
-        for (int j = tid; j < kRound; j += kZScanThreads)
-            if (base + j < g.groups) f.gofs[base + j] = s_v[j];
-        carry = all;
-        __syncthreads();
-    }
-    if (tid == 0) *f.n_words = carry;
+// Ordering of one wave's own LDS accesses (clear, OR, read back, clear).
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 }
 
-// The loop bound is uniform over the work-group (kZWaves consecutive
-// groups), so every wave reaches the barriers.
 __global__ void __launch_bounds__(kZWaves * 64) k_z_pack(ZArgs a) {
     __shared__ uint32_t s_words[kZWaves][kZGroupWords + 2];
     const ZFillDev &f = a.f[blockIdx.y];
     const ZGeom g = z_geom(f);
     const int lane = threadIdx.x & 63;
-    const int wl = threadIdx.x >> 6;
+    const int sub = lane & 7, jb = lane >> 3;
+    const int wl = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t *acc = s_words[wl];
-    const int64_t step = (int64_t)gridDim.x * kZWaves;
-    for (int64_t g0 = (int64_t)blockIdx.x * kZWaves; g0 < g.groups; g0 += step) {
-        const int64_t gi = g0 + wl;
-        const bool live = gi < g.groups;
-        ZLane o;
-        if (live) {
-            z_read(f, g, gi, lane, o);
-        } else {
-            o.n = 0;
-            o.nw = 0;
-            o.w = 0;
-        }
-        // exclusive prefix of the payload sizes over the group's blocks
-        int64_t inc = o.nw;
+    const int64_t W = (int64_t)gridDim.x * kZWaves;
+    const int64_t v = (int64_t)blockIdx.x * kZWaves + wl;
+    int64_t lo, hi;
+    z_range(g, v, W, &lo, &hi);
+    // where this wave's payload starts: the sizes of the waves before it
+    int64_t before = 0;
 #pragma unroll
-        for (int d = 8; d < 64; d <<= 1) {
-            const int64_t u = __shfl_up(inc, d, 64);
-            if (lane >= d) inc += u;
+    for (int r = 0; r < kZMaxGrid * kZWaves / 64; r++) {
+        const int64_t k = lane + 64 * r;
+        if (k < v) before += f.gofs[k];
+    }
+    int64_t carry = wave_sum_i64(before);
+    ZAt at;
+    at.c = g.gpr ? lo / g.gpr : 0;
+    at.gr = lo - at.c * g.gpr;
+    for (int64_t g0 = lo; g0 < hi; g0 += kZPackUnroll) {
+        int4 q[kZPackUnroll];
+        uint32_t hw[kZPackUnroll];
+        ZAt ats[kZPackUnroll];
+#pragma unroll
+        for (int u = 0; u < kZPackUnroll; u++) {
+            ats[u] = at;
+            const int64_t kb = at.gr * kZGroup + jb;
+            q[u] = g0 + u < hi ? z_load(f, g, at, lane) : make_int4(0, 0, 0, 0);
+            hw[u] = (g0 + u < hi && kb < g.nb) ? f.hdr[at.c * g.nb + kb] : 0u;
+            z_next(g, at);
         }
-        const int64_t base = inc - o.nw;                 // words before this block in the group
-        const int64_t total = __shfl(inc, 63, 64);       // the group's payload words
-        const int64_t start = live ? f.gofs[gi] : 0;
-        if (live && f.offsets && (lane & 7) == 0 && o.n > 0) f.offsets[o.b] = start + base;
-        for (int k = lane; k < kZGroupWords + 2; k += 64) acc[k] = 0u;
-        __syncthreads();
-        if (o.w > 0) {
+#pragma unroll
+        for (int u = 0; u < kZPackUnroll; u++) {
+            if (g0 + u >= hi) break;
+            const bool full = (ats[u].gr + 1) * (kZGroup * kZBlock) <= g.L;
+            const int n = full ? kZBlock : z_block_len(g, ats[u], lane);
+            uint32_t z[kVec];
+            if (full)
+                z_codes<true>(q[u], sub, n, z);
+            else
+                z_codes<false>(q[u], sub, n, z);
+            const uint32_t w = hw[u] >> 16;
+            const uint32_t nw = z_words(n, w);
+            // the group's blocks' payload sizes: where the lane's block starts, and the total
+            uint32_t base = 0, total = 0;
+#pragma unroll
+            for (int j = 0; j < kZGroup; j++) {
+                const uint32_t t = (uint32_t)__builtin_amdgcn_readlane((int)nw, 8 * j);
+                base += j < jb ? t : 0u;
+                total += t;
+            }
+            if (f.offsets && sub == 0 && n > 0)
+                f.offsets[ats[u].c * g.nb + ats[u].gr * kZGroup + jb] = carry + base;
+            for (uint32_t k = lane; k < total; k += 64) acc[k] = 0u;
+            wave_lds_order();
+            // code i of the block sits at bit (i - 1) w of its payload
 #pragma unroll
             for (int e = 0; e < kVec; e++) {
-                const int i = (lane & 7) * kVec + e;
-                if (i >= 1 && i < o.n) {
-                    const uint32_t p = (uint32_t)base * 32u + (uint32_t)(i - 1) * o.w;
-                    const uint32_t jw = p >> 5, s = p & 31u;
-                    atomicOr(&acc[jw], o.z[e] << s);
-                    if (s + o.w > 32u) atomicOr(&acc[jw + 1], o.z[e] >> (32u - s));
+                if (z[e]) {
+                    const uint32_t pos = base * 32u + (uint32_t)(sub * kVec + e - 1) * w;
+                    const uint64_t val = (uint64_t)z[e] << (pos & 31u);
+                    atomicOr(&acc[pos >> 5], (uint32_t)val);
+                    if ((uint32_t)(val >> 32)) atomicOr(&acc[(pos >> 5) + 1], (uint32_t)(val >> 32));
                 }
             }
+            wave_lds_order();
+            for (uint32_t k = lane; k < total; k += 64) {
+                const int64_t at_w = carry + k;
+                if (at_w < f.cap) f.words[at_w] = acc[k];
+            }
+            wave_lds_order();
+            carry += total;
         }
-        __syncthreads();
-        for (int k = lane; k < total; k += 64) {
-            const int64_t at = start + k;
-            if (at < f.cap) f.words[at] = acc[k];
-        }
-        __syncthreads();
     }
+    if (v == W - 1 && lane == 0) *f.n_words = carry;
 }
 
 }  // namespace
 
 hipError_t launch_z(const ZArgs &a, int grid, hipStream_t s) {
-    if (a.n < 1 || a.n > kZMaxFills) return hipErrorInvalidValue;
+    if (a.n < 1 || a.n > kZMaxFills || grid < 1 || grid > kZMaxGrid) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_z_size, dim3(grid, a.n), dim3(kZWaves * 64), 0, s, a);
-    hipLaunchKernelGGL(k_z_scan, dim3(1, a.n), dim3(kZScanThreads), 0, s, a);
     hipLaunchKernelGGL(k_z_pack, dim3(grid, a.n), dim3(kZWaves * 64), 0, s, a);
     return hipGetLastError();
 }

@@ -934,11 +934,22 @@ int daq_compress_batch(daq_ctx *ctx, const daq_z_fill *fills, int32_t n, void *s
     if (!ctx || n < 0 || (n > 0 && !fills)) return DAQ_EINVAL;
     if (n == 0) return DAQ_OK;
     const hipStream_t stream = (hipStream_t)stream_;
-    int64_t need = 0;
     for (int32_t i = 0; i < n; i++) {
         const int rc = check_z_fill(fills[i]);
         if (rc) return rc;
-        need += z_groups(fills[i]);
+    }
+    // Work-groups per fill of each launch: the resident count (8 per CU)
+    // shared by its fills, at most kZMaxGrid, fewer for short streams.
+    auto grid_of = [&](int32_t i0, int32_t m) {
+        int64_t most = 1;
+        for (int32_t j = 0; j < m; j++) most = std::max(most, z_groups(fills[i0 + j]));
+        const int64_t wide = std::min<int64_t>(daqk::kZMaxGrid, std::max<int64_t>(1, (int64_t)8 * ctx->n_cu / m));
+        return (int)std::max<int64_t>(1, std::min<int64_t>(wide, (most + daqk::kZWaves - 1) / daqk::kZWaves));
+    };
+    int64_t need = 0;  // one word per wave of a launch (launches run in stream order)
+    for (int32_t i0 = 0; i0 < n; i0 += daqk::kZMaxFills) {
+        const int32_t m = std::min<int32_t>(n - i0, daqk::kZMaxFills);
+        need = std::max<int64_t>(need, (int64_t)m * grid_of(i0, m) * daqk::kZWaves);
     }
     DeviceGuard guard(ctx->device);
     Scratch *s = scratch_for(ctx, stream);
@@ -947,15 +958,19 @@ int daq_compress_batch(daq_ctx *ctx, const daq_z_fill *fills, int32_t n, void *s
         (void)hipFree(s->z_gofs);
         s->z_gofs = nullptr;
         s->z_gofs_cap = 0;
-        const int64_t cap = std::max<int64_t>(need + need / 2, 4096);
+        const int64_t cap = std::max<int64_t>(need, 4096);
         HIP_TRY(hipMalloc(&s->z_gofs, (size_t)cap * sizeof(int64_t)));
         s->z_gofs_cap = cap;
     }
-    int64_t at = 0;
+    size_t slot = 0;
+    if (ctx->timing) {
+        const int rc = timing_begin(ctx, stream, &slot);
+        if (rc) return rc;
+    }
     for (int32_t i0 = 0; i0 < n; i0 += daqk::kZMaxFills) {
         daqk::ZArgs a{};
         a.n = std::min<int32_t>(n - i0, daqk::kZMaxFills);
-        int64_t part_most = 1;
+        const int grid = grid_of(i0, a.n);
         for (int32_t j = 0; j < a.n; j++) {
             const daq_z_fill &z = fills[i0 + j];
             daqk::ZFillDev &d = a.f[j];
@@ -965,19 +980,15 @@ int daq_compress_batch(daq_ctx *ctx, const daq_z_fill *fills, int32_t n, void *s
             d.max_len = z.max_len;
             d.hdr = z.hdr;
             d.offsets = z.offsets;
-            d.gofs = s->z_gofs + at;
+            d.gofs = s->z_gofs + (int64_t)j * grid * daqk::kZWaves;
             d.words = z.words;
             d.cap = z.words_cap;
             d.n_words = z.n_words;
             d.C = z.n_channels;
-            at += z_groups(z);
-            part_most = std::max(part_most, z_groups(z));
         }
-        // Resident work-groups of four waves: 8 per CU, shared by the fills.
-        const int64_t wide = std::max<int64_t>(1, (int64_t)8 * ctx->n_cu / a.n);
-        const int grid = (int)std::min<int64_t>(wide, (part_most + 3) / 4);
-        HIP_TRY(daqk::launch_z(a, std::max(grid, 1), stream));
+        HIP_TRY(daqk::launch_z(a, grid, stream));
     }
+    if (ctx->timing) return timing_end(ctx, stream, slot);
     return DAQ_OK;
 }
 
