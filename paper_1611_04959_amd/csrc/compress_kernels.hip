@@ -45,8 +45,16 @@ struct ZGeom {
 };
 
 // Samples each row of fill f compresses: its total_len, clamped to [0, max_len].
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// (The length comes from a vector load: taking it through readfirstlane lets
+// the compiler keep the whole geometry in scalar registers.)
 __device__ __forceinline__ ZGeom z_geom(const ZFillDev &f) {
-    const int64_t tl = *reinterpret_cast<const volatile int64_t *>(&f.counts->total_len);
+    const int64_t tl = uniform_i64(*reinterpret_cast<const volatile int64_t *>(&f.counts->total_len));
     ZGeom g;
     g.L = tl < f.max_len ? (tl > 0 ? tl : 0) : f.max_len;
     g.nb = (g.L + kZBlock - 1) / kZBlock;
@@ -207,7 +215,7 @@ __global__ void __launch_bounds__(kZWaves * 64) k_z_pack(ZArgs a) {
         const int64_t k = lane + 64 * r;
         if (k < v) before += f.gofs[k];
     }
-    int64_t carry = wave_sum_i64(before);
+    int64_t carry = uniform_i64(wave_sum_i64(before));
     ZAt at;
     at.c = g.gpr ? lo / g.gpr : 0;
     at.gr = lo - at.c * g.gpr;
