@@ -148,3 +148,22 @@ def test_header_constants_match_the_binding():
         assert hasattr(daq, name), name
     assert checked >= 10
 
+
+def test_compress_descriptor_and_word_bound():
+    """daq_z_fill is the 80-byte record the header states; the binding's word
+    bound (34 per block) is what the widest block needs: 63 codes of 17 bits,
+    which the oracle's encoder reaches on alternating int16 extremes."""
+    import numpy as np
+    import oracle
+    assert ctypes.sizeof(daq.daq_z_fill) == 80
+    x = np.where(np.arange(128) % 2, 32767, -32768).astype(np.int16)[None, :]
+    hdr, words = oracle.z_compress(x)
+    assert (hdr >> 16).tolist() == [daq.DAQ_Z_MAX_WIDTH] * 2
+    assert len(words) == daq.z_words_bound(1, 128) == 68
+
+
+def test_compress_rejects_bad_arguments_without_touching_a_gpu():
+    lib = daq.load_library()
+    assert lib.daq_compress_batch(None, None, 0, None) == daq.DAQ_EINVAL
+    z = daq.daq_z_fill(0x1000, 8, 0x2000, 8, 0x3000, None, 0x4000, 16, 0x5000, 1, 0)
+    assert lib.daq_compress_batch(None, (daq.daq_z_fill * 1)(z), 1, None) == daq.DAQ_EINVAL
