@@ -255,14 +255,30 @@ __global__ void __launch_bounds__(kZWaves * 64) k_z_pack(ZArgs a) {
                 f.offsets[ats[u].c * g.nb + ats[u].gr * kZGroup + jb] = carry + base;
             for (uint32_t k = lane; k < total; k += 64) acc[k] = 0u;
             wave_lds_order();
-            // code i of the block sits at bit (i - 1) w of its payload
+            // code i of the block sits at bit (i - 1) w of its payload; up to
+            // 16 bits wide, two neighbouring codes go in with one OR pair
+            if (w <= 16) {
 #pragma unroll
-            for (int e = 0; e < kVec; e++) {
-                if (z[e]) {
-                    const uint32_t pos = base * 32u + (uint32_t)(sub * kVec + e - 1) * w;
-                    const uint64_t val = (uint64_t)z[e] << (pos & 31u);
-                    atomicOr(&acc[pos >> 5], (uint32_t)val);
-                    if ((uint32_t)(val >> 32)) atomicOr(&acc[(pos >> 5) + 1], (uint32_t)(val >> 32));
+                for (int m = 0; m < kVec / 2; m++) {
+                    // the lane's first pair on a block's first lane is code 1 alone
+                    const bool lead = sub == 0 && m == 0;
+                    const uint32_t pv = lead ? z[1] : (z[2 * m] | (z[2 * m + 1] << w));
+                    if (pv) {
+                        const uint32_t pos = base * 32u + (uint32_t)(lead ? 0 : sub * kVec + 2 * m - 1) * w;
+                        const uint64_t val = (uint64_t)pv << (pos & 31u);
+                        atomicOr(&acc[pos >> 5], (uint32_t)val);
+                        if ((uint32_t)(val >> 32)) atomicOr(&acc[(pos >> 5) + 1], (uint32_t)(val >> 32));
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < kVec; e++) {
+                    if (z[e]) {
+                        const uint32_t pos = base * 32u + (uint32_t)(sub * kVec + e - 1) * w;
+                        const uint64_t val = (uint64_t)z[e] << (pos & 31u);
+                        atomicOr(&acc[pos >> 5], (uint32_t)val);
+                        if ((uint32_t)(val >> 32)) atomicOr(&acc[(pos >> 5) + 1], (uint32_t)(val >> 32));
+                    }
                 }
             }
             wave_lds_order();
