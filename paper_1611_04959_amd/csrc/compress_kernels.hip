@@ -29,10 +29,10 @@ constexpr int kZMaxWords = 34;  // ceil(63 * 17 / 32): the widest block's payloa
 constexpr int kZGroupWords = kZGroup * kZMaxWords;
 // Groups a wave loads before it uses them, in the size and the pack pass.
 #ifndef DAQ_Z_UNROLL
-#define DAQ_Z_UNROLL 8
+#define DAQ_Z_UNROLL 4
 #endif
 #ifndef DAQ_Z_PACK_UNROLL
-#define DAQ_Z_PACK_UNROLL 1
+#define DAQ_Z_PACK_UNROLL 2
 #endif
 constexpr int kZUnroll = DAQ_Z_UNROLL;
 constexpr int kZPackUnroll = DAQ_Z_PACK_UNROLL;
