@@ -3,8 +3,9 @@ against the CPU oracle, bit-exact: block headers, payload words, stream
 length and block offsets, over ragged row lengths (short last blocks, rows of
 one sample, empty streams), extreme differences (17-bit codes), flat rows
 (empty payloads), batches past one launch's fill count, a cut-short stream,
-max_len clamping, argument errors, and the 16-fill workload chopped on the
-device and then compressed, decoded back to the oracle's packed samples."""
+max_len clamping, argument errors, 40 fills of random shape in one call, and
+the 16-fill workload chopped on the device and then compressed, decoded back
+to the oracle's packed samples."""
 import numpy as np
 import pytest
 
@@ -225,3 +226,25 @@ def test_workload_16_fills_chopped_then_compressed(ctx):
     ratio = raw_words / sum(int(z.n_words.item()) for z in zouts)
     log("compression ratio %.2f" % ratio)
     assert ratio > 1.5
+
+
+def test_random_shapes_in_one_call(ctx):
+    """40 fills of random shape and content in one call (three launches):
+    channel counts 1..70, lengths 0..5000, padded strides, max_len above the
+    length, and a mix of the row kinds above."""
+    rng = np.random.default_rng(2024)
+    xs, Ls, outs, zouts = [], [], [], []
+    kinds = ["noise", "wide", "flat", "mixed"]
+    for i in range(40):
+        C, L = int(rng.integers(1, 71)), int(rng.integers(0, 5001))
+        x = rows(5000 + i, C, L, kinds[int(rng.integers(0, 4))])
+        o = packed_out(x, L, extra=8 * int(rng.integers(0, 3)))
+        xs.append(x)
+        Ls.append(L)
+        outs.append(o)
+        zouts.append(daq.alloc_z_out(C, int(o.out.shape[1]), offsets=bool(i % 3), device="cuda"))
+    log("compress 40 random fills")
+    ctx.daq_compress_batch(outs, zouts)
+    torch.cuda.synchronize()
+    for i in range(40):
+        check(zouts[i], xs[i], Ls[i], "random fill %d (C=%d L=%d)" % (i, xs[i].shape[0], Ls[i]))
