@@ -167,3 +167,13 @@ def test_compress_rejects_bad_arguments_without_touching_a_gpu():
     assert lib.daq_compress_batch(None, None, 0, None) == daq.DAQ_EINVAL
     z = daq.daq_z_fill(0x1000, 8, 0x2000, 8, 0x3000, None, 0x4000, 16, 0x5000, 1, 0)
     assert lib.daq_compress_batch(None, (daq.daq_z_fill * 1)(z), 1, None) == daq.DAQ_EINVAL
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """Without the built library the binding raises instead of falling back."""
+    monkeypatch.setattr(daq, "LIB_PATH", str(tmp_path / "libdaqisland.so"))
+    monkeypatch.setattr(daq, "_lib", None)
+    with pytest.raises(ImportError):
+        daq.load_library()
+    with pytest.raises(ImportError):
+        daq.Context(0)
