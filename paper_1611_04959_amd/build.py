@@ -40,5 +40,26 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+C_CLIENT_SRC = os.path.join(ROOT, "tests", "native", "c_client.c")
+C_CLIENT = os.path.join(ROOT, "tests", "native", "c_client")
+
+
+def build_c_client(verbose: bool = False) -> str:
+    """The plain C client of include/daq.h used by the tests (gcc, C11, HIP's C
+    runtime API), linked against the library built above."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cmd = ["gcc", "-std=c11", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(rocm, "include"),
+           "-I", os.path.join(ROOT, "include"), C_CLIENT_SRC, "-L", HERE, "-ldaqisland",
+           "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-Wl,-rpath,$ORIGIN/../../paper_1611_04959_amd",
+           "-Wl,-rpath," + os.path.join(rocm, "lib"), "-o", C_CLIENT]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("gcc failed:\n" + r.stderr)
+    return C_CLIENT
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_c_client(verbose=True))
