@@ -208,6 +208,16 @@ def oracle_check(oracle, kind, payload) -> bool:
         x, x0, sp, thrs, found, truth = payload
         want = [[chop(h, dataclasses.replace(sp, threshold=t)).n_islands for t in thrs] for h in (x, x0)]
         return want == [list(found), list(truth)]
+    if kind == "tq":
+        x, sp, k, (isl, n, total, st, ped, out), qsum, acc = payload
+        ref = chop(x, sp)
+        N = sp.n_samples
+        qped, Q = oracle.qmethod(x, N, ped_samples=sp.ped_samples)
+        want = (k * (x[:, :N].astype(np.int64) - qped[:, None].astype(np.int64))) % 2**32
+        return bool(n == ref.n_islands and total == ref.total_len and st == 0 and
+                    np.array_equal(isl, ref.islands) and np.array_equal(ped, ref.ped) and
+                    np.array_equal(out, ref.out) and np.array_equal(qsum, Q) and
+                    np.array_equal(want, acc.astype(np.int64) % 2**32))
     if kind == "compress":
         x, sp, hdr, words = payload
         ref = chop(x, sp)
@@ -307,6 +317,59 @@ def fig2_bench(daq, synth, ctx, n_fills=16):
     del xd, x0d, fills, outs, base, qs
     torch.cuda.empty_cache()
     return res
+
+
+def tq_bench(daq, ctx, xs, fills, specs, steps, warmup=2):
+    """Both methods on the 16 fills: one daq_process_batch_q call (the Q-method inside the chop's
+    scan pass, one read of the raw samples) against daq_process_batch then daq_qmethod_batch."""
+    import numpy as np
+    import torch
+    outs = [daq.alloc_out(f) for f in fills]
+    qs = [daq.alloc_q_out(f) for f in fills]
+    for q in qs:
+        q.ped = None
+    outs2 = [daq.alloc_out(f) for f in fills]
+    qs2 = [daq.alloc_q_out(f) for f in fills]
+
+    def fused():
+        ctx.daq_process_batch_q(fills, outs, qs)
+
+    def separate():
+        ctx.daq_process_batch(fills, outs2)
+        ctx.daq_qmethod_batch(fills, qs2)
+
+    res = {}
+    for name, fn in (("fused", fused), ("separate", separate)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / steps
+    tot = [int(o.counts[1].item()) for o in outs]
+    n_isl = [int(o.counts[0].item()) for o in outs]
+    C = xs[0].shape[0]
+    raw = sum(s.raw_bytes for s in specs)
+    acc_bytes = sum(2 * 4 * s.n_samples * x.shape[0] for s, x in zip(specs, xs))
+    alg = raw + acc_bytes + sum(8 * ((s.n_samples + 31) // 32) for s in specs) + sum(2 * C * t for t in tot) \
+        + sum(24 * n for n in n_isl)
+    out = {"workload": "T-method and Q-method on the same %d fills: daq_process_batch_q (one read of the raw "
+                       "samples) against daq_process_batch followed by daq_qmethod_batch" % len(fills),
+           "steps": steps, "fused_ms": round(res["fused"], 4), "separate_ms": round(res["separate"], 4),
+           "speedup": round(res["separate"] / res["fused"], 3),
+           "fused_algorithmic_gbs": round(alg / res["fused"] / 1e6, 1),
+           "fused_pct_hbm_peak": round(100 * alg / res["fused"] / 1e6 / HBM_PEAK_GBS, 2),
+           "algorithmic_bytes_per_call": alg, "parity_fill0": None}
+    k = warmup + steps
+    PENDING.append(("tq", out, (xs[0], specs[0], k, outs[0].host(), qs[0].qsum.cpu().numpy(),
+                                qs[0].acc[:, :specs[0].n_samples].cpu().numpy())))
+    del outs, qs, outs2, qs2
+    torch.cuda.empty_cache()
+    return out
 
 
 def ingest12_bench(daq, ctx, xs, specs, steps):
@@ -504,6 +567,7 @@ def main():
     ap.add_argument("--no-ingest", action="store_true", help="skip the 12-bit ingest line")
     ap.add_argument("--no-compress", action="store_true", help="skip the compression line")
     ap.add_argument("--no-fig2", action="store_true", help="skip the Figure 2 analog")
+    ap.add_argument("--no-tq", action="store_true", help="skip the fused T-method + Q-method line")
     ap.add_argument("--stress", action="store_true",
                     help="also time the whole-detector stress batch (96 calorimeter fills, 5.8 GB)")
     args = ap.parse_args()
@@ -687,6 +751,12 @@ def main():
         qmethod = q_bench(daq, ctx, xs, fills, specs, steps=max(10, args.steps // 2), warmup=3)
         log("Q-method: %.1f GB/s raw, %.0f GB/s algorithmic" % (qmethod["raw_gbs"], qmethod["roofline"]["achieved"]))
 
+    tq = None
+    if not args.no_tq:
+        log("T-method and Q-method in one pass on the %d fills" % len(specs))
+        tq = tq_bench(daq, ctx, xs, fills, specs, steps=max(10, args.steps // 2))
+        log("T+Q: fused %.3f ms, separate %.3f ms" % (tq["fused_ms"], tq["separate_ms"]))
+
     ingest = None
     if not args.no_ingest:
         log("12-bit ingest of the %d fills" % len(specs))
@@ -777,6 +847,7 @@ def main():
         "roofline": roofline,
         "hbm_ceiling": ceil,
         "qmethod": qmethod,
+        "tq_fused": tq,
         "ingest12": ingest,
         "compress": compress,
         "fig2_analog": fig2,

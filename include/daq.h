@@ -243,6 +243,17 @@ typedef struct daq_q_out {
 int daq_qmethod_batch(daq_ctx *ctx, const daq_fill *fills,
                       const daq_q_out *outs, int32_t n, void *stream);
 
+/* Both methods on one read: daq_process_batch's T-method results in outs and
+ * the Q-method's in qouts (as daq_qmethod_batch computes them), the sums and
+ * accumulator updates taken inside the chop's scan pass, so the raw samples
+ * are read once for both. Runs the split schedule whatever the context's
+ * (plain launches, no graph). The pedestals go to outs[i].ped or, when that
+ * is NULL, to qouts[i].ped (DAQ_EINVAL if both are set). Errors as for both
+ * calls. */
+int daq_process_batch_q(daq_ctx *ctx, const daq_fill *fills,
+                        const daq_fill_out *outs, const daq_q_out *qouts,
+                        int32_t n, void *stream);
+
 /* ---- 12-bit ingest ---------------------------------------------------------
  * The digitizers deliver 12-bit samples (Section 3); the frontend unpacks them
  * before a fill is copied to the GPU. Here the packed words can be copied

@@ -142,6 +142,8 @@ def load_library():
         "daq_qmethod_batch": ([vp, ctypes.POINTER(daq_fill), ctypes.POINTER(daq_q_out), i32, vp],
                               ctypes.c_int),
         "daq_unpack12": ([vp, vp, i64, i32, i64, vp, i64, vp], ctypes.c_int),
+        "daq_process_batch_q": ([vp, ctypes.POINTER(daq_fill), ctypes.POINTER(daq_fill_out),
+                                 ctypes.POINTER(daq_q_out), i32, vp], ctypes.c_int),
         "daq_compress_batch": ([vp, ctypes.POINTER(daq_z_fill), i32, vp], ctypes.c_int),
         "daq_packed12_stride": ([i64], i64),
         "daq_ctx_set_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
@@ -397,6 +399,18 @@ class Context:
             qa[i] = q.c_struct()
         _check(self._lib.daq_qmethod_batch(self.handle, fa, qa, n, _stream_handle(stream)),
                "daq_qmethod_batch")
+
+    def daq_process_batch_q(self, fills: Sequence[Fill], outs: Sequence[FillOut], qouts: Sequence[QOut],
+                            stream=None):
+        """The T-method (outs) and the Q-method (qouts) on one read of the raw samples."""
+        fa, oa, n = self._arrays(fills, outs)
+        if len(qouts) != n:
+            raise ValueError("fills and qouts differ in length")
+        qa = (daq_q_out * max(n, 1))()
+        for i, q in enumerate(qouts):
+            qa[i] = q.c_struct()
+        _check(self._lib.daq_process_batch_q(self.handle, fa, oa, qa, n, _stream_handle(stream)),
+               "daq_process_batch_q")
 
     def daq_unpack12(self, packed, n_samples: int, raw, stream=None):
         """packed: uint8 [C, packed_stride] on the device; raw: int16 [C, row_stride] (written)."""

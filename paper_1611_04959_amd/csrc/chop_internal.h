@@ -102,6 +102,8 @@ struct KArgs {
     int64_t copy_slots;    // split variant, when hdr is null
     int32_t part, parts;   // split variant: this launch covers fill group `part`
                            // of `parts` equal groups of the batch
+    int32_t q_fused;       // split variant: the scan pass also runs the Q-method
+    int32_t pad_q;
     FillDev one;
 };
 

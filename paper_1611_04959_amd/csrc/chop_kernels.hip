@@ -175,6 +175,109 @@ __device__ __forceinline__ void store16(int16_t *p, const uint4 v) {
     __builtin_nontemporal_store(w, (DAQ_GLOBAL u32x4 *)p);
 }
 
+constexpr int kQBin = 32;  // samples per decimated bin (Table 2: 560k / 17.5k)
+
+__device__ __forceinline__ void store16_i32(int32_t *p, const uint4 v, bool stream) {
+    u32x4 w;
+    w.x = v.x;
+    w.y = v.y;
+    w.z = v.z;
+    w.w = v.w;
+    if (stream) __builtin_nontemporal_store(w, (DAQ_GLOBAL u32x4 *)p);
+    else *(DAQ_GLOBAL u32x4 *)p = w;
+}
+
+// The same with the Q-method on the read (Section 3, Q-method paragraph;
+// Table 2, decimation and fill-by-fill rows): an owner thread also adds
+// x - ped[c] to the fill's accumulator rows for its 8 samples and returns the
+// pedestal-subtracted calorimeter sum of its valid samples in *gsum. Every
+// load of a round (raw rows, pedestals, accumulator rows) is issued before
+// the round's first store.
+template <int R, bool STREAM>
+__device__ uint32_t group_flags_q(const FillDev &fd, int64_t p, int32_t thr_eff, int64_t valid, bool owner,
+                                  int64_t ped_total, int64_t *gsum) {
+    auto ld = [](const int16_t *q) { return STREAM ? load16_stream(q) : load16(q); };
+    const int16_t *xr = fd.raw + p;
+    int32_t *ar = (owner && fd.acc != nullptr) ? fd.acc + p : nullptr;
+    const bool full = valid >= kVec;
+    const int nv = full ? kVec : (int)valid;
+    int32_t s[kVec] = {0, 0, 0, 0, 0, 0, 0, 0};
+    auto update = [&](int c, const uint4 v, const u32x4 a0, const u32x4 a1, int32_t pc) {
+        int32_t *row = ar + (int64_t)c * fd.acc_stride;
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+        uint32_t d[kVec];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            d[2 * k] = (uint32_t)((int32_t)(int16_t)(w[k] & 0xFFFFu) - pc);
+            d[2 * k + 1] = (uint32_t)((int32_t)(int16_t)(w[k] >> 16) - pc);
+        }
+        if (full) {
+            store16_i32(row, make_uint4(a0.x + d[0], a0.y + d[1], a0.z + d[2], a0.w + d[3]), STREAM);
+            store16_i32(row + 4, make_uint4(a1.x + d[4], a1.y + d[5], a1.z + d[6], a1.w + d[7]), STREAM);
+        } else {
+            for (int k = 0; k < nv; k++) gbl(row)[k] = (int32_t)((uint32_t)gbl(row)[k] + d[k]);
+        }
+    };
+    auto load_acc = [&](int c, u32x4 &a0, u32x4 &a1, int32_t &pc) {
+        pc = *gbl(fd.ped + c);
+        if (full) {
+            const int32_t *row = ar + (int64_t)c * fd.acc_stride;
+            a0 = *(const DAQ_GLOBAL u32x4 *)row;
+            a1 = *(const DAQ_GLOBAL u32x4 *)(row + 4);
+        } else {
+            a0 = a1 = u32x4{0u, 0u, 0u, 0u};
+        }
+    };
+    int c = 0;
+    for (; c + R <= fd.C; c += R) {
+        uint4 v[R];
+        u32x4 a0[R], a1[R];
+        int32_t pc[R];
+#pragma unroll
+        for (int u = 0; u < R; u++) v[u] = ld(xr + (int64_t)(c + u) * fd.stride);
+        if (ar != nullptr) {
+#pragma unroll
+            for (int u = 0; u < R; u++) load_acc(c + u, a0[u], a1[u], pc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < R; u++) {
+            add8(s, v[u]);
+            if (ar != nullptr) update(c + u, v[u], a0[u], a1[u], pc[u]);
+        }
+    }
+    for (; c < fd.C; c++) {
+        const uint4 v = ld(xr + (int64_t)c * fd.stride);
+        add8(s, v);
+        if (ar != nullptr) {
+            u32x4 a0, a1;
+            int32_t pc;
+            load_acc(c, a0, a1, pc);
+            update(c, v, a0, a1, pc);
+        }
+    }
+    if (owner) {
+#pragma unroll
+        for (int k = 0; k < kVec; k++) *gsum += k < nv ? (int64_t)s[k] - ped_total : 0;
+    }
+    return flags8(s, thr_eff, valid);
+}
+
+// Adds the lanes' group sums (8-sample groups at p) into the decimated sums
+// of their kQBin-sample bins: the first lane of each bin within the wave sums
+// the bin's next lanes and makes one atomic add. Executed by whole waves.
+__device__ __forceinline__ void q_bin_add(const FillDev &fd, int64_t p, int64_t gsum) {
+    const int lane = threadIdx.x & 63;
+    const int k = (int)((p >> 3) & (kQBin / kVec - 1));  // group index within its bin
+    int64_t acc = gsum;
+#pragma unroll
+    for (int d = 1; d < kQBin / kVec; d++) {
+        const int64_t t = __shfl_down(gsum, d, 64);
+        if (lane + d < 64 && k + d < kQBin / kVec) acc += t;
+    }
+    if (fd.qsum != nullptr && (k == 0 || lane == 0) && acc != 0 && p >= 0 && p < fd.n)
+        atomicAdd(reinterpret_cast<unsigned long long *>(fd.qsum + (p >> 5)), (unsigned long long)acc);
+}
+
 // Flags of 8 samples starting at p (all C rows read, nothing kept); R rows
 // are in flight per round. STREAM: non-temporal loads.
 template <int R, bool STREAM = false>
@@ -938,9 +1041,9 @@ struct ChopGeom {
 // Step 1 for a tile of NT groups: flags of this thread's 8 samples from all
 // channel rows (Table 2 waveform-sum and threshold rows), R rows in flight,
 // halo groups of wide windows loaded apart; bitmap zero padding; barrier.
-template <int NT, int R>
+template <int NT, int R, bool Q = false>
 __device__ __forceinline__ void chop_flags(const FillDev &fd, const ChopGeom<NT> &q, int32_t thr_eff,
-                                           uint8_t *s_bits, bool stream = false) {
+                                           uint8_t *s_bits, bool stream = false, int64_t ped_total = 0) {
     const int tid = threadIdx.x;
     const int64_t N = fd.n;
     uint32_t fb = 0;
@@ -949,9 +1052,17 @@ __device__ __forceinline__ void chop_flags(const FillDev &fd, const ChopGeom<NT>
     const int w = tid >> 6;
     const bool halo_wave = !fd.wide && (w == 0 || w == NT / 64 - 1);
     const bool nt = stream && !halo_wave;
-    if (q.p >= 0 && q.p < N)
-        fb = nt ? group_flags<R, true>(fd.raw + q.p, fd.stride, fd.C, thr_eff, N - q.p)
-                : group_flags<R, false>(fd.raw + q.p, fd.stride, fd.C, thr_eff, N - q.p);
+    if constexpr (Q) {
+        int64_t gsum = 0;
+        if (q.p >= 0 && q.p < N)
+            fb = nt ? group_flags_q<R, true>(fd, q.p, thr_eff, N - q.p, q.owner, ped_total, &gsum)
+                    : group_flags_q<R, false>(fd, q.p, thr_eff, N - q.p, q.owner, ped_total, &gsum);
+        q_bin_add(fd, q.p, gsum);
+    } else {
+        if (q.p >= 0 && q.p < N)
+            fb = nt ? group_flags<R, true>(fd.raw + q.p, fd.stride, fd.C, thr_eff, N - q.p)
+                    : group_flags<R, false>(fd.raw + q.p, fd.stride, fd.C, thr_eff, N - q.p);
+    }
     s_bits[q.g] = (uint8_t)fb;
     if (fd.wide) {
         for (int h = tid; h < fd.gl + fd.gr; h += NT) {
@@ -1374,6 +1485,9 @@ __device__ __forceinline__ PartRange part_range(const KArgs &a, int nf, int64_t 
     return r;
 }
 
+#ifndef DAQ_Q_SCAN_ROWS
+#define DAQ_Q_SCAN_ROWS 4  // the same with the Q-method fused (three loads per row)
+#endif
 #ifndef DAQ_SCAN_ROWS
 #define DAQ_SCAN_ROWS 6  // channel rows each thread has in flight
 #endif
@@ -1381,16 +1495,16 @@ __device__ __forceinline__ PartRange part_range(const KArgs &a, int nf, int64_t 
 // Flags and dilation of one tile (Table 2 threshold and pre/post rows): the
 // island-mask bits of samples p - 1 .. p + 8 of the calling thread (zero for
 // threads that own no samples).
-template <int NT, int R>
+template <int NT, int R, bool Q = false>
 __device__ __forceinline__ uint32_t tile_mask10(const FillDev &fd, const ChopGeom<NT> &q, int32_t thr_eff,
-                                                uint8_t *lds, bool stream) {
+                                                uint8_t *lds, bool stream, int64_t ped_total = 0) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
     const int64_t N = fd.n;
     uint8_t *s_bits = lds;
     uint32_t *s_pc = reinterpret_cast<uint32_t *>(lds + ChopLds<NT>::kWords * 8);
-    chop_flags<NT, R>(fd, q, thr_eff, s_bits, stream);
+    chop_flags<NT, R, Q>(fd, q, thr_eff, s_bits, stream, ped_total);
     const int Wn = (q.G + 7) >> 3;
     const uint64_t *words = reinterpret_cast<const uint64_t *>(s_bits);
     // windows of at most 55 samples: the flags around a group fit one 64-bit
@@ -1444,12 +1558,12 @@ __device__ __forceinline__ uint32_t tile_mask10(const FillDev &fd, const ChopGeo
 // Scan pass, one tile: flags, dilation, mask bits, totals. The tile's word
 // in tile_state (zero before the launch) receives each wave's totals by an
 // atomic add, so the tile ends without a work-group barrier.
-template <int NT, int R>
+template <int NT, int R, bool Q = false>
 __device__ __forceinline__ void scan_pass_tile(const KArgs &a, const FillDev &fd, int32_t thr_eff, int64_t tile,
-                                               uint8_t *lds) {
+                                               uint8_t *lds, int64_t ped_total = 0) {
     const int lane = threadIdx.x & 63;
     const ChopGeom<NT> q(fd, tile);
-    const uint32_t m10 = tile_mask10<NT, R>(fd, q, thr_eff, lds, stream_loads(a));
+    const uint32_t m10 = tile_mask10<NT, R, Q>(fd, q, thr_eff, lds, stream_loads(a), ped_total);
     if (q.owner) {
         // the owned samples' mask byte: t0 is a multiple of 8
         const int64_t byte = (q.t0 >> 3) + (q.g - fd.gl);
@@ -1466,7 +1580,7 @@ __device__ __forceinline__ void scan_pass_tile(const KArgs &a, const FillDev &fd
                   (unsigned long long)(((uint64_t)(mine >> 16) << 31) | (uint64_t)(mine & 0xFFFFu)));
 }
 
-template <int NT, int R>
+template <int NT, int R, bool Q = false>
 __global__ void __launch_bounds__(NT) k_scan_pass(KArgs a) {
     // two bitmaps, used by alternate tiles: a wave still reading one tile's
     // bitmap never meets the next tile's writes, so tiles need no closing
@@ -1483,6 +1597,7 @@ __global__ void __launch_bounds__(NT) k_scan_pass(KArgs a) {
     FillDev fd{};
     int cur = -1;
     int32_t thr_eff = 0;
+    int64_t ped_total = 0;  // Q: the sum of the fill's pedestals
     int buf = 0;
     const PartRange pr = part_range(a, nf, total);
     for (int64_t tile = pr.tile_lo + blockIdx.x; tile < pr.tile_hi; tile += gridDim.x) {
@@ -1494,10 +1609,12 @@ __global__ void __launch_bounds__(NT) k_scan_pass(KArgs a) {
                 else hi = mid - 1;
             }
             fd = fill_at(a, lo);
-            thr_eff = clamp_thr(*gbl(a.thr_eff + lo));
+            const int64_t te = *gbl(a.thr_eff + lo);
+            thr_eff = clamp_thr(te);
+            ped_total = te - (int64_t)fd.thr;
             cur = lo;
         }
-        scan_pass_tile<NT, R>(a, fd, thr_eff, tile, s_lds[buf]);
+        scan_pass_tile<NT, R, Q>(a, fd, thr_eff, tile, s_lds[buf], ped_total);
         buf ^= 1;
     }
 }
@@ -1935,18 +2052,6 @@ __global__ void __launch_bounds__(NT) k_pipe(KArgs a) {
 // the channel pedestal (one 32-byte read-modify-write). The pedestal-
 // subtracted column sums of four consecutive threads make one 32-sample bin.
 
-constexpr int kQBin = 32;  // samples per decimated bin (Table 2: 560k / 17.5k)
-
-__device__ __forceinline__ void store16_i32(int32_t *p, const uint4 v, bool stream) {
-    u32x4 w;
-    w.x = v.x;
-    w.y = v.y;
-    w.z = v.z;
-    w.w = v.w;
-    if (stream) __builtin_nontemporal_store(w, (DAQ_GLOBAL u32x4 *)p);
-    else *(DAQ_GLOBAL u32x4 *)p = w;
-}
-
 template <int NT>
 __global__ void __launch_bounds__(NT) k_q_pass(KArgs a) {
     static_assert((NT * kVec) % kQBin == 0 && kQBin % kVec == 0, "bins never cross a tile");
@@ -2114,6 +2219,8 @@ __global__ void __launch_bounds__(256) k_prepare(KArgs a) {
             }
             __syncthreads();
         }
+        if (fd.qsum != nullptr)  // decimated sums built by atomic adds (fused Q-method)
+            for (int64_t i = threadIdx.x; i < (fd.n + kQBin - 1) / kQBin; i += 256) fd.qsum[i] = 0;
         if (fd.mbits != nullptr && threadIdx.x < 2 * kMaskGuard) {
             const int64_t nbytes = fd.n_tiles * fd.tout / kVec;
             const int i = threadIdx.x;
@@ -2206,6 +2313,12 @@ hipError_t launch_chop(const KArgs &a, int threads, int variant, int grid, hipSt
 }
 
 hipError_t launch_scan(const KArgs &a, int threads, int grid, hipStream_t s) {
+    if (a.q_fused) {
+        if (threads == 256) hipLaunchKernelGGL((k_scan_pass<256, DAQ_Q_SCAN_ROWS, true>), dim3(grid), dim3(256), 0, s, a);
+        else if (threads == 512) hipLaunchKernelGGL((k_scan_pass<512, DAQ_Q_SCAN_ROWS, true>), dim3(grid), dim3(512), 0, s, a);
+        else return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
     if (threads == 256) hipLaunchKernelGGL((k_scan_pass<256, DAQ_SCAN_ROWS>), dim3(grid), dim3(256), 0, s, a);
     else if (threads == 512) hipLaunchKernelGGL((k_scan_pass<512, DAQ_SCAN_ROWS>), dim3(grid), dim3(512), 0, s, a);
     else return hipErrorInvalidValue;

@@ -457,18 +457,30 @@ int capture_graphs(daq_ctx *ctx, Scratch *s, const daq_schedule &sc) {
 // The fused pass over n fills. n == 1 without `force_table` passes the one
 // descriptor in the kernel arguments; otherwise the descriptors go through a
 // pinned staging slot into the device table (and graphs may be replayed).
+int check_q_out(const daq_fill &f, const daq_q_out &o);
+bool q_acc_overlap(const daq_fill *fills, const daq_q_out *outs, int32_t n);
+
+// qouts (optional): the Q-method runs inside the split schedule's scan pass,
+// on the same read of the raw samples (plain launches, no graph).
 int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int32_t n,
-              hipStream_t stream, bool force_table) {
+              hipStream_t stream, bool force_table, const daq_q_out *qouts = nullptr) {
     if (!ctx || n < 0 || (n > 0 && (!fills || !outs))) return DAQ_EINVAL;
     for (int32_t i = 0; i < n; i++) {
         int rc = check_fill(&fills[i]);
         if (rc) return rc;
         rc = check_out(&outs[i]);
         if (rc) return rc;
+        if (qouts) {
+            rc = check_q_out(fills[i], qouts[i]);
+            if (rc) return rc;
+            if (qouts[i].ped && outs[i].ped) return DAQ_EINVAL;
+        }
     }
+    if (qouts && q_acc_overlap(fills, qouts, n)) return DAQ_EINVAL;
     if (n == 0) return DAQ_OK;
     DeviceGuard guard(ctx->device);
     daq_schedule sc = ctx->sched;
+    if (qouts && sc.variant != daqk::kVariantSplit) sc = daq_schedule{256, 16, daqk::kVariantSplit, 0};
     // the register variant keeps exactly 54 rows per thread: calls with other
     // channel counts run the re-read variant
     if (sc.variant == daqk::kVariantResident && !all_calorimeters(fills, n)) sc.variant = daqk::kVariantReload;
@@ -494,11 +506,37 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     // tile words double as per-fill words (pipe variant): at least one per fill
     int rc = ensure_scratch(s, std::max<int64_t>(total, n), n, mask_total);
     if (rc) return rc;
+    // fused Q-method: the accumulator update needs the pedestals in memory
+    std::vector<int64_t> poff((size_t)n, -1);
+    if (qouts) {
+        int64_t ped_need = 0;
+        for (int32_t i = 0; i < n; i++)
+            if (!outs[i].ped && !qouts[i].ped) {
+                poff[(size_t)i] = ped_need;
+                ped_need += fills[i].n_channels;
+            }
+        if (ped_need > s->q_ped_cap) {
+            HIP_TRY(hipStreamSynchronize(stream));
+            (void)hipFree(s->q_ped);
+            s->q_ped = nullptr;
+            s->q_ped_cap = 0;
+            const int64_t cap = std::max<int64_t>(ped_need + ped_need / 2, 4096);
+            HIP_TRY(hipMalloc(&s->q_ped, (size_t)cap * sizeof(int32_t)));
+            s->q_ped_cap = cap;
+        }
+    }
     auto desc = [&](int32_t i) {
         FillDev d = make_desc(fills[i], outs[i], base[(size_t)i], sc);
         d.mbits = split ? s->mask + moff[(size_t)i] + daqk::kMaskGuard : nullptr;
         d.runs = split ? reinterpret_cast<int32_t *>(s->mask + moff[(size_t)i] + lay[(size_t)i].runs) : nullptr;
         d.cmap = split ? reinterpret_cast<int32_t *>(s->mask + moff[(size_t)i] + lay[(size_t)i].cmap) : nullptr;
+        if (qouts) {
+            const daq_q_out &q = qouts[i];
+            if (!d.ped) d.ped = q.ped ? q.ped : s->q_ped + poff[(size_t)i];
+            d.qsum = q.qsum;
+            d.acc = q.acc;
+            d.acc_stride = q.acc ? q.acc_stride : 0;
+        }
         return d;
     };
     KArgs a{};
@@ -510,6 +548,7 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     a.total_tiles = total;
     a.stream_loads = raw_bytes > kStreamLoadBytes ? 1 : 0;
     a.copy_slots = split ? max_chunks * n : 0;
+    a.q_fused = qouts ? 1 : 0;
     if (n == 1 && !force_table) {
         a.one = desc(0);
         return launch_pair(ctx, s, a, total, stream, sc);
@@ -538,7 +577,7 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
     }
     a.table = s->table;
     a.hdr = s->hdr;
-    const bool use_graph = ctx->graphs && sc.wgs_per_cu > 0;
+    const bool use_graph = ctx->graphs && sc.wgs_per_cu > 0 && !qouts;
     if (!use_graph) return launch_pair(ctx, s, a, total, stream, sc);
     GraphKey want;
     want.threads = sc.threads;
@@ -999,6 +1038,12 @@ int daq_qmethod_batch(daq_ctx *ctx, const daq_fill *fills, const daq_q_out *outs
 int daq_process_batch(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int32_t n,
                       void *stream) {
     return run_fused(ctx, fills, outs, n, (hipStream_t)stream, true);
+}
+
+int daq_process_batch_q(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, const daq_q_out *qouts,
+                        int32_t n, void *stream) {
+    if (n > 0 && !qouts) return DAQ_EINVAL;
+    return run_fused(ctx, fills, outs, n, (hipStream_t)stream, true, qouts);
 }
 
 int daq_ctx_set_schedule(daq_ctx *ctx, const daq_schedule *s) {
