@@ -2,7 +2,8 @@
 ABI): the T-method's island tables, pedestals and packed samples equal the
 oracle's chop, and the Q-method's decimated sums and accumulators equal the
 oracle's Q-method, bit-exact, over ragged lengths and channel counts, both
-tile sizes, a context on another schedule, where the pedestals go, argument
+tile sizes, a batch cut into fill groups on several streams, a context on
+another schedule, where the pedestals go, argument
 errors, and the 16-fill workload (also against the two separate calls)."""
 import numpy as np
 import pytest
@@ -42,8 +43,8 @@ def _check_q(q, Q, acc, N, what):
 
 
 @pytest.mark.parametrize("sched", [(256, 16, daq.DAQ_VARIANT_SPLIT, 0), (512, 8, daq.DAQ_VARIANT_SPLIT, 0),
-                                   (256, 16, daq.DAQ_VARIANT_RELOAD, 0)],
-                         ids=["split256", "split512", "context_on_reload"])
+                                   (256, 16, daq.DAQ_VARIANT_SPLIT, 3), (256, 16, daq.DAQ_VARIANT_RELOAD, 0)],
+                         ids=["split256", "split512", "split_three_groups", "context_on_reload"])
 def test_random_fills(ctx, sched):
     ctx.set_schedule(*sched)
     rng = np.random.default_rng(sched[0] + sched[2])
