@@ -2199,17 +2199,30 @@ __global__ void __launch_bounds__(256) k_prepare(KArgs a) {
             for (int i = threadIdx.x; i < cn; i += 256) s_acc[i] = 0;
             __syncthreads();
             const int64_t items = (int64_t)cn * nch;
-            for (int64_t i = threadIdx.x; i < items; i += 256) {
-                const int cl = (int)(i / nch);
-                const int64_t t = (i - (int64_t)cl * nch) * kVec;
-                const uint4 v = load16(fd.raw + (int64_t)(c0 + cl) * fd.stride + t);
-                int32_t s[kVec] = {0, 0, 0, 0, 0, 0, 0, 0};
-                add8(s, v);
-                int32_t part = 0;
+            // four items per thread and round, all loads issued before the adds
+            constexpr int kItems = 4;
+            for (int64_t i0 = threadIdx.x; i0 < items; i0 += 256 * kItems) {
+                uint4 v[kItems];
+                int cl[kItems];
+                int64_t t[kItems];
 #pragma unroll
-                for (int k = 0; k < kVec; k++) part += (t + k < n) ? s[k] : 0;
-                atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[cl]),
-                          (unsigned long long)(long long)part);
+                for (int u = 0; u < kItems; u++) {
+                    const int64_t i = i0 + (int64_t)u * 256;
+                    cl[u] = (int)(i / nch);
+                    t[u] = (i - (int64_t)cl[u] * nch) * kVec;
+                    if (i < items) v[u] = load16(fd.raw + (int64_t)(c0 + cl[u]) * fd.stride + t[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < kItems; u++) {
+                    if (i0 + (int64_t)u * 256 >= items) break;
+                    int32_t s[kVec] = {0, 0, 0, 0, 0, 0, 0, 0};
+                    add8(s, v[u]);
+                    int32_t part = 0;
+#pragma unroll
+                    for (int k = 0; k < kVec; k++) part += (t[u] + k < n) ? s[k] : 0;
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[cl[u]]),
+                              (unsigned long long)(long long)part);
+                }
             }
             __syncthreads();
             for (int i = threadIdx.x; i < cn; i += 256) {
