@@ -243,7 +243,8 @@ typedef struct daq_q_out {
 int daq_qmethod_batch(daq_ctx *ctx, const daq_fill *fills,
                       const daq_q_out *outs, int32_t n, void *stream);
 
-/* Both methods on one read: daq_process_batch's T-method results in outs and
+/* Both methods on one read (Section 3 and Table 2 run the T-method and the
+ * Q-method on every fill): daq_process_batch's T-method results in outs and
  * the Q-method's in qouts (as daq_qmethod_batch computes them), the sums and
  * accumulator updates taken inside the chop's scan pass, so the raw samples
  * are read once for both. Runs the split schedule whatever the context's
@@ -313,8 +314,8 @@ typedef struct daq_z_fill {
  * no-op), asynchronously on `stream`: a size pass and a pack pass over up to
  * 16 fills at a time. The context keeps per-stream scratch of 8 bytes per
  * wave of a launch (at most 128 KB), allocated (synchronously) on first
- * need. DAQ_EINVAL for a
- * null pointer, a negative size, stride < max_len or reserved != 0;
+ * need. DAQ_EINVAL for a null pointer, a negative size, stride < max_len or
+ * reserved != 0;
  * DAQ_ERANGE past DAQ_MAX_CHANNELS / DAQ_MAX_SAMPLES; DAQ_EALIGN for packed
  * or stride as stated above, or another pointer not aligned to its type.
  * Fills of one call must not share outputs. */
