@@ -573,8 +573,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(fills are independent units; see the sharding notes). Run with --gpus 1.",
+        print("bench.py measures one GPU: the library runs on one device and has no multi-GPU path "
+              "(fills are independent units, so a detector shards by calorimeter). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 
