@@ -140,3 +140,25 @@ def test_workload_16_fills_fused_and_separate(ctx):
         assert torch.equal(qouts[i].qsum, qouts2[i].qsum), i
         assert torch.equal(qouts[i].acc, qouts2[i].acc), i
         assert torch.equal(outs[i].counts, outs2[i].counts), i
+
+
+def test_capacity_overflow_leaves_the_q_method_exact(ctx):
+    """Too small an island table: the T-method reports DAQ_STATUS_CAPACITY and
+    keeps the records that fit; the Q-method outputs are unaffected."""
+    x = np.full((54, 20_000), 1000, np.int16)
+    x[0, 100:20_000:200] -= 500
+    p = params(-100, 8, 24, 50)
+    ref = oracle.chop(x, n_samples=20_000, ped_samples=50, threshold=-100, pre=8, post=24)
+    assert ref.n_islands == 100
+    f = make_fill(dev(x), 20_000, p)
+    o = daq.alloc_out(f, capacity=37)
+    q = daq.alloc_q_out(f)
+    q.ped = None
+    ctx.daq_process_batch_q([f], [o], [q])
+    torch.cuda.synchronize()
+    isl, n, total, status, ped, out = o.host()
+    assert n == 100 and total == ref.total_len
+    assert status & daq.DAQ_STATUS_CAPACITY
+    np.testing.assert_array_equal(isl, ref.islands[:37])
+    pq, Q, acc = _q_ref(x, 20_000, 50, np.zeros(q.acc.shape, np.int32))
+    _check_q(q, Q, acc, 20_000, "capacity overflow")
