@@ -177,3 +177,12 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
         daq.load_library()
     with pytest.raises(ImportError):
         daq.Context(0)
+
+
+def test_fused_call_rejects_bad_arguments_without_touching_a_gpu():
+    lib = daq.load_library()
+    f = (daq.daq_fill * 1)(daq.daq_fill(0x1000, 10, 16, 1, 100, -200, 8, 24, 0))
+    o = (daq.daq_fill_out * 1)(daq.daq_fill_out(0x2000, 1, 0x3000, 0x4000, 0x5000, 16))
+    q = (daq.daq_q_out * 1)(daq.daq_q_out(0x6000, 0x7000, 16, None))
+    assert lib.daq_process_batch_q(None, f, o, q, 1, None) == daq.DAQ_EINVAL
+    assert lib.daq_qmethod_batch(None, f, q, 1, None) == daq.DAQ_EINVAL
