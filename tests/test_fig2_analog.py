@@ -8,7 +8,10 @@ baseline) the found islands match the true ones to a few per cent; within
 about 2 sigma noise crossings inflate them several times over; and the marks
 nest with the threshold (a lower threshold flags a subset of samples, so each
 of its islands lies inside one of the higher threshold's and the packed
-length does not grow). No GPU: the GPU side of the same counts is checked in
+length does not grow). Per true pulse: every pulse deeper than 1.5 times the
+threshold's depth below the baseline starts inside a found island, while
+pulses shallower than half of it are caught only when they sit in another
+pulse's island. No GPU: the GPU side of the same counts is checked in
 tests/test_gpu_fig2.py."""
 import numpy as np
 import pytest
@@ -71,3 +74,22 @@ def test_islands_nest_with_the_threshold():
             assert (j >= 0).all()
             assert (r.islands[:, 1] <= stops[j]).all()
         prev = r
+
+
+@pytest.mark.parametrize("k", [10, 20])
+def test_pulse_efficiency_by_amplitude(k):
+    """Per pulse of the generator's truth list (start time, summed amplitude):
+    found when its start lies inside an island."""
+    for index in range(2):
+        sp = synth.FillSpec(seed=synth.fill_seed("fig2", 0, index))
+        x, truth = synth.render(sp, truth=True)
+        depth = k * SIGMA_SUM
+        r = chop(x, sp.n_samples, int(baseline(x, sp.n_samples) - depth))
+        starts, stops = r.islands[:, 0], r.islands[:, 1]
+        j = np.searchsorted(starts, truth["t0"], side="right") - 1
+        inside = (j >= 0) & (truth["t0"] < stops[np.maximum(j, 0)])
+        deep = truth["amp"] >= 1.5 * depth
+        shallow = truth["amp"] < 0.5 * depth
+        assert deep.sum() > 1000 and shallow.sum() > 20
+        assert inside[deep].all()
+        assert inside[shallow].mean() < 0.8
