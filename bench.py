@@ -306,12 +306,31 @@ def fig2_bench(daq, synth, ctx, n_fills=16):
     ms = (time.perf_counter() - t0) * 1e3
     counts = np.array([int(o.counts[0].item()) for o in outs]).reshape(2, n_fills, len(FIG2_KS))
     found, truth = counts[0].sum(0), counts[1].sum(0)
+    # per true pulse (the generator's list): found when its start lies in an island of the
+    # noisy fill; pulses deeper than 1.5 times the threshold's depth, and all pulses
+    eff_deep, eff_all = np.zeros(len(FIG2_KS)), np.zeros(len(FIG2_KS))
+    n_deep, n_all = np.zeros(len(FIG2_KS)), np.zeros(len(FIG2_KS))
+    for i, sp in enumerate(specs):
+        _, pulses = synth.render(sp, truth=True)
+        for kk, k in enumerate(FIG2_KS):
+            o = outs[i * len(FIG2_KS) + kk]
+            n_isl = min(int(o.counts[0].item()), int(o.islands.shape[0]))
+            isl = o.islands[:n_isl].cpu().numpy()
+            j = np.searchsorted(isl[:, 0], pulses["t0"], side="right") - 1
+            inside = (j >= 0) & (pulses["t0"] < isl[np.maximum(j, 0), 1]) if n_isl else np.zeros(len(pulses), bool)
+            deep = pulses["amp"] >= 1.5 * k * sigma
+            eff_deep[kk] += inside[deep].sum()
+            n_deep[kk] += deep.sum()
+            eff_all[kk] += inside.sum()
+            n_all[kk] += len(pulses)
     res = {"workload": "Figure 2 analog: %d fills x 54 ch x 560,000 at the nominal rate, thresholds k sigma "
                        "below each fill's baseline (sigma = %.1f ADC, the summed noise), islands found vs "
                        "the same chop of the noiseless rendering; one launch of %d entries"
                        % (n_fills, sigma, len(fills)),
            "k_sigma": FIG2_KS, "found": found.tolist(), "truth": truth.tolist(),
            "ratio": [round(float(f) / max(float(t), 1.0), 4) for f, t in zip(found, truth)],
+           "pulse_efficiency_deep": [round(float(e) / max(float(n), 1.0), 4) for e, n in zip(eff_deep, n_deep)],
+           "pulse_efficiency_all": [round(float(e) / max(float(n), 1.0), 4) for e, n in zip(eff_all, n_all)],
            "ms_per_sweep": round(ms, 3), "parity_fill0": None}
     PENDING.append(("fig2", res, (xs[0], x0s[0], specs[0], thr[0], counts[0][0].tolist(), counts[1][0].tolist())))
     del xd, x0d, fills, outs, base, qs
