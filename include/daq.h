@@ -322,6 +322,30 @@ typedef struct daq_z_fill {
 int daq_compress_batch(daq_ctx *ctx, const daq_z_fill *fills, int32_t n,
                        void *stream);
 
+/* One compressed stream to decode (the inverse of daq_compress_batch, for a
+ * reader of the stream: the event builder's side). */
+typedef struct daq_z_stream {
+    const uint32_t *hdr;      /* n_channels * ceil(n_samples / 64) headers   */
+    const int64_t *offsets;   /* as many payload word offsets (required)     */
+    const uint32_t *words;    /* the payload                                 */
+    int64_t n_words;          /* words readable at `words`                   */
+    int16_t *out;             /* n_channels rows of out_stride int16 (16-byte
+                                 aligned): samples t < n_samples are written */
+    int64_t out_stride;       /* >= n_samples, % 8 == 0                       */
+    int64_t n_samples;        /* L of the stream (its fill's total_len)       */
+    int32_t n_channels;
+    int32_t reserved;         /* 0                                           */
+} daq_z_stream;               /* 64 bytes, device pointers                   */
+
+/* Decode n streams (host array, copied; n = 0 is a no-op), asynchronously on
+ * `stream`, up to 16 per launch. A stream written by daq_compress_batch
+ * decodes to exactly the packed rows it was made from. For any other input
+ * the samples are unspecified, but no word at or past n_words is read and
+ * widths above 17 are taken as 17. Errors as for daq_compress_batch
+ * (DAQ_EALIGN for out or out_stride, or an array not aligned to its type). */
+int daq_decompress_batch(daq_ctx *ctx, const daq_z_stream *streams, int32_t n,
+                         void *stream);
+
 /* Schedule of the fused kernel used by daq_chop_fill / daq_process_batch.
  * EINVAL for values outside the documented sets. */
 int daq_ctx_set_schedule(daq_ctx *ctx, const daq_schedule *s);

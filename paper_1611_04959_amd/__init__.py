@@ -70,6 +70,12 @@ class daq_z_fill(ctypes.Structure):
                 ("n_channels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class daq_z_stream(ctypes.Structure):
+    _fields_ = [("hdr", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("words", ctypes.c_void_p),
+                ("n_words", ctypes.c_int64), ("out", ctypes.c_void_p), ("out_stride", ctypes.c_int64),
+                ("n_samples", ctypes.c_int64), ("n_channels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class daq_schedule(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("parts", ctypes.c_int32)]
@@ -145,6 +151,7 @@ def load_library():
         "daq_process_batch_q": ([vp, ctypes.POINTER(daq_fill), ctypes.POINTER(daq_fill_out),
                                  ctypes.POINTER(daq_q_out), i32, vp], ctypes.c_int),
         "daq_compress_batch": ([vp, ctypes.POINTER(daq_z_fill), i32, vp], ctypes.c_int),
+        "daq_decompress_batch": ([vp, ctypes.POINTER(daq_z_stream), i32, vp], ctypes.c_int),
         "daq_packed12_stride": ([i64], i64),
         "daq_ctx_set_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
         "daq_ctx_get_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
@@ -432,6 +439,22 @@ class Context:
                                _ptr(z.offsets), z.words.data_ptr(), cap, z.n_words.data_ptr(),
                                int(o.out.shape[0]), 0)
         _check(self._lib.daq_compress_batch(self.handle, za, n, _stream_handle(stream)), "daq_compress_batch")
+
+    def daq_decompress_batch(self, zouts: Sequence[ZOut], n_samples: Sequence[int], outs, stream=None):
+        """Decode streams made by daq_compress_batch (n_samples: each stream's total_len) into
+        int16 [C, out_stride] tensors `outs`."""
+        if not (len(zouts) == len(n_samples) == len(outs)):
+            raise ValueError("zouts, n_samples and outs differ in length")
+        n = len(zouts)
+        za = (daq_z_stream * max(n, 1))()
+        for i, (z, L, o) in enumerate(zip(zouts, n_samples, outs)):
+            if z.offsets is None:
+                raise ValueError("decoding needs the block offsets")
+            za[i] = daq_z_stream(z.hdr.data_ptr(), z.offsets.data_ptr(), z.words.data_ptr(),
+                                 min(int(z.n_words.item()), int(z.words.numel())), o.data_ptr(),
+                                 int(o.stride(0)), int(L), int(o.shape[0]), 0)
+        _check(self._lib.daq_decompress_batch(self.handle, za, n, _stream_handle(stream)),
+               "daq_decompress_batch")
 
     def daq_autotune(self, fills: Sequence[Fill], outs: Sequence[FillOut], stream=None,
                      cache_path: Optional[str] = None) -> daq_schedule:

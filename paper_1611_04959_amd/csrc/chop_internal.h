@@ -187,4 +187,22 @@ struct ZArgs {
 };
 hipError_t launch_z(const ZArgs &a, int grid, hipStream_t s);
 
+// Decompression: one stream back into packed rows.
+struct ZStreamDev {
+    const uint32_t *hdr;
+    const int64_t *offsets;
+    const uint32_t *words;
+    int64_t n_words;
+    int16_t *out;
+    int64_t out_stride;
+    int64_t L;
+    int32_t C;
+    int32_t pad;
+};
+struct ZDecArgs {
+    ZStreamDev f[kZMaxFills];
+    int32_t n;
+};
+hipError_t launch_unz(const ZDecArgs &a, int grid, hipStream_t s);
+
 }  // namespace daqk

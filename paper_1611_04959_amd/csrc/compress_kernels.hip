@@ -293,7 +293,104 @@ __global__ void __launch_bounds__(kZWaves * 64) k_z_pack(ZArgs a) {
     if (v == W - 1 && lane == 0) *f.n_words = carry;
 }
 
+// ---- decompression ------------------------------------------------------------
+//
+// The same 8-block groups: a wave copies the group's payload words (contiguous
+// in the stream) into its LDS, then lane l decodes the codes of samples
+// 8 l .. 8 l + 7 of the group (each from one or two words), undoes the
+// zigzag, and adds the differences up: a prefix within the lane, then across
+// the block's 8 lanes, plus the block's first sample. Words past n_words are
+// read as zero, so a damaged stream cannot make the kernel read out of bounds.
+__global__ void __launch_bounds__(kZWaves * 64) k_unz(ZDecArgs a) {
+    __shared__ uint32_t s_words[kZWaves][kZGroupWords + 2];
+    const ZStreamDev &f = a.f[blockIdx.y];
+    const int lane = threadIdx.x & 63;
+    const int sub = lane & 7, jb = lane >> 3;
+    const int wl = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t *buf = s_words[wl];
+    const int64_t L = f.L;
+    const int64_t nb = (L + kZBlock - 1) / kZBlock;
+    const int64_t gpr = (nb + kZGroup - 1) / kZGroup;
+    const int64_t groups = gpr * f.C;
+    const int64_t step = (int64_t)gridDim.x * kZWaves;
+    for (int64_t gi = (int64_t)blockIdx.x * kZWaves + wl; gi < groups; gi += step) {
+        const int64_t c = gi / gpr;
+        const int64_t kb0 = (gi - c * gpr) * kZGroup;
+        const int64_t kb = kb0 + jb;
+        const int64_t left = L - kb * kZBlock;
+        const int n = left <= 0 ? 0 : (left < kZBlock ? (int)left : kZBlock);
+        const int64_t b = c * nb + kb;
+        uint32_t hw = 0;
+        int64_t off = 0;
+        if (n > 0) {
+            hw = f.hdr[b];
+            off = f.offsets[b];
+        }
+        uint32_t w = hw >> 16;
+        w = w > 17u ? 17u : w;
+        const uint32_t nw = n > 0 ? ((uint32_t)(n - 1) * w + 31u) >> 5 : 0u;
+        // the group's payload: from its first block's offset to the end of its last block
+        const int64_t start = __shfl(off, 0, 64);
+        const int last = (int)((nb - kb0 < kZGroup ? nb - kb0 : kZGroup) - 1);
+        const int64_t end = __shfl(off + (int64_t)nw, 8 * last, 64);
+        int64_t span = end - start;
+        span = span < 0 ? 0 : (span > kZGroupWords ? kZGroupWords : span);
+        for (int k = lane; k < span + 2 && k < kZGroupWords + 2; k += 64) {
+            const int64_t at = start + k;
+            buf[k] = (at >= 0 && at < f.n_words && k < span) ? f.words[at] : 0u;
+        }
+        wave_lds_order();
+        int32_t v[kVec];
+        int32_t run = 0;
+#pragma unroll
+        for (int e = 0; e < kVec; e++) {
+            const int i = sub * kVec + e;
+            int32_t d = 0;
+            if (i >= 1 && i < n && w > 0) {
+                const int64_t pos = (off - start) * 32 + (int64_t)(i - 1) * w;
+                const int64_t wi = pos >> 5;
+                const uint32_t sh = (uint32_t)(pos & 31);
+                uint64_t pair = 0;
+                if (wi >= 0 && wi < kZGroupWords) pair = (uint64_t)buf[wi] | ((uint64_t)buf[wi + 1] << 32);
+                const uint32_t z = (uint32_t)(pair >> sh) & ((1u << w) - 1u);
+                d = (int32_t)(z >> 1) ^ -(int32_t)(z & 1u);
+            }
+            run += d;
+            v[e] = run;
+        }
+        // exclusive prefix of the lane totals over the block's 8 lanes
+        int32_t inc = run;
+#pragma unroll
+        for (int dd = 1; dd < 8; dd <<= 1) {
+            const int32_t t = __shfl_up(inc, dd, 64);
+            if (sub >= dd) inc += t;
+        }
+        const int32_t before = inc - run + (int32_t)(int16_t)(hw & 0xFFFFu);
+        wave_lds_order();
+        if (n > 0) {
+            int16_t *row = f.out + c * f.out_stride + kb * kZBlock + sub * kVec;
+            const int valid = n - sub * kVec;
+            if (valid >= kVec) {
+                uint4 q;
+                q.x = (uint32_t)(uint16_t)(before + v[0]) | ((uint32_t)(uint16_t)(before + v[1]) << 16);
+                q.y = (uint32_t)(uint16_t)(before + v[2]) | ((uint32_t)(uint16_t)(before + v[3]) << 16);
+                q.z = (uint32_t)(uint16_t)(before + v[4]) | ((uint32_t)(uint16_t)(before + v[5]) << 16);
+                q.w = (uint32_t)(uint16_t)(before + v[6]) | ((uint32_t)(uint16_t)(before + v[7]) << 16);
+                *reinterpret_cast<uint4 *>(row) = q;
+            } else {
+                for (int e = 0; e < valid; e++) row[e] = (int16_t)(before + v[e]);
+            }
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_unz(const ZDecArgs &a, int grid, hipStream_t s) {
+    if (a.n < 1 || a.n > kZMaxFills || grid < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_unz, dim3(grid, a.n), dim3(kZWaves * 64), 0, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_z(const ZArgs &a, int grid, hipStream_t s) {
     if (a.n < 1 || a.n > kZMaxFills || grid < 1 || grid > kZMaxGrid) return hipErrorInvalidValue;

@@ -1031,6 +1031,45 @@ int daq_compress_batch(daq_ctx *ctx, const daq_z_fill *fills, int32_t n, void *s
     return DAQ_OK;
 }
 
+int daq_decompress_batch(daq_ctx *ctx, const daq_z_stream *streams, int32_t n, void *stream_) {
+    if (!ctx || n < 0 || (n > 0 && !streams)) return DAQ_EINVAL;
+    for (int32_t i = 0; i < n; i++) {
+        const daq_z_stream &z = streams[i];
+        if (!z.hdr || !z.offsets || !z.out || z.n_samples < 0 || z.n_words < 0 || z.n_channels < 1 ||
+            z.reserved != 0 || (z.n_words > 0 && !z.words) || z.out_stride < z.n_samples)
+            return DAQ_EINVAL;
+        if (z.n_channels > DAQ_MAX_CHANNELS || z.n_samples > DAQ_MAX_SAMPLES) return DAQ_ERANGE;
+        if (!aligned16(z.out) || (z.out_stride % daqk::kVec) != 0 || !aligned_to(z.hdr, 4) ||
+            !aligned_to(z.offsets, 8) || !aligned_to(z.words, 4))
+            return DAQ_EALIGN;
+    }
+    if (n == 0) return DAQ_OK;
+    DeviceGuard guard(ctx->device);
+    for (int32_t i0 = 0; i0 < n; i0 += daqk::kZMaxFills) {
+        daqk::ZDecArgs a{};
+        a.n = std::min<int32_t>(n - i0, daqk::kZMaxFills);
+        int64_t most = 1;
+        for (int32_t j = 0; j < a.n; j++) {
+            const daq_z_stream &z = streams[i0 + j];
+            daqk::ZStreamDev &d = a.f[j];
+            d.hdr = z.hdr;
+            d.offsets = z.offsets;
+            d.words = z.words;
+            d.n_words = z.n_words;
+            d.out = z.out;
+            d.out_stride = z.out_stride;
+            d.L = z.n_samples;
+            d.C = z.n_channels;
+            const int64_t nb = (z.n_samples + DAQ_Z_BLOCK - 1) / DAQ_Z_BLOCK;
+            most = std::max<int64_t>(most, (nb + 7) / 8 * z.n_channels);
+        }
+        const int64_t wide = std::max<int64_t>(1, (int64_t)8 * ctx->n_cu / a.n);
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(wide, (most + daqk::kZWaves - 1) / daqk::kZWaves));
+        HIP_TRY(daqk::launch_unz(a, grid, (hipStream_t)stream_));
+    }
+    return DAQ_OK;
+}
+
 int daq_qmethod_batch(daq_ctx *ctx, const daq_fill *fills, const daq_q_out *outs, int32_t n, void *stream) {
     return run_qmethod(ctx, fills, outs, n, (hipStream_t)stream);
 }

@@ -248,3 +248,97 @@ def test_random_shapes_in_one_call(ctx):
     torch.cuda.synchronize()
     for i in range(40):
         check(zouts[i], xs[i], Ls[i], "random fill %d (C=%d L=%d)" % (i, xs[i].shape[0], Ls[i]))
+
+
+def _offsets_of(hdr, C, L):
+    """Payload offsets from the headers (the format's size rule)."""
+    nb = -(-L // B)
+    n = np.array([min(B, L - (b % max(nb, 1)) * B) for b in range(len(hdr))], np.int64)
+    sizes = ((n - 1) * (hdr >> 16).astype(np.int64) + 31) // 32
+    return np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64) if len(hdr) else np.zeros(0, np.int64)
+
+
+@pytest.mark.parametrize("C,L", [(1, 1), (3, 63), (3, 65), (2, 513), (54, 1000), (5, 4097)])
+@pytest.mark.parametrize("kind", ["noise", "wide", "flat", "mixed"])
+def test_decompress_round_trip(ctx, C, L, kind):
+    """Compressed on the device, decoded on the device: the packed rows come
+    back exactly, samples past L untouched. The oracle's own stream decodes
+    the same way."""
+    x = rows(C * 131 + L + len(kind), C, L, kind)
+    o = packed_out(x, L)
+    zo = daq.alloc_z_out(C, o.out.shape[1], device="cuda")
+    ctx.daq_compress_batch([o], [zo])
+    back = torch.full((C, max(daq.padded(L), 8) + 8), -3, dtype=torch.int16, device="cuda")
+    log("decompress C=%d L=%d %s" % (C, L, kind))
+    ctx.daq_decompress_batch([zo], [L], [back])
+    torch.cuda.synchronize()
+    got = back.cpu().numpy()
+    np.testing.assert_array_equal(got[:, :L], x[:, :L])
+    assert (got[:, L:] == -3).all()
+    # the oracle's stream, decoded by the device
+    hdr, words = oracle.z_compress(x, L)
+    z2 = daq.ZOut(dev(hdr.view(np.int32) if len(hdr) else np.zeros(1, np.int32)),
+                  dev(_offsets_of(hdr, C, L) if len(hdr) else np.zeros(1, np.int64)),
+                  dev(words.view(np.int32) if len(words) else np.zeros(1, np.int32)),
+                  torch.tensor([len(words)], dtype=torch.int64, device="cuda"))
+    back2 = torch.full_like(back, -3)
+    ctx.daq_decompress_batch([z2], [L], [back2])
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(back2.cpu().numpy()[:, :L], x[:, :L])
+
+
+def test_decompress_16_fills_and_damaged_streams(ctx):
+    """The 16 benchmark fills chopped, compressed and decoded in one call each
+    (bit-exact against the packed rows); then streams cut short or with
+    widths past 17 decode without error (samples unspecified)."""
+    specs = synth.config_c1()
+    xs = synth.render_many(specs)
+    ns = [s.n_samples for s in specs]
+    ps = [params(s.threshold, s.pre, s.post, s.ped_samples) for s in specs]
+    fills = [make_fill(d, n, p) for d, n, p in zip(synth.to_device(xs), ns, ps)]
+    outs = [daq.alloc_out(f) for f in fills]
+    zouts = [daq.alloc_z_out(o.out.shape[0], o.out.shape[1], device="cuda") for o in outs]
+    ctx.daq_process_batch(fills, outs)
+    ctx.daq_compress_batch(outs, zouts)
+    torch.cuda.synchronize()
+    Ls = [int(o.counts[1].item()) for o in outs]
+    backs = [torch.zeros_like(o.out) for o in outs]
+    log("decompress 16 fills")
+    ctx.daq_decompress_batch(zouts, Ls, backs)
+    torch.cuda.synchronize()
+    for i, (o, bk, L) in enumerate(zip(outs, backs, Ls)):
+        assert torch.equal(bk[:, :L], o.out[:, :L]), i
+    # damaged: half the words, and every header's width field set to 31
+    z = zouts[0]
+    z.n_words.fill_(int(z.n_words.item()) // 2)
+    ctx.daq_decompress_batch([z], [Ls[0]], [backs[0]])
+    z.hdr.bitwise_or_(0x1F << 16)
+    ctx.daq_decompress_batch([z], [Ls[0]], [backs[0]])
+    torch.cuda.synchronize()
+
+
+def test_decompress_argument_errors(ctx):
+    lib = daq.load_library()
+    C, L = 2, 100
+    x = rows(3, C, L, "noise")
+    o = packed_out(x, L)
+    zo = daq.alloc_z_out(C, o.out.shape[1], device="cuda")
+    back = torch.zeros((C, 104), dtype=torch.int16, device="cuda")
+
+    def call(**kw):
+        s = daq.daq_z_stream(zo.hdr.data_ptr(), zo.offsets.data_ptr(), zo.words.data_ptr(), 10,
+                             back.data_ptr(), 104, L, C, 0)
+        for k, v in kw.items():
+            setattr(s, k, v)
+        return lib.daq_decompress_batch(ctx.handle, (daq.daq_z_stream * 1)(s), 1, None)
+
+    assert call() == daq.DAQ_OK
+    torch.cuda.synchronize()
+    assert call(offsets=None) == daq.DAQ_EINVAL
+    assert call(hdr=None) == daq.DAQ_EINVAL
+    assert call(out_stride=99) == daq.DAQ_EINVAL
+    assert call(reserved=2) == daq.DAQ_EINVAL
+    assert call(n_channels=0) == daq.DAQ_EINVAL
+    assert call(out=back.data_ptr() + 2) == daq.DAQ_EALIGN
+    assert call(out_stride=108) == daq.DAQ_EALIGN
+    assert lib.daq_decompress_batch(ctx.handle, None, 0, None) == daq.DAQ_OK
