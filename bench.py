@@ -228,7 +228,8 @@ def oracle_check(oracle, kind, payload) -> bool:
 
 def z_bench(daq, ctx, outs, x0, spec0, steps, warmup=3):
     """Lossless compression of the 16 chopped fills (per-block delta, zigzag and bit
-    width), one daq_compress_batch call per step over the packed rows of the last launch."""
+    width), one daq_compress_batch call per step over the packed rows of the last launch;
+    then one daq_decompress_batch call per step decoding the streams back."""
     import numpy as np
     import torch
     C = int(outs[0].out.shape[0])
@@ -253,6 +254,20 @@ def z_bench(daq, ctx, outs, x0, spec0, steps, warmup=3):
     n_words = sum(int(z.n_words.item()) for z in zouts)
     alg = packed + 12 * blocks + 4 * n_words          # samples read; headers, offsets, payload written
     stream_bytes = 4 * blocks + 4 * n_words           # what leaves the frontend: headers and payload
+    # decoding the same streams back into packed rows
+    backs = [torch.empty_like(o.out) for o in outs]
+    for _ in range(warmup):
+        ctx.daq_decompress_batch(zouts, tot, backs)
+    torch.cuda.synchronize()
+    d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    d0.record()
+    for _ in range(steps):
+        ctx.daq_decompress_batch(zouts, tot, backs)
+    d1.record()
+    torch.cuda.synchronize()
+    dms = d0.elapsed_time(d1) / steps
+    round_trip = all(torch.equal(b[:, :t], o.out[:, :t]) for b, o, t in zip(backs, outs, tot))
+    dec_alg = packed + 12 * blocks + 4 * n_words      # payload, headers and offsets read; samples written
     res = {}
     hdr0, _, words0 = zouts[0].host(C, tot[0])
     PENDING.append(("compress", res, (x0, spec0, hdr0, words0)))
@@ -265,6 +280,10 @@ def z_bench(daq, ctx, outs, x0, spec0, steps, warmup=3):
                              "unit": "GB/s", "frac": round(alg / kms / 1e6 / HBM_PEAK_GBS, 4),
                              "kernel": "one call: k_z_size, k_z_pack",
                              "algorithmic_bytes_per_launch": alg},
+                "decompress": {"ms_per_step": round(dms, 4), "packed_gbs": round(packed / dms / 1e6, 1),
+                               "algorithmic_gbs": round(dec_alg / dms / 1e6, 1),
+                               "frac": round(dec_alg / dms / 1e6 / HBM_PEAK_GBS, 4), "kernel": "k_unz",
+                               "round_trip_exact": bool(round_trip)},
                 "parity_fill0": None})
     return res
 

@@ -450,9 +450,10 @@ class Context:
         for i, (z, L, o) in enumerate(zip(zouts, n_samples, outs)):
             if z.offsets is None:
                 raise ValueError("decoding needs the block offsets")
+            # the words the buffer holds bound the reads (no device round trip per call)
             za[i] = daq_z_stream(z.hdr.data_ptr(), z.offsets.data_ptr(), z.words.data_ptr(),
-                                 min(int(z.n_words.item()), int(z.words.numel())), o.data_ptr(),
-                                 int(o.stride(0)), int(L), int(o.shape[0]), 0)
+                                 int(z.words.numel()), o.data_ptr(), int(o.stride(0)), int(L),
+                                 int(o.shape[0]), 0)
         _check(self._lib.daq_decompress_batch(self.handle, za, n, _stream_handle(stream)),
                "daq_decompress_batch")
 
