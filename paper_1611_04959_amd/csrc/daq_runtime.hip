@@ -1031,6 +1031,10 @@ int daq_compress_batch(daq_ctx *ctx, const daq_z_fill *fills, int32_t n, void *s
     return DAQ_OK;
 }
 
+#ifndef DAQ_UNZ_WGS_PER_CU
+#define DAQ_UNZ_WGS_PER_CU 32  // decoding work-groups per CU, shared by the launch's streams (latency-bound: more in flight)
+#endif
+
 int daq_decompress_batch(daq_ctx *ctx, const daq_z_stream *streams, int32_t n, void *stream_) {
     if (!ctx || n < 0 || (n > 0 && !streams)) return DAQ_EINVAL;
     for (int32_t i = 0; i < n; i++) {
@@ -1063,7 +1067,7 @@ int daq_decompress_batch(daq_ctx *ctx, const daq_z_stream *streams, int32_t n, v
             const int64_t nb = (z.n_samples + DAQ_Z_BLOCK - 1) / DAQ_Z_BLOCK;
             most = std::max<int64_t>(most, (nb + 7) / 8 * z.n_channels);
         }
-        const int64_t wide = std::max<int64_t>(1, (int64_t)8 * ctx->n_cu / a.n);
+        const int64_t wide = std::max<int64_t>(1, (int64_t)DAQ_UNZ_WGS_PER_CU * ctx->n_cu / a.n);
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(wide, (most + daqk::kZWaves - 1) / daqk::kZWaves));
         HIP_TRY(daqk::launch_unz(a, grid, (hipStream_t)stream_));
     }
