@@ -180,7 +180,10 @@ struct ZFillDev {
 // payload sizes of the waves before it: at most kZMaxGrid * kZWaves).
 constexpr int kZMaxFills = 16;
 constexpr int kZWaves = 4;
-constexpr int kZMaxGrid = 256;
+#ifndef DAQ_Z_MAX_GRID
+#define DAQ_Z_MAX_GRID 256
+#endif
+constexpr int kZMaxGrid = DAQ_Z_MAX_GRID;
 struct ZArgs {
     ZFillDev f[kZMaxFills];
     int32_t n;

@@ -969,6 +969,10 @@ int check_z_fill(const daq_z_fill &z) {
 
 }  // namespace
 
+#ifndef DAQ_Z_WGS_PER_CU
+#define DAQ_Z_WGS_PER_CU 8  // compression work-groups per CU, shared by the launch's fills
+#endif
+
 int daq_compress_batch(daq_ctx *ctx, const daq_z_fill *fills, int32_t n, void *stream_) {
     if (!ctx || n < 0 || (n > 0 && !fills)) return DAQ_EINVAL;
     if (n == 0) return DAQ_OK;
@@ -982,7 +986,8 @@ int daq_compress_batch(daq_ctx *ctx, const daq_z_fill *fills, int32_t n, void *s
     auto grid_of = [&](int32_t i0, int32_t m) {
         int64_t most = 1;
         for (int32_t j = 0; j < m; j++) most = std::max(most, z_groups(fills[i0 + j]));
-        const int64_t wide = std::min<int64_t>(daqk::kZMaxGrid, std::max<int64_t>(1, (int64_t)8 * ctx->n_cu / m));
+        const int64_t wide =
+            std::min<int64_t>(daqk::kZMaxGrid, std::max<int64_t>(1, (int64_t)DAQ_Z_WGS_PER_CU * ctx->n_cu / m));
         return (int)std::max<int64_t>(1, std::min<int64_t>(wide, (most + daqk::kZWaves - 1) / daqk::kZWaves));
     };
     int64_t need = 0;  // one word per wave of a launch (launches run in stream order)
