@@ -19,7 +19,6 @@ sample, after the oracle has checked the first fill of every line.
 import argparse
 import dataclasses
 import concurrent.futures as cf
-import hashlib
 import json
 import os
 import sys
@@ -34,7 +33,6 @@ HBM_PEAK_GBS = 8000.0
 PENDING = []
 METRIC = "raw ADC GB/s island-chopped & % HBM peak; p99 fill latency, batched vs plain"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "chop_16fills_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1611_04959_amd", "csrc", "chop_kernels.hip")
 
 
 def log(msg):
@@ -47,7 +45,10 @@ def pct(vals, q):
 
 
 def kernel_sha():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of every source the chop kernels are built from (the traffic
+    file's counts apply only to the version they were taken for)."""
+    from paper_1611_04959_amd.traffic import kernel_sha as sha
+    return sha()
 
 
 def distinct_copies(xd, k):
@@ -111,9 +112,11 @@ def batch_bench(daq, synth, specs, what, steps=20, warmup=3):
     ms = (time.perf_counter() - t0) * 1e3 / steps
     kern = ctx.kernel_times_ms()
     ctx.set_timing(False)
-    tot = sum(int(o.counts[1].item()) for o in outs)
+    cnt = torch.stack([o.counts for o in outs]).cpu().numpy()
+    tot = int(cnt[:, 1].sum())
     ctx.close()
     res = {"workload": what, "fills": len(specs), "raw_gb": round(raw / 1e9, 3),
+           "seeds": [sp.seed for sp in specs], "islands": [int(v) for v in cnt[:, 0]],
            "ms_per_step": round(ms, 4), "gbs": round(raw / (ms * 1e-3) / 1e9, 1),
            "pct_hbm_peak": round(100 * raw / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
            "kernel_ms_mean": round(float(np.mean(kern)), 4) if kern else None,
@@ -505,6 +508,7 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
         keeps `depth` fills submitted and unfinished for `dur` seconds."""
         pending = []          # (arrival_ns, stream) not yet admitted
         arr_ns = {}
+        kept = None
         lat, done_bytes = [], 0
         t0 = time.monotonic_ns()
         i, n_off = 0, 0
@@ -535,17 +539,30 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
                 assert c.error == 0 and c.status == 0
                 lat.append((c.t_ready_ns - arr_ns.pop(c.ticket)) * 1e-6)
                 done_bytes += raw
-                srv.release(c.ticket)
+                # the first completion whose samples are a rendered fill is kept
+                # (its slot unreleased) for the oracle check after the run
+                data = (c.tag % len(host)) if host is not None else (c.tag if c.tag < len(xs) else None)
+                if kept is None and data is not None:
+                    kept = (c, data)
+                else:
+                    srv.release(c.ticket)
             if times is not None and i >= len(times) and not pending and not arr_ns:
                 break
             if times is None and now >= end_ns and not pending and not arr_ns:
                 break
         wall = (time.monotonic_ns() - t0) * 1e-9
         st = srv.stats()
-        return {"fills": len(lat), "p50_ms": round(pct(lat, 50), 4), "p99_ms": round(pct(lat, 99), 4),
-                "max_ms": round(max(lat), 4), "gbs": round(done_bytes / wall / 1e9, 1),
-                "wall_s": round(wall, 2), "batches": int(st.batches),
-                "peak_resident_gb": round(st.arena_peak / 1e9, 2)}
+        res = {"fills": len(lat), "p50_ms": round(pct(lat, 50), 4), "p99_ms": round(pct(lat, 99), 4),
+               "max_ms": round(max(lat), 4), "gbs": round(done_bytes / wall / 1e9, 1),
+               "wall_s": round(wall, 2), "batches": int(st.batches),
+               "peak_resident_gb": round(st.arena_peak / 1e9, 2), "parity_fill0": None}
+        if kept is not None:
+            c, data = kept
+            isl, ped, out = srv.results(c, synth.CHANNELS)
+            PENDING.append(("chop", res, (xs[data], specs[data],
+                                          (isl, c.n_islands, c.total_len, c.status, ped, out))))
+            srv.release(c.ticket)
+        return res
 
     rate = 24 * 12 / 1.4
     rng = np.random.default_rng(3)
@@ -573,7 +590,8 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
                 p = np.zeros((x.shape[0], pst), np.uint8)
                 p[:, :(3 * N + 1) // 2] = trip[:, :(3 * N + 1) // 2]
                 hp.append(torch.from_numpy(p).pin_memory())
-            log("serving: host-fed 12-bit words, saturated")
+            log("serving: host-fed 12-bit words at the nominal rate, then saturated")
+            ingest["nominal_packed12"] = run(arrivals(rate, 5.0, rng), host=hp, packed=True)
             ingest["saturation_packed12"] = run(None, host=hp, depth=32, packed=True)
     except RuntimeError as e:  # pinned memory unavailable
         log("ingest skipped: %s" % e)
@@ -584,6 +602,7 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
                         "in HBM; Poisson arrivals, 24 x 12 fills per 1.4 s on average with 5x bursts "
                         "(80 ms, 10 % duty)", "offered_fills_per_s": round(rate, 1),
             "budget_gb": budget_gb, "n_streams": n_streams, "max_batch": max_batch,
+            "seeds": [sp.seed for sp in specs],
             "nominal": nominal, "saturation": sat, "ingest_pcie": ingest}
 
 
@@ -606,8 +625,8 @@ def main():
     ap.add_argument("--no-compress", action="store_true", help="skip the compression line")
     ap.add_argument("--no-fig2", action="store_true", help="skip the Figure 2 analog")
     ap.add_argument("--no-tq", action="store_true", help="skip the fused T-method + Q-method line")
-    ap.add_argument("--stress", action="store_true",
-                    help="also time the whole-detector stress batch (96 calorimeter fills, 5.8 GB)")
+    ap.add_argument("--no-stress", action="store_true",
+                    help="skip the whole-detector stress batch (96 calorimeter fills, 5.8 GB)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -819,7 +838,7 @@ def main():
         others["uneven"] = batch_bench(daq, synth, synth.config_c2(), "24 uneven calorimeter streams: N ~ "
                                        "U{100k..560k}, rate 0.5-4x, thr -400..-150, pre 4-16, post 16-48",
                                        steps=max(10, args.steps // 2))
-    if args.stress:
+    if not args.no_stress:
         others["stress"] = batch_bench(daq, synth, synth.config_c4(), "whole detector: 4 fills x 24 "
                                        "calorimeters x 54 ch x 560,000, 10x rate, thr -100, pre 8, post 48",
                                        steps=max(5, args.steps // 10))
@@ -842,24 +861,44 @@ def main():
             log("oracle checks of %d lines" % len(PENDING))
             for kind, into, payload in PENDING:
                 into["parity_fill0"] = oracle_check(oracle, kind, payload)
-            cores = min(os.cpu_count() or 1, 16)
-            log("CPU oracle baseline on %d threads for ~%.0f s" % (cores, args.cpu_seconds))
-            done = 0
-            tc0 = time.perf_counter()
+            threads = len(os.sched_getaffinity(0))
 
             def one(i):
-                oracle.chop(xs[i], n_samples=N, ped_samples=specs[i].ped_samples,
-                            threshold=specs[i].threshold, pre=specs[i].pre, post=specs[i].post)
-                return specs[i].raw_bytes
+                sp = specs[i % len(specs)]
+                oracle.chop(xs[i % len(specs)], n_samples=sp.n_samples, ped_samples=sp.ped_samples,
+                            threshold=sp.threshold, pre=sp.pre, post=sp.post)
+                return sp.raw_bytes
 
-            with cf.ThreadPoolExecutor(cores) as ex:
+            # one core: whole fills in turn for a fifth of the budget
+            log("CPU oracle on one core for ~%.0f s" % (args.cpu_seconds / 5))
+            done1, k = 0, 0
+            ts0 = time.perf_counter()
+            while time.perf_counter() - ts0 < args.cpu_seconds / 5:
+                done1 += one(k)
+                k += 1
+            single = done1 / (time.perf_counter() - ts0) / 1e9
+            # every core the process may run on: one fill per thread at a time
+            log("CPU oracle baseline on %d threads for ~%.0f s" % (threads, args.cpu_seconds))
+            done = 0
+            tc0 = time.perf_counter()
+            with cf.ThreadPoolExecutor(threads) as ex:
                 while time.perf_counter() - tc0 < args.cpu_seconds:
-                    done += sum(ex.map(one, range(len(specs))))
+                    done += sum(ex.map(one, range(max(threads, len(specs)))))
             tc1 = time.perf_counter()
-            cpu = {"value": round(done / (tc1 - tc0) / 1e9, 3), "unit": "GB/s", "cores": cores,
+            model = ""
+            try:
+                for ln in open("/proc/cpuinfo"):
+                    if ln.startswith("model name"):
+                        model = ln.split(":", 1)[1].strip()
+                        break
+            except OSError:
+                pass
+            cpu = {"value": round(done / (tc1 - tc0) / 1e9, 3), "unit": "GB/s", "cores": threads,
                    "kind": "oracle",
-                   "sample": "the same %d fills, repeated for %.1f s (%.2f GB raw), one fill per thread"
-                             % (len(specs), tc1 - tc0, done / 1e9)}
+                   "sample": "the %d bench fills, each chopped whole by one thread, %d threads at a time, "
+                             "repeated for %.1f s (%.2f GB raw)" % (len(specs), threads, tc1 - tc0, done / 1e9),
+                   "cpu_model": model, "nproc": os.cpu_count(), "threads": threads,
+                   "single_core_gbs": round(single, 3)}
         except ImportError:
             cpu = None
 
@@ -873,13 +912,15 @@ def main():
                    "fills": len(specs), "channels": C, "samples": N, "rate": 3.0,
                    "threshold": -200, "pre": 8, "post": 24, "ped_samples": 100,
                    "schedule": {"threads": sched[0], "wgs_per_cu": sched[1], "variant": sched[2],
-                                "parts": sched[3]}},
+                                "parts": sched[3]},
+                   "seeds": [s.seed for s in specs]},
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "batched": {"gbs": round(value, 1), "p50_fill_ms": round(pct(step_ms, 50), 4),
                     "p99_fill_ms": round(pct(step_ms, 99), 4)},
         "pipelined": pipelined,
         "plain": plain,
         "islands_per_fill": round(float(np.mean(n_isl)), 1),
+        "islands": n_isl,
         "occupancy": round(sum(tot) / (N * len(specs)), 4),
         "parity_fill0": main_check.get("parity_fill0"),
         "roofline": roofline,

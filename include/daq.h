@@ -367,12 +367,20 @@ int daq_ctx_kernel_time(daq_ctx *ctx, float *ms);
 int daq_ctx_kernel_times(daq_ctx *ctx, float *ms, int32_t max);
 
 /* Times every candidate schedule on the given batch, checks that each one's
- * island tables, counts and packed samples equal the first candidate's byte
- * for byte (DAQ_EMISMATCH otherwise), keeps the fastest as the context's
- * schedule and writes it to *best. Synchronises `stream`; the outputs hold
- * the last candidate's (identical) results. When cache_path is not NULL the
- * choice is looked up there first and stored there after tuning, keyed by
- * device name and batch shape. */
+ * results equal the first candidate's byte for byte (DAQ_EMISMATCH
+ * otherwise), keeps the fastest as the context's schedule and writes it to
+ * *best. Before its checked run every candidate's output buffers are filled
+ * with a poison pattern (records and counts all ones, pedestals and packed
+ * rows 0x5A bytes), so a candidate that leaves an output unwritten fails the
+ * check; the check compares the counts, the records below min(n_islands,
+ * capacity), the pedestals and every packed row below min(total_len,
+ * out_stride) with a copy of the first candidate's outputs (the library's
+ * default split schedule). The menu holds the split, re-read, register and
+ * LDS variants; DAQ_VARIANT_PIPE is chosen only by daq_ctx_set_schedule.
+ * Allocates a device copy of the outputs for the duration of the call.
+ * Synchronises `stream`; the outputs hold the last candidate's (identical)
+ * results. When cache_path is not NULL the choice is looked up there first
+ * and stored there after tuning, keyed by device name and batch shape. */
 int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs,
                  int32_t n, void *stream, const char *cache_path,
                  daq_schedule *best);

@@ -75,8 +75,6 @@ struct Scratch {
     hipGraphExec_t g_prep = nullptr, g_chop = nullptr;  // the two halves (timed launches)
     hipGraphExec_t g_all = nullptr;                     // both in one graph (untimed launches)
     GraphKey key;
-    uint64_t *digest = nullptr;  // autotune digests
-    int32_t digest_cap = 0;
     uint64_t *tile_pref = nullptr;  // split variant: tile prefixes (tile_cap)
     uint8_t *mask = nullptr;        // split variant: island-mask bits of all fills
     int64_t mask_cap = 0;
@@ -170,7 +168,6 @@ void free_scratch(Scratch *s) {
     (void)hipFree(s->ticket);
     (void)hipFree(s->thr_eff);
     (void)hipFree(s->hdr);
-    (void)hipFree(s->digest);
     (void)hipFree(s->tile_pref);
     (void)hipFree(s->mask);
     (void)hipFree(s->q_ped);
@@ -607,52 +604,158 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
 
 // ---- autotune ---------------------------------------------------------------
 
-__global__ void k_digest(const FillDev *tab, int n, uint64_t *out) {
-    // order-independent digest of island records, counts and packed samples
-    // of fill blockIdx.y; blocks along x split the packed rows
+// Poison of every output buffer before a candidate's first run: records and
+// counts all bits set (each field reads -1), pedestals and packed rows 0x5A
+// bytes. A candidate that leaves an output unwritten then differs from the
+// reference instead of inheriting the previous candidate's bytes.
+__global__ void k_poison_outputs(const FillDev *tab, int n) {
     const int f = blockIdx.y;
     if (f >= n) return;
     const FillDev d = tab[f];
-    auto mix = [](uint64_t z) {
-        z += 0x9E3779B97F4A7C15ull;
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-        return z ^ (z >> 31);
-    };
-    uint64_t acc = 0;
-    const int64_t n_isl = d.counts->n_islands;
-    const int64_t tl = d.counts->total_len;
-    const int64_t nrec = n_isl < d.cap ? n_isl : d.cap;
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
-    if (gtid == 0) acc += mix(mix((uint64_t)n_isl) ^ mix((uint64_t)tl + 7) ^ (uint64_t)d.counts->status);
-    for (int64_t i = gtid; i < nrec; i += gsz)
-        acc += mix(mix((uint64_t)i * 3 + 1) ^ mix((uint64_t)d.isl[i].start) ^ mix((uint64_t)d.isl[i].stop << 1) ^
-                   mix((uint64_t)d.isl[i].offset << 2));
-    if (d.out) {
-        const int64_t lim = tl < d.out_stride ? tl : d.out_stride;
-        for (int c = 0; c < d.C; c++)
-            for (int64_t p = gtid; p < lim; p += gsz)
-                acc += mix(((uint64_t)c << 40) ^ ((uint64_t)p << 8) ^ mix((uint64_t)(uint16_t)d.out[(int64_t)c * d.out_stride + p]));
+    if (gtid == 0 && d.counts) {
+        d.counts->n_islands = -1;
+        d.counts->total_len = -1;
+        d.counts->status = -1;
+        d.counts->reserved = -1;
     }
-    for (int dd = 32; dd > 0; dd >>= 1) acc += __shfl_xor(acc, dd, 64);
-    if ((threadIdx.x & 63) == 0) atomicAdd((unsigned long long *)&out[f], (unsigned long long)acc);
+    int64_t *isl = reinterpret_cast<int64_t *>(d.isl);
+    for (int64_t i = gtid; i < 3 * d.cap; i += gsz) isl[i] = -1;
+    if (d.ped)
+        for (int64_t i = gtid; i < d.C; i += gsz) d.ped[i] = 0x5A5A5A5A;
+    if (d.out) {
+        const int64_t total = (int64_t)d.C * d.out_stride;  // the rows are contiguous
+        int64_t head = 0;
+        if (((uintptr_t)d.out & 15u) == 0) {
+            uint4 *o16 = reinterpret_cast<uint4 *>(d.out);
+            const uint4 v = make_uint4(0x5A5A5A5Au, 0x5A5A5A5Au, 0x5A5A5A5Au, 0x5A5A5A5Au);
+            for (int64_t i = gtid; i < total / 8; i += gsz) o16[i] = v;
+            head = total / 8 * 8;
+        }
+        for (int64_t i = head + gtid; i < total; i += gsz) d.out[i] = (int16_t)0x5A5A;
+    }
 }
 
-int digest_batch(daq_ctx *ctx, Scratch *s, int32_t n, hipStream_t stream, std::vector<uint64_t> &host) {
-    if (s->digest_cap < n) {
-        (void)hipFree(s->digest);
-        s->digest = nullptr;
-        HIP_TRY(hipMalloc(&s->digest, (size_t)n * sizeof(uint64_t)));
-        s->digest_cap = n;
+// Where the reference copy of one fill's outputs sits.
+struct RefFill {
+    const daq_counts *counts;
+    const int64_t *isl;
+    const int32_t *ped;
+    const int16_t *out;
+};
+
+// Counts the elements of fill blockIdx.y's defined outputs that differ from
+// the reference: counts, records [0, min(n, cap)), pedestals, and every
+// packed row up to min(total_len, out_stride).
+__global__ void k_compare_outputs(const FillDev *tab, const RefFill *ref, int n, unsigned long long *bad) {
+    const int f = blockIdx.y;
+    if (f >= n) return;
+    const FillDev d = tab[f];
+    const RefFill r = ref[f];
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+    const daq_counts c = *d.counts, rc = *r.counts;
+    if (c.n_islands != rc.n_islands || c.total_len != rc.total_len || c.status != rc.status ||
+        c.reserved != rc.reserved) {
+        if (gtid == 0) atomicAdd(&bad[f], 1ull);
+        return;
     }
-    HIP_TRY(hipMemsetAsync(s->digest, 0, (size_t)n * sizeof(uint64_t), stream));
-    hipLaunchKernelGGL(k_digest, dim3(64, n), dim3(256), 0, stream, s->table, n, s->digest);
+    unsigned long long miss = 0;
+    const int64_t nrec = c.n_islands < d.cap ? (c.n_islands < 0 ? 0 : c.n_islands) : d.cap;
+    const int64_t *isl = reinterpret_cast<const int64_t *>(d.isl);
+    for (int64_t i = gtid; i < 3 * nrec; i += gsz) miss += isl[i] != r.isl[i];
+    if (d.ped)
+        for (int64_t i = gtid; i < d.C; i += gsz) miss += d.ped[i] != r.ped[i];
+    if (d.out) {
+        const int64_t len = c.total_len < d.out_stride ? (c.total_len < 0 ? 0 : c.total_len) : d.out_stride;
+        const int64_t items = (int64_t)d.C * len;
+        for (int64_t i = gtid; i < items; i += gsz) {
+            const int64_t row = i / (len > 0 ? len : 1), k = i - row * len;
+            miss += d.out[row * d.out_stride + k] != r.out[row * d.out_stride + k];
+        }
+    }
+    for (int dd = 32; dd > 0; dd >>= 1) miss += __shfl_xor(miss, dd, 64);
+    if ((threadIdx.x & 63) == 0 && miss) atomicAdd(&bad[f], miss);
+}
+
+constexpr int kCheckBlocks = 256;  // blocks per fill of the poison and compare kernels
+
+// The reference copy of a batch's outputs (the first candidate's), in one
+// device allocation owned by the autotune call.
+struct RefCopy {
+    uint8_t *buf = nullptr;
+    RefFill *d_ref = nullptr;
+    unsigned long long *d_bad = nullptr;
+    std::vector<RefFill> host;
+    ~RefCopy() {
+        (void)hipFree(buf);
+        (void)hipFree(d_ref);
+        (void)hipFree(d_bad);
+    }
+};
+
+int64_t up256(int64_t b) { return (b + 255) / 256 * 256; }
+
+int poison_outputs(Scratch *s, int32_t n, hipStream_t stream) {
+    hipLaunchKernelGGL(k_poison_outputs, dim3(kCheckBlocks, n), dim3(256), 0, stream, s->table, n);
     HIP_TRY(hipGetLastError());
-    host.assign((size_t)n, 0);
-    HIP_TRY(hipMemcpyAsync(host.data(), s->digest, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
+    return DAQ_OK;
+}
+
+// Copies every output buffer of the batch (whole buffers) into `rf`.
+int snapshot_outputs(const daq_fill *fills, const daq_fill_out *outs, int32_t n, hipStream_t stream, RefCopy &rf) {
+    int64_t bytes = 0;
+    for (int32_t i = 0; i < n; i++) {
+        const int64_t C = fills[i].n_channels;
+        bytes += up256(sizeof(daq_counts)) + up256(24 * outs[i].capacity) + up256(4 * C) +
+                 (outs[i].out ? up256(2 * C * outs[i].out_stride) : 0);
+    }
+    HIP_TRY(hipMalloc(&rf.buf, (size_t)std::max<int64_t>(bytes, 256)));
+    HIP_TRY(hipMalloc(&rf.d_ref, (size_t)n * sizeof(RefFill)));
+    HIP_TRY(hipMalloc(&rf.d_bad, (size_t)n * sizeof(unsigned long long)));
+    rf.host.assign((size_t)n, RefFill{});
+    int64_t o = 0;
+    for (int32_t i = 0; i < n; i++) {
+        const daq_fill_out &q = outs[i];
+        const int64_t C = fills[i].n_channels;
+        RefFill &r = rf.host[(size_t)i];
+        uint8_t *b = rf.buf + o;
+        r.counts = reinterpret_cast<const daq_counts *>(b);
+        HIP_TRY(hipMemcpyAsync(b, q.counts, sizeof(daq_counts), hipMemcpyDeviceToDevice, stream));
+        b += up256(sizeof(daq_counts));
+        r.isl = reinterpret_cast<const int64_t *>(b);
+        if (q.capacity > 0)
+            HIP_TRY(hipMemcpyAsync(b, q.islands, (size_t)(24 * q.capacity), hipMemcpyDeviceToDevice, stream));
+        b += up256(24 * q.capacity);
+        r.ped = reinterpret_cast<const int32_t *>(b);
+        if (q.ped) HIP_TRY(hipMemcpyAsync(b, q.ped, (size_t)(4 * C), hipMemcpyDeviceToDevice, stream));
+        b += up256(4 * C);
+        r.out = reinterpret_cast<const int16_t *>(b);
+        if (q.out) {
+            HIP_TRY(hipMemcpyAsync(b, q.out, (size_t)(2 * C * q.out_stride), hipMemcpyDeviceToDevice, stream));
+            b += up256(2 * C * q.out_stride);
+        }
+        o = b - rf.buf;
+    }
+    HIP_TRY(hipMemcpyAsync(rf.d_ref, rf.host.data(), (size_t)n * sizeof(RefFill), hipMemcpyHostToDevice, stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    (void)ctx;
+    return DAQ_OK;
+}
+
+// Compares the batch's current outputs with the reference copy, element by
+// element; *same is false when any fill differs.
+int compare_outputs(Scratch *s, int32_t n, hipStream_t stream, RefCopy &rf, bool *same) {
+    HIP_TRY(hipMemsetAsync(rf.d_bad, 0, (size_t)n * sizeof(unsigned long long), stream));
+    hipLaunchKernelGGL(k_compare_outputs, dim3(kCheckBlocks, n), dim3(256), 0, stream, s->table, rf.d_ref, n,
+                       rf.d_bad);
+    HIP_TRY(hipGetLastError());
+    std::vector<unsigned long long> bad((size_t)n, 0);
+    HIP_TRY(hipMemcpyAsync(bad.data(), rf.d_bad, (size_t)n * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    *same = true;
+    for (unsigned long long b : bad) *same = *same && b == 0;
     return DAQ_OK;
 }
 
@@ -1174,9 +1277,11 @@ int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, 
     const bool calo = all_calorimeters(fills, n);
     const int V0 = daqk::kVariantReload, V1 = daqk::kVariantResident, V2 = daqk::kVariantStream;
     const int V3 = daqk::kVariantReload18, V4 = daqk::kVariantReload27, V5 = daqk::kVariantSplit;
-    const int V6 = daqk::kVariantPipe;
-    const daq_schedule menu[] = {{512, 2, V6, 0},
-                                 {256, 16, V5, 0}, {256, 16, V5, 2}, {256, 16, V5, 3}, {256, 16, V5, 4},
+    // the library's default first: it is the reference every other candidate
+    // is compared with. The persistent variant is not on the menu (it never
+    // won, and its bounded waits may give up); daq_ctx_set_schedule selects it.
+    const daq_schedule menu[] = {{256, 16, V5, 0},
+                                 {256, 16, V5, 2}, {256, 16, V5, 3}, {256, 16, V5, 4},
                                  {256, 8, V5, 0},  {256, 8, V5, 2},  {512, 4, V5, 0},  {256, 4, V0, 0},
                                  {256, 8, V0, 0},  {512, 2, V0, 0},  {256, 2, V2, 0},  {256, 4, V3, 0},
                                  {256, 3, V4, 0},  {128, 8, V0, 0},  {256, 1, V1, 0}};
@@ -1186,21 +1291,35 @@ int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, 
     const bool saved_timing = ctx->timing;
     ctx->timing = true;
     DeviceGuard guard(ctx->device);
-    std::vector<uint64_t> ref, dig;
+    RefCopy ref;
     float best_ms = 1e30f;
     daq_schedule best_s = saved;
     int rc = DAQ_OK;
     for (size_t k = 0; k < cand.size() && rc == DAQ_OK; k++) {
         ctx->sched = cand[k];
+        // the descriptor table is staged by the first run; poison through it
+        // once it exists, then run again from poisoned outputs
         rc = run_fused(ctx, fills, outs, n, st, true);  // warm-up (and capture)
         if (rc) break;
         Scratch *s = scratch_for(ctx, st);
-        rc = digest_batch(ctx, s, n, st, dig);
+        rc = poison_outputs(s, n, st);
+        if (!rc) rc = run_fused(ctx, fills, outs, n, st, true);
+        if (!rc) {
+            float ms0 = 0.f;  // untimed: discard the two runs' timings
+            rc = daq_ctx_kernel_time(ctx, &ms0);
+        }
         if (rc) break;
-        if (k == 0) ref = dig;
-        else if (dig != ref) {
-            rc = DAQ_EMISMATCH;
-            break;
+        if (k == 0) {
+            rc = snapshot_outputs(fills, outs, n, st, ref);
+            if (rc) break;
+        } else {
+            bool same = false;
+            rc = compare_outputs(s, n, st, ref, &same);
+            if (rc) break;
+            if (!same) {
+                rc = DAQ_EMISMATCH;
+                break;
+            }
         }
         float tot = 0.f;
         const int reps = 5;

@@ -25,12 +25,19 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SRC = os.path.join(HERE, "csrc", "chop_kernels.hip")
+#: every source the chop kernels are compiled from: the counts recorded for
+#: one version are not reported for another
+KERNEL_SOURCES = (os.path.join(HERE, "csrc", "chop_kernels.hip"), os.path.join(HERE, "csrc", "chop_internal.h"),
+                  os.path.join(os.path.dirname(HERE), "include", "daq.h"))
 PASS_KERNELS = ("k_prepare", "k_scan_pass", "k_prefix_pass", "k_edge_pass", "k_copy_pass", "k_chop", "k_pipe")
 
 
 def kernel_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        h.update(os.path.basename(path).encode() + b"\0")
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def copy_run(mib: int = 1024, reps: int = 3):

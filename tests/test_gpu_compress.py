@@ -19,7 +19,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU machines
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_1611_04959_amd as daq  # noqa: E402
-from gpu_util import dev, log, make_fill, oracle_many  # noqa: E402
+from gpu_util import dev, log, make_fill, oracle_many, poison  # noqa: E402
 from test_gpu_parity import params  # noqa: E402
 
 B = oracle.Z_BLOCK
@@ -302,7 +302,7 @@ def test_decompress_16_fills_and_damaged_streams(ctx):
     ctx.daq_compress_batch(outs, zouts)
     torch.cuda.synchronize()
     Ls = [int(o.counts[1].item()) for o in outs]
-    backs = [torch.zeros_like(o.out) for o in outs]
+    backs = [poison(torch.empty_like(o.out)) for o in outs]
     log("decompress 16 fills")
     ctx.daq_decompress_batch(zouts, Ls, backs)
     torch.cuda.synchronize()

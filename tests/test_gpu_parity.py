@@ -22,7 +22,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU machines
 import golden_io  # noqa: E402
 import paper_1611_04959_amd as daq  # noqa: E402
 from gpu_util import (assert_same, dev, log, make_fill, oracle_many, oracle_result, pad_stride,  # noqa: E402
-                      run)
+                      poison, poison_out, run)
 
 SCHEDULES = [(256, 2, 2, 0), (256, 1, 2, 0), (256, 0, 2, 0), (256, 4, 0, 0), (256, 1, 1, 0), (512, 2, 0, 0),
              (512, 1, 1, 0), (128, 8, 0, 0), (128, 2, 1, 0), (256, 0, 0, 0), (512, 0, 1, 0), (256, 4, 3, 0),
@@ -201,7 +201,7 @@ def test_capacity_and_out_stride_overflow(ctx):
         log("out stride overflow mode=%s" % mode)
         f = make_fill(dev(x), 20_000, p)
         o = daq.alloc_out(f)
-        o.out = torch.zeros((54, 1000), dtype=torch.int16, device="cuda")
+        o.out = poison(torch.empty((54, 1000), dtype=torch.int16, device="cuda"))
         run(ctx, mode, [f], [o])
         isl, n, total, status, ped, out = o.host()
         assert status == daq.DAQ_STATUS_OUT_STRIDE and total == ref.total_len > 1000
@@ -297,8 +297,7 @@ def test_workload_16_fills_batched(ctx):
     ctx.set_graphs(True)
     for rep in range(3):
         for o in outs:
-            o.out.zero_()
-            o.islands.zero_()
+            poison_out(o)
         run(ctx, "batch", fills, outs)
         for i, (o, r) in enumerate(zip(outs, refs)):
             assert_same(o, r, ctx="rep %d fill %d (seed %d)" % (rep, i, specs[i].seed))
@@ -321,8 +320,7 @@ def test_workload_16_fills_pipe(ctx, sched):
     ctx.set_graphs(True)
     for rep in range(3):
         for o in outs:
-            o.out.zero_()
-            o.islands.zero_()
+            poison_out(o)
         log("pipe 16 fills sched=%s rep=%d" % (sched, rep))
         run(ctx, "batch", fills, outs)
         for i, (o, r) in enumerate(zip(outs, refs)):

@@ -18,7 +18,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU machines
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_1611_04959_amd as daq  # noqa: E402
-from gpu_util import dev, log, pad_stride  # noqa: E402
+from gpu_util import dev, log, pad_stride, poison  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -106,9 +106,9 @@ def test_null_outputs(ctx):
     acc = np.zeros((54, 10_000), np.int32)
     ped, Q = oracle.qmethod(x, 10_000, acc=acc)
     f = daq.Fill(dev(x), 10_000)
-    only_q = daq.QOut(qsum=torch.zeros(len(Q), dtype=torch.int64, device="cuda"))
+    only_q = daq.QOut(qsum=poison(torch.empty(len(Q), dtype=torch.int64, device="cuda")))
     only_acc = daq.QOut(acc=torch.zeros((54, 10_000), dtype=torch.int32, device="cuda"))
-    only_ped = daq.QOut(ped=torch.zeros(54, dtype=torch.int32, device="cuda"))
+    only_ped = daq.QOut(ped=poison(torch.empty(54, dtype=torch.int32, device="cuda")))
     f2 = daq.Fill(dev(x), 10_000)
     f3 = daq.Fill(dev(x), 10_000)
     ctx.daq_qmethod_batch([f, f2, f3], [only_q, only_acc, only_ped])

@@ -18,7 +18,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU machines
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_1611_04959_amd as daq  # noqa: E402
-from gpu_util import log, oracle_many  # noqa: E402
+from gpu_util import log, oracle_many, poison, poison_slot  # noqa: E402
 
 
 def _specs(n, seed):
@@ -73,6 +73,7 @@ def _check(srv, c, ref, C, what):
     np.testing.assert_array_equal(isl, ref.islands, err_msg=what + ": islands")
     np.testing.assert_array_equal(ped, ref.ped, err_msg=what + ": ped")
     np.testing.assert_array_equal(out, ref.out, err_msg=what + ": out")
+    poison_slot(srv, c, C)  # the slot's next user starts from poison
     return isl, ped, out
 
 
@@ -80,7 +81,7 @@ def test_alone_equals_in_the_mix(ctx, workload):
     specs, xs, xd, fills, refs = workload
     C = synth.CHANNELS
     need = max(daq.slot_bytes(f) for f in fills)
-    arena = torch.empty(6 * need, dtype=torch.uint8, device="cuda")  # room for ~6 fills at once
+    arena = poison(torch.empty(6 * need, dtype=torch.uint8, device="cuda"))  # room for ~6 fills at once
     with daq.Server(ctx, arena, n_streams=3, max_batch=4) as srv:
         alone = {}
         for i, f in enumerate(fills):
@@ -123,7 +124,7 @@ def test_alone_equals_in_the_mix(ctx, workload):
 def test_batches_overlap_on_the_device(ctx, workload):
     specs, xs, xd, fills, refs = workload
     need = sum(daq.slot_bytes(f) for f in fills)
-    arena = torch.empty(need + (1 << 20), dtype=torch.uint8, device="cuda")
+    arena = poison(torch.empty(need + (1 << 20), dtype=torch.uint8, device="cuda"))
     with daq.Server(ctx, arena, n_streams=3, max_batch=2) as srv:
         for rep in range(3):
             tickets = [srv.submit(f, tag=i) for i, f in enumerate(fills)]
@@ -144,7 +145,7 @@ def test_host_fed_fills_match(ctx, workload):
     specs, xs, xd, fills, refs = workload
     host = [torch.from_numpy(x).pin_memory() for x in xs[:3]]
     need = sum(daq.slot_bytes(f, host_raw=True) for f in fills[:3])
-    arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+    arena = poison(torch.empty(need, dtype=torch.uint8, device="cuda"))
     with daq.Server(ctx, arena, n_streams=2, max_batch=2) as srv:
         for i in range(3):
             assert srv.submit(fills[i], tag=i, host_raw=host[i]) is not None
@@ -173,7 +174,7 @@ def test_host_packed12_fills_match(ctx, workload):
         p[:, :nb] = trip[:, :nb]
         host.append(torch.from_numpy(p).pin_memory())
     need = sum(daq.slot_bytes(f, host_packed12=True) for f in fills[:3])
-    arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+    arena = poison(torch.empty(need, dtype=torch.uint8, device="cuda"))
     with daq.Server(ctx, arena, n_streams=2, max_batch=2) as srv:
         for i in range(3):
             assert srv.submit(fills[i], tag=i, host_packed12=host[i]) is not None
@@ -187,7 +188,7 @@ def test_admission_and_release_rules(ctx, workload):
     specs, xs, xd, fills, refs = workload
     f = fills[0]
     one = daq.slot_bytes(f)
-    arena = torch.empty(2 * one + 1024, dtype=torch.uint8, device="cuda")
+    arena = poison(torch.empty(2 * one + 1024, dtype=torch.uint8, device="cuda"))
     with daq.Server(ctx, arena, n_streams=1, max_batch=8) as srv:
         t1 = srv.submit(f, tag=1)
         t2 = srv.submit(f, tag=2)
@@ -219,7 +220,7 @@ def test_persistent_schedule_serves_the_same(workload):
     try:
         c2.set_schedule(512, 2, daq.DAQ_VARIANT_PIPE)
         need = sum(daq.slot_bytes(f) for f in fills)
-        arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+        arena = poison(torch.empty(need, dtype=torch.uint8, device="cuda"))
         with daq.Server(c2, arena, n_streams=2, max_batch=4) as srv:
             log("server with the persistent schedule: %d fills" % len(fills))
             for i, f in enumerate(fills):
@@ -230,3 +231,59 @@ def test_persistent_schedule_serves_the_same(workload):
                 srv.release(c.ticket)
     finally:
         c2.close()
+
+
+def test_serving_burst_full_size(ctx):
+    """Serving-configuration fills at their own shape (54 x 560,000, the
+    streams' nominal distributions): each fill served alone, then a burst of
+    ten submitted at once to a server whose budget holds three slots, so
+    admission refuses fills until slots are released. Every completion equals
+    the oracle and the same fill served alone; the arena and every released
+    slot hold poison."""
+    specs = [synth.config_c3_fill(s, 0) for s in range(10)]
+    xs = synth.render_many(specs)
+    log("serving burst: oracle on %d full-size fills" % len(specs))
+    refs = oracle_many(xs, [s.n_samples for s in specs],
+                       [{"threshold": s.threshold, "pre": s.pre, "post": s.post, "ped_samples": s.ped_samples}
+                        for s in specs])
+    xd = synth.to_device(xs)
+    fills = [daq.Fill(d, s.n_samples, threshold=s.threshold, pre=s.pre, post=s.post,
+                      ped_samples=s.ped_samples) for d, s in zip(xd, specs)]
+    C = synth.CHANNELS
+    need = max(daq.slot_bytes(f) for f in fills)
+    arena = poison(torch.empty(3 * need + 4096, dtype=torch.uint8, device="cuda"))
+    with daq.Server(ctx, arena, n_streams=3, max_batch=16) as srv:
+        alone = {}
+        for i, f in enumerate(fills):
+            log("serving burst: fill %d alone" % i)
+            t = srv.submit(f, tag=i)
+            assert t is not None
+            (c,) = _drain(srv, 1).values()
+            assert c.tag == i and c.batch_fills == 1
+            alone[i] = _check(srv, c, refs[i], C, "alone %d" % i)
+            srv.release(t)
+        log("serving burst: %d fills at once, budget of 3 slots" % len(fills))
+        pending, got, rejected = list(range(len(fills))), [], 0
+        t_end = time.time() + 120
+        while pending or len(got) < len(fills):
+            assert time.time() < t_end, "burst did not finish"
+            while pending:
+                t = srv.submit(fills[pending[0]], tag=pending[0])
+                if t is None:
+                    rejected += 1
+                    break
+                pending.pop(0)
+            for c in srv.poll(64, 2_000):
+                i = c.tag
+                isl, ped, out = _check(srv, c, refs[i], C, "burst %d" % i)
+                np.testing.assert_array_equal(isl, alone[i][0])
+                np.testing.assert_array_equal(ped, alone[i][1])
+                np.testing.assert_array_equal(out, alone[i][2])
+                got.append(c)
+                srv.release(c.ticket)
+        st = srv.stats()
+        log("serving burst: %d batches, %d refused submits, largest batch %d" %
+            (st.batches, rejected, max(c.batch_fills for c in got)))
+        assert rejected > 0 and st.rejected == rejected  # the budget did bind
+        assert sorted(c.tag for c in got) == list(range(len(fills)))
+        assert st.arena_in_use == 0
