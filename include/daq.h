@@ -209,6 +209,30 @@ int daq_chop_fill(daq_ctx *ctx, const daq_fill *fill, const daq_fill_out *out,
 int daq_process_batch(daq_ctx *ctx, const daq_fill *fills,
                       const daq_fill_out *outs, int32_t n, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * results as daq_process_batch, computed with the split schedule (the
+ * context's thread count and persistent grid when it holds a split schedule,
+ * else 256 threads and 16 work-groups per CU) by plain kernel launches only:
+ * no allocation, no graph, no event, no memset and no host staging. Every
+ * scratch buffer of the call (look-back words, tile totals and prefixes,
+ * effective thresholds, the descriptor table, each fill's mask bits, run
+ * table and chunk map) lives in one static device array of
+ * DAQ_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from the first
+ * daq_ctx_create on that GPU until the process ends; the descriptors reach it
+ * through kernel arguments. Calls on one GPU share that array: calls that
+ * overlap in time on one GPU (other streams, other contexts or threads) race
+ * and must be serialised by the caller; each call clears what it needs.
+ * Needs daq_noalloc_scratch_bytes(fills, n) <= DAQ_NOALLOC_SCRATCH_BYTES
+ * (DAQ_ERANGE otherwise, before anything is launched; 16 fills of
+ * 54 x 560,000 need about 3.5 MB). Other errors as for daq_process_batch;
+ * the context's timing, graph and fill-group settings do not apply. */
+#define DAQ_NOALLOC_SCRATCH_BYTES ((int64_t)32 << 20)
+int64_t daq_noalloc_scratch_bytes(const daq_fill *fills, int32_t n);
+int daq_process_batch_noalloc(daq_ctx *ctx, const daq_fill *fills,
+                              const daq_fill_out *outs, int32_t n,
+                              void *stream);
+
 /* ---- Q-method -------------------------------------------------------------
  * The second output stream of the GPU (Section 3, Q-method paragraph; Table 2,
  * the decimation and fill-by-fill rows): instead of chopping, the detector

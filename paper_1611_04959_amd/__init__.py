@@ -145,6 +145,9 @@ def load_library():
         "daq_chop_fill": ([vp, ctypes.POINTER(daq_fill), ctypes.POINTER(daq_fill_out), vp], ctypes.c_int),
         "daq_process_batch": ([vp, ctypes.POINTER(daq_fill), ctypes.POINTER(daq_fill_out), i32, vp],
                               ctypes.c_int),
+        "daq_process_batch_noalloc": ([vp, ctypes.POINTER(daq_fill), ctypes.POINTER(daq_fill_out), i32, vp],
+                                      ctypes.c_int),
+        "daq_noalloc_scratch_bytes": ([ctypes.POINTER(daq_fill), i32], i64),
         "daq_qmethod_batch": ([vp, ctypes.POINTER(daq_fill), ctypes.POINTER(daq_q_out), i32, vp],
                               ctypes.c_int),
         "daq_unpack12": ([vp, vp, i64, i32, i64, vp, i64, vp], ctypes.c_int),
@@ -198,6 +201,18 @@ def _stream_handle(stream) -> Optional[int]:
 
 def daq_max_islands(n_samples: int, pre: int, post: int) -> int:
     return int(load_library().daq_max_islands(n_samples, pre, post))
+
+
+DAQ_NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def noalloc_scratch_bytes(fills: Sequence["Fill"]) -> int:
+    """Scratch bytes daq_process_batch_noalloc needs for these fills (negative: an error code)."""
+    n = len(fills)
+    fa = (daq_fill * max(n, 1))()
+    for i, f in enumerate(fills):
+        fa[i] = f.c_struct()
+    return int(load_library().daq_noalloc_scratch_bytes(fa, n))
 
 
 def padded(n: int) -> int:
@@ -394,6 +409,12 @@ class Context:
         fa, oa, n = self._arrays(fills, outs)
         _check(self._lib.daq_process_batch(self.handle, fa, oa, n, _stream_handle(stream)),
                "daq_process_batch")
+
+    def daq_process_batch_noalloc(self, fills: Sequence[Fill], outs: Sequence[FillOut], stream=None):
+        """daq_process_batch without any allocation (scratch in the library's static device array)."""
+        fa, oa, n = self._arrays(fills, outs)
+        _check(self._lib.daq_process_batch_noalloc(self.handle, fa, oa, n, _stream_handle(stream)),
+               "daq_process_batch_noalloc")
 
     def daq_qmethod_batch(self, fills: Sequence[Fill], qouts: Sequence[QOut], stream=None):
         if len(fills) != len(qouts):

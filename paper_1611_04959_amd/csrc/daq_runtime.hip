@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -777,6 +778,103 @@ std::string shape_key(const daq_ctx *ctx, const daq_fill *fills, int32_t n) {
     return o.str();
 }
 
+// ---- scratch of the no-allocation entry point ----------------------------------
+//
+// One static device array per GPU (each device holds its own copy at its own
+// address). Host code never passes `scratch` itself to a kernel or a copy: on
+// the host that name is only a stand-in for the symbol. Its device address is
+// looked up once per device, at the first daq_ctx_create on it, and kept in
+// g_noalloc_ptr.
+static __device__ __align__(256) uint8_t scratch[DAQ_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+uint8_t *g_noalloc_ptr[kMaxDevices] = {};
+
+// With `device` current: looks up the device address of the scratch array.
+int noalloc_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return DAQ_OK;  // such devices cannot use the entry point
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr[device]) return DAQ_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol);
+    g_noalloc_ptr[device] = static_cast<uint8_t *>(p);
+    return DAQ_OK;
+}
+
+uint8_t *noalloc_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    return g_noalloc_ptr[device];
+}
+
+// Descriptors of up to kPutFills fills travel as kernel arguments into the
+// table in the scratch array (no host staging buffer, no copy call).
+constexpr int kPutFills = 16;
+struct PutDescArgs {
+    FillDev d[kPutFills];
+    BatchHdr hdr;
+    FillDev *dst;      // table entry of d[0]
+    BatchHdr *dst_hdr; // written when write_hdr
+    int32_t count, write_hdr;
+};
+static_assert(sizeof(PutDescArgs) <= 3584, "kernel arguments of the descriptor upload (explicit arguments well below 4 KB)");
+
+__global__ void k_put_descs(PutDescArgs a) {
+    constexpr int W = (int)(sizeof(FillDev) / 16);  // 16-byte words per descriptor
+    const int i = (int)threadIdx.x;
+    if (i < a.count * W) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(&a.d[0]);
+        reinterpret_cast<uint4 *>(a.dst)[i] = src[i];
+    }
+    if (a.write_hdr && i == 0) *a.dst_hdr = a.hdr;
+}
+
+// Layout of one no-allocation call inside the scratch array (byte offsets).
+struct NoAllocLayout {
+    int64_t ticket = 0, thr_eff = 0, hdr = 0, tile_state = 0, tile_pref = 0, fills = 0, bytes = 0;
+    int64_t total_tiles = 0, max_chunks = 0;
+};
+
+int64_t up16(int64_t b) { return (b + 15) / 16 * 16; }
+
+// Validated fills only.
+NoAllocLayout noalloc_layout(const daq_fill *fills, int32_t n, const daq_schedule &sc) {
+    NoAllocLayout L;
+    int64_t tiles = 0, per_fill = 0;
+    for (int32_t i = 0; i < n; i++) {
+        tiles += tiles_of(fills[i], sc);
+        per_fill += up16(split_layout_of(fills[i], sc).bytes);
+        L.max_chunks = std::max<int64_t>(L.max_chunks, (fills[i].n_samples + daqk::kCopyChunk - 1) / daqk::kCopyChunk);
+    }
+    L.total_tiles = tiles;
+    int64_t o = 0;
+    L.ticket = o;
+    o += 256;
+    L.thr_eff = o;
+    o = up256(o + 8 * (int64_t)std::max(n, 1));
+    L.hdr = o;
+    o = up256(o + (int64_t)sizeof(BatchHdr) + (int64_t)n * (int64_t)sizeof(FillDev));
+    L.tile_state = o;
+    o = up256(o + 8 * std::max<int64_t>(tiles, n));
+    L.tile_pref = o;
+    o = up256(o + 8 * std::max<int64_t>(tiles, n));
+    L.fills = o;
+    o += per_fill;
+    L.bytes = o;
+    return L;
+}
+
+daq_schedule noalloc_schedule(const daq_ctx *ctx) {
+    daq_schedule sc{256, 16, daqk::kVariantSplit, 0};
+    if (ctx->sched.variant == daqk::kVariantSplit) {
+        sc.threads = ctx->sched.threads;
+        sc.wgs_per_cu = ctx->sched.wgs_per_cu > 0 ? ctx->sched.wgs_per_cu : 16;
+    }
+    return sc;
+}
+
 }  // namespace
 
 // ---- C ABI --------------------------------------------------------------------
@@ -824,6 +922,11 @@ int daq_ctx_create(daq_ctx **out, int device) {
     }
     c->n_cu = prop.multiProcessorCount;
     c->name = prop.gcnArchName;
+    const int rc = noalloc_init(device);
+    if (rc != DAQ_OK) {
+        delete c;
+        return rc;
+    }
     *out = c;
     return DAQ_OK;
 }
@@ -1189,6 +1292,90 @@ int daq_qmethod_batch(daq_ctx *ctx, const daq_fill *fills, const daq_q_out *outs
 int daq_process_batch(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int32_t n,
                       void *stream) {
     return run_fused(ctx, fills, outs, n, (hipStream_t)stream, true);
+}
+
+int64_t daq_noalloc_scratch_bytes(const daq_fill *fills, int32_t n) {
+    if (n < 0 || (n > 0 && !fills)) return DAQ_EINVAL;
+    for (int32_t i = 0; i < n; i++) {
+        const int rc = check_fill(&fills[i]);
+        if (rc) return rc;
+    }
+    int64_t most = 0;
+    for (int threads : {256, 512})
+        most = std::max(most, noalloc_layout(fills, n, daq_schedule{threads, 16, daqk::kVariantSplit, 0}).bytes);
+    return most;
+}
+
+int daq_process_batch_noalloc(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int32_t n,
+                              void *stream_) {
+    if (!ctx || n < 0 || (n > 0 && (!fills || !outs))) return DAQ_EINVAL;
+    for (int32_t i = 0; i < n; i++) {
+        int rc = check_fill(&fills[i]);
+        if (rc) return rc;
+        rc = check_out(&outs[i]);
+        if (rc) return rc;
+    }
+    if (n == 0) return DAQ_OK;
+    const daq_schedule sc = noalloc_schedule(ctx);
+    const NoAllocLayout L = noalloc_layout(fills, n, sc);
+    if (L.bytes > DAQ_NOALLOC_SCRATCH_BYTES) return DAQ_ERANGE;
+    DeviceGuard guard(ctx->device);
+    uint8_t *base = noalloc_ptr(ctx->device);
+    if (!base) return DAQ_EINVAL;
+    const hipStream_t stream = (hipStream_t)stream_;
+    int64_t raw_bytes = 0;
+    for (int32_t i = 0; i < n; i++) raw_bytes += 2 * (int64_t)fills[i].n_channels * fills[i].n_samples;
+    BatchHdr *d_hdr = reinterpret_cast<BatchHdr *>(base + L.hdr);
+    FillDev *d_table = reinterpret_cast<FillDev *>(d_hdr + 1);
+    KArgs a{};
+    a.table = d_table;
+    a.hdr = d_hdr;
+    a.tile_state = reinterpret_cast<uint64_t *>(base + L.tile_state);
+    a.ticket = reinterpret_cast<uint32_t *>(base + L.ticket);
+    a.thr_eff = reinterpret_cast<int64_t *>(base + L.thr_eff);
+    a.tile_pref = reinterpret_cast<uint64_t *>(base + L.tile_pref);
+    a.n_fills = n;
+    a.total_tiles = L.total_tiles;
+    a.stream_loads = raw_bytes > kStreamLoadBytes ? 1 : 0;
+    a.copy_slots = L.max_chunks * n;
+    a.part = 0;
+    a.parts = 1;
+    // descriptors, kPutFills per launch; the header with the first group
+    PutDescArgs put{};
+    put.hdr.n_fills = n;
+    put.hdr.stream_loads = a.stream_loads;
+    put.hdr.total_tiles = L.total_tiles;
+    put.hdr.copy_slots = a.copy_slots;
+    put.dst_hdr = d_hdr;
+    int64_t tile_base = 0, foff = L.fills;
+    for (int32_t i0 = 0; i0 < n; i0 += kPutFills) {
+        put.count = std::min<int32_t>(kPutFills, n - i0);
+        put.write_hdr = i0 == 0 ? 1 : 0;
+        put.dst = d_table + i0;
+        for (int32_t k = 0; k < put.count; k++) {
+            const daq_fill &f = fills[i0 + k];
+            const SplitLayout sl = split_layout_of(f, sc);
+            FillDev d = make_desc(f, outs[i0 + k], tile_base, sc);
+            d.mbits = base + foff + daqk::kMaskGuard;
+            d.runs = reinterpret_cast<int32_t *>(base + foff + sl.runs);
+            d.cmap = reinterpret_cast<int32_t *>(base + foff + sl.cmap);
+            put.d[k] = d;
+            tile_base += d.n_tiles;
+            foff += up16(sl.bytes);
+        }
+        hipLaunchKernelGGL(k_put_descs, dim3(1), dim3(kPutFills * sizeof(FillDev) / 16), 0, stream, put);
+        HIP_TRY(hipGetLastError());
+    }
+    int prep_blocks = (int)std::min<int64_t>(kPrepareBlocks, std::max<int64_t>(1, (L.total_tiles + 2047) / 2048));
+    prep_blocks = std::max(prep_blocks, std::min(n, kPrepareBlocks));
+    prep_blocks = std::min(prep_blocks, std::max(n, 64));
+    HIP_TRY(daqk::launch_prepare(a, prep_blocks, stream));
+    if (L.total_tiles == 0) return DAQ_OK;
+    const int grid = chop_grid(ctx, sc, L.total_tiles);
+    HIP_TRY(daqk::launch_scan(a, sc.threads, grid, stream));
+    const int pb = kPrefixBlocks;
+    HIP_TRY(daqk::launch_emit(a, sc.threads, grid, pb, stream));
+    return DAQ_OK;
 }
 
 int daq_process_batch_q(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, const daq_q_out *qouts,
