@@ -59,6 +59,7 @@ extern "C" {
 #define DAQ_EAGAIN (-5)   /* server: HBM budget or queue full, try later      */
 #define DAQ_ERANGE (-6)   /* a size exceeds a documented limit                */
 #define DAQ_EMISMATCH (-7) /* autotune: schedules disagreed (a library bug)   */
+#define DAQ_ETIMEDOUT (-8) /* server: a batch outlived the batch time-out     */
 
 /* ---- device-written status bits (daq_counts.status) -------------------- */
 #define DAQ_STATUS_CAPACITY 1   /* more islands than `capacity`: the first
@@ -213,9 +214,9 @@ int daq_process_batch(daq_ctx *ctx, const daq_fill *fills,
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * results as daq_process_batch, computed with the split schedule (the
  * context's thread count and persistent grid when it holds a split schedule,
- * else 256 threads and 16 work-groups per CU) by plain kernel launches only:
+ * else 512 threads and 8 work-groups per CU) by plain kernel launches only:
  * no allocation, no graph, no event, no memset and no host staging. Every
- * scratch buffer of the call (look-back words, tile totals and prefixes,
+ * scratch buffer of the call (look-back words, tile totals,
  * effective thresholds, the descriptor table, each fill's mask bits, run
  * table and chunk map) lives in one static device array of
  * DAQ_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from the first
@@ -370,8 +371,9 @@ typedef struct daq_z_stream {
 int daq_decompress_batch(daq_ctx *ctx, const daq_z_stream *streams, int32_t n,
                          void *stream);
 
-/* Schedule of the fused kernel used by daq_chop_fill / daq_process_batch.
- * EINVAL for values outside the documented sets. */
+/* Schedule of the fused kernel used by daq_chop_fill / daq_process_batch
+ * (a new context holds the split variant, 512 threads, 8 work-groups per
+ * CU). EINVAL for values outside the documented sets. */
 int daq_ctx_set_schedule(daq_ctx *ctx, const daq_schedule *s);
 int daq_ctx_get_schedule(daq_ctx *ctx, daq_schedule *s);
 
@@ -460,9 +462,12 @@ typedef struct daq_completion {
     daq_fill_out out;    /* device pointers into the arena, valid until
                             daq_release(ticket)                               */
     const int16_t *raw;  /* device raw rows the fill was chopped from        */
-    int32_t status;      /* DAQ_OK, or the error of the batch launch          */
+    int32_t status;      /* DAQ_OK, the error of the batch launch, or
+                            DAQ_ETIMEDOUT (counts are then zero and the slot
+                            is held until the device has finished with it)   */
     int32_t batch_fills; /* fills in the launch that carried this one        */
-    int64_t t_submit_ns; /* steady clock (ns): submit accepted                */
+    int64_t t_submit_ns; /* steady clock (ns): the fill's arrival (the time
+                            given to daq_submit_fill_at, else its admission)  */
     int64_t t_launch_ns; /* its batch handed to the device                    */
     int64_t t_ready_ns;  /* results complete in device memory                 */
 } daq_completion;
@@ -478,6 +483,14 @@ typedef struct daq_server_stats {
     uint64_t arena_peak;
     int32_t pending;      /* admitted, not yet launched                      */
     int32_t running;      /* launched, not yet complete                      */
+    /* deadtime accounting (the abstract asks for deadtime-free records):   */
+    uint64_t late;        /* fills admitted later than the admission deadline
+                             after their arrival                              */
+    uint64_t timed_out;   /* fills whose batch outlived the batch time-out   */
+    uint64_t deadtime_ns; /* total time during which the server refused
+                             fills: from a refused submit to the next
+                             admission                                        */
+    uint64_t admit_wait_max_ns; /* longest arrival-to-admission wait         */
 } daq_server_stats;
 
 /* Bytes of arena one fill takes (its slot, above). EINVAL as
@@ -500,20 +513,42 @@ int daq_server_create(daq_server **out, daq_ctx *ctx, void *d_arena,
 int daq_submit_fill(daq_server *srv, const daq_fill *fill, int32_t flags,
                     uint64_t tag, uint64_t *ticket);
 
+/* daq_submit_fill for a fill that arrived at t_arrive_ns on the steady clock
+ * (CLOCK_MONOTONIC, ns; 0 = now): a caller that retries after DAQ_EAGAIN
+ * passes the first attempt's time, so the admission wait, the deadline check
+ * and the completion's t_submit_ns run from the arrival. A time in the
+ * future is taken as now. */
+int daq_submit_fill_at(daq_server *srv, const daq_fill *fill, int32_t flags,
+                       uint64_t tag, int64_t t_arrive_ns, uint64_t *ticket);
+
+/* Limits of the serving loop (both 0 = none; at creation: a 10 ms admission
+ * deadline, the spacing of fills inside a burst (Section 3), and a 10 s
+ * batch time-out).
+ * admit_deadline_us: a fill admitted later than this after its arrival
+ *   counts in stats.late.
+ * batch_timeout_us: the longest a worker waits for its batch. Past it the
+ *   batch's fills complete with status DAQ_ETIMEDOUT and the worker takes
+ *   new work; their slots are freed (after daq_release) only once the device
+ *   has finished with them. EINVAL for negative values. */
+int daq_server_set_limits(daq_server *srv, int64_t admit_deadline_us,
+                          int64_t batch_timeout_us);
+
 /* Copies up to max finished fills (oldest completion first) to out and
  * returns how many; waits up to timeout_us for the first one (0 = do not
  * wait). Negative on error. */
 int daq_poll(daq_server *srv, daq_completion *out, int32_t max,
              int32_t timeout_us);
 
-/* Frees the slot of a finished fill. DAQ_EAGAIN while the fill is queued or
+/* Frees the slot of a finished fill (for a DAQ_ETIMEDOUT fill: once the
+ * device has finished with it). DAQ_EAGAIN while the fill is queued or
  * running, EINVAL for an unknown or already released ticket. */
 int daq_release(daq_server *srv, uint64_t ticket);
 
 int daq_server_get_stats(daq_server *srv, daq_server_stats *st);
 
-/* Stops the workers after their current launches (queued fills are dropped)
- * and frees the server's host and scratch memory. NULL ok. */
+/* Stops the workers after their current launches (queued fills are dropped),
+ * waits for the device to finish every launch (timed-out ones included) and
+ * frees the server's host and scratch memory. NULL ok. */
 void daq_server_destroy(daq_server *srv);
 
 #ifdef __cplusplus

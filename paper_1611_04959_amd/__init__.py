@@ -30,6 +30,7 @@ DAQ_ENOMEM = -4
 DAQ_EAGAIN = -5
 DAQ_ERANGE = -6
 DAQ_EMISMATCH = -7
+DAQ_ETIMEDOUT = -8
 DAQ_STATUS_CAPACITY = 1
 DAQ_STATUS_OUT_STRIDE = 2
 DAQ_STATUS_INCOMPLETE = 4
@@ -98,7 +99,9 @@ class daq_server_stats(ctypes.Structure):
                 ("completed", ctypes.c_uint64), ("released", ctypes.c_uint64),
                 ("batches", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
                 ("arena_in_use", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64),
-                ("pending", ctypes.c_int32), ("running", ctypes.c_int32)]
+                ("pending", ctypes.c_int32), ("running", ctypes.c_int32),
+                ("late", ctypes.c_uint64), ("timed_out", ctypes.c_uint64),
+                ("deadtime_ns", ctypes.c_uint64), ("admit_wait_max_ns", ctypes.c_uint64)]
 
 
 DAQ_SUBMIT_HOST_RAW = 1
@@ -170,6 +173,9 @@ def load_library():
         "daq_server_create": ([ctypes.POINTER(vp), vp, vp, ctypes.c_size_t, i32, i32], ctypes.c_int),
         "daq_submit_fill": ([vp, ctypes.POINTER(daq_fill), i32, ctypes.c_uint64,
                              ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "daq_submit_fill_at": ([vp, ctypes.POINTER(daq_fill), i32, ctypes.c_uint64, i64,
+                                ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "daq_server_set_limits": ([vp, i64, i64], ctypes.c_int),
         "daq_poll": ([vp, ctypes.POINTER(daq_completion), i32, i32], ctypes.c_int),
         "daq_release": ([vp, ctypes.c_uint64], ctypes.c_int),
         "daq_server_get_stats": ([vp, ctypes.POINTER(daq_server_stats)], ctypes.c_int),
@@ -344,6 +350,23 @@ def alloc_z_out(n_channels: int, max_len: int, words_cap: Optional[int] = None, 
                 torch.zeros(1, dtype=torch.int64, device=device))
 
 
+class Batch:
+    """The C arrays of one batch (daq_fill and daq_fill_out per fill), built
+    once so that repeated launches of the same fills and outputs skip the
+    argument marshalling. Holds references to the fills and outputs."""
+
+    def __init__(self, fills: Sequence["Fill"], outs: Sequence["FillOut"]):
+        if len(fills) != len(outs):
+            raise ValueError("fills and outs differ in length")
+        self.fills, self.outs = list(fills), list(outs)
+        self.n = len(self.fills)
+        self.fa = (daq_fill * max(self.n, 1))()
+        self.oa = (daq_fill_out * max(self.n, 1))()
+        for i, (f, o) in enumerate(zip(self.fills, self.outs)):
+            self.fa[i] = f.c_struct()
+            self.oa[i] = o.c_struct()
+
+
 class Context:
     """A daq_ctx on one HIP device."""
 
@@ -405,8 +428,12 @@ class Context:
             oa[i] = o.c_struct()
         return fa, oa, n
 
-    def daq_process_batch(self, fills: Sequence[Fill], outs: Sequence[FillOut], stream=None):
-        fa, oa, n = self._arrays(fills, outs)
+    def daq_process_batch(self, fills, outs: Optional[Sequence[FillOut]] = None, stream=None):
+        """fills: a sequence of Fill (with outs), or a prepared Batch (outs None)."""
+        if isinstance(fills, Batch):
+            fa, oa, n = fills.fa, fills.oa, fills.n
+        else:
+            fa, oa, n = self._arrays(fills, outs)
         _check(self._lib.daq_process_batch(self.handle, fa, oa, n, _stream_handle(stream)),
                "daq_process_batch")
 
@@ -520,7 +547,7 @@ def version() -> str:
     return load_library().daq_version().decode()
 
 
-__all__: List[str] = ["Context", "Fill", "FillOut", "alloc_out", "ZOut", "alloc_z_out", "z_words_bound", "daq_max_islands", "load_library",
+__all__: List[str] = ["Batch", "Context", "Fill", "FillOut", "alloc_out", "ZOut", "alloc_z_out", "z_words_bound", "daq_max_islands", "load_library",
                       "version", "DaqError", "padded", "daq_schedule"]
 
 
@@ -597,8 +624,18 @@ class Server:
     def __exit__(self, *exc):
         self.close()
 
-    def submit(self, fill: Fill, tag: int = 0, host_raw=None, host_packed12=None) -> Optional[int]:
+    def set_limits(self, admit_deadline_us: int = 10_000, batch_timeout_us: int = 10_000_000):
+        """daq_server_set_limits: admission deadline (late fills) and batch time-out (watchdog)."""
+        _check(self._lib.daq_server_set_limits(self._h, int(admit_deadline_us), int(batch_timeout_us)),
+               "daq_server_set_limits")
+
+    def submit(self, fill: Fill, tag: int = 0, host_raw=None, host_packed12=None,
+               arrival_ns: int = 0) -> Optional[int]:
         """Admits a fill; returns its ticket, or None when the budget is full now.
+
+        ``arrival_ns`` (``time.monotonic_ns()`` of the fill's arrival; 0 = now)
+        lets a caller that retries after a refusal keep the first attempt's
+        time (daq_submit_fill_at).
 
         With ``host_raw`` (a CPU int16 [C, row_stride] tensor, pinned for
         speed) the samples are copied into the arena by the server and
@@ -626,7 +663,8 @@ class Server:
             f.n_channels = int(host_raw.shape[0])
             flags = DAQ_SUBMIT_HOST_RAW
         t = ctypes.c_uint64(0)
-        rc = self._lib.daq_submit_fill(self._h, ctypes.byref(f), flags, int(tag), ctypes.byref(t))
+        rc = self._lib.daq_submit_fill_at(self._h, ctypes.byref(f), flags, int(tag), int(arrival_ns),
+                                          ctypes.byref(t))
         if rc == DAQ_EAGAIN:
             return None
         _check(rc, "daq_submit_fill")

@@ -27,9 +27,11 @@ constexpr int kVariantPipe = 6;      // one persistent kernel: scan tiles and co
 constexpr int kVariantLast = 6;
 // Guard bytes around each fill's island-mask bits (read as zero past the ends).
 constexpr int kMaskGuard = 16;
-// Packed samples per channel row that one work-group of the copy pass writes.
+// Packed positions per chunk of a row: the copy pass writes one chunk of a
+// channel group per wave (one 16-byte word per lane), and the edge pass
+// records the island holding every multiple of it.
 #ifndef DAQ_COPY_CHUNK
-#define DAQ_COPY_CHUNK 1024
+#define DAQ_COPY_CHUNK 512
 #endif
 constexpr int kCopyChunk = DAQ_COPY_CHUNK;
 // Tile of the LDS variant: groups of 8 samples per row buffer, work-group size.
@@ -148,7 +150,12 @@ hipError_t launch_chop(const KArgs &a, int threads, int variant, int grid, hipSt
 // Split variant: the scan pass, then the prefix, edge and copy passes, over
 // the fill group a.part of a.parts.
 hipError_t launch_scan(const KArgs &a, int threads, int grid, hipStream_t s);
-hipError_t launch_emit(const KArgs &a, int threads, int grid, int prefix_blocks, hipStream_t s);
+hipError_t launch_emit(const KArgs &a, int threads, int grid, int copy_grid, int prefix_blocks, hipStream_t s);
+// Work-groups per CU of the copy pass's persistent grid.
+#ifndef DAQ_COPY_WGS_PER_CU
+#define DAQ_COPY_WGS_PER_CU 4
+#endif
+constexpr int kCopyWgsPerCu = DAQ_COPY_WGS_PER_CU;
 hipError_t launch_pipe(const KArgs &a, int threads, int grid, hipStream_t s);
 hipError_t launch_q(const KArgs &a, int threads, int grid, hipStream_t s);
 hipError_t launch_unpack12(const uint8_t *in, int64_t in_stride, int32_t C, int64_t n, int16_t *out,

@@ -6,11 +6,13 @@
 //
 // k_prepare  per fill: pedestals (Table 2 pedestal row) and the effective
 //            threshold thr + sum(ped); clears the look-back words and counts.
-// k_scan_pass, k_prefix_pass, k_edge_pass, k_copy_pass
+// k_scan_pass, k_edge_pass, k_copy_pass
 //            the split schedule (the default): a streaming scan that writes
-//            one island-mask bit per sample and tile totals, the tiles'
-//            prefixes, the island records and a run table, and a copy of
-//            the island samples in equal chunks of packed positions.
+//            one island-mask bit per sample and tile totals; an edge pass
+//            (one wave per tile: its prefix from the totals of the fill's
+//            earlier tiles, the island records, a run table, the counts);
+//            and a copy of the island samples in equal chunks of packed
+//            positions.
 // k_pipe     one persistent kernel: scan tiles (steps 1-4a below) and copy
 //            chunks of finished fills, taken from shared counters.
 // k_chop     the fused pass. Each thread of a work-group takes 8 consecutive
@@ -782,9 +784,6 @@ __device__ __forceinline__ uint4 lds_read8(const uint32_t *base, int e) {
     return make_uint4(w0, w1, w2, w3);
 }
 
-#ifndef DAQ_STAGE_WORDS
-#define DAQ_STAGE_WORDS 2048  // staged words of the copy pass (two buffers)
-#endif
 
 // Descriptor of packed line j (an int4, the same for every channel when all
 // rows share one line phase): x = staged element of the line's first sample
@@ -1555,15 +1554,85 @@ __device__ __forceinline__ uint32_t tile_mask10(const FillDev &fd, const ChopGeo
     return m10;
 }
 
-// Scan pass, one tile: flags, dilation, mask bits, totals. The tile's word
-// in tile_state (zero before the launch) receives each wave's totals by an
-// atomic add, so the tile ends without a work-group barrier.
+constexpr int kPedChannels = 512;  // channels whose pedestal sums one round accumulates in LDS
+
+// Pedestals (Table 2 pedestal row): every channel's mean of its first
+// n = min(Np, N) samples, rounded half up (floor((2 P + n) / (2 n)) of the
+// int64 sum P); 0 for an empty fill. Returns their sum; writes ped[] when
+// `write`. Called by a whole work-group of NT threads (barriers inside); its
+// threads take (channel, 8-sample chunk) pairs with 16-byte loads, four per
+// thread and round with every load issued before the adds.
+template <int NT>
+__device__ int64_t fill_pedestals(const FillDev &fd, bool write, long long *s_acc, long long *s_ped) {
+    const int64_t n = fd.n < (int64_t)fd.np ? fd.n : (int64_t)fd.np;
+    const int64_t nch = (n + kVec - 1) / kVec;
+    if (threadIdx.x == 0) *s_ped = 0;
+    for (int c0 = 0; c0 < fd.C; c0 += kPedChannels) {
+        const int cn = fd.C - c0 < kPedChannels ? fd.C - c0 : kPedChannels;
+        for (int i = threadIdx.x; i < cn; i += NT) s_acc[i] = 0;
+        __syncthreads();
+        const int64_t items = (int64_t)cn * nch;
+        constexpr int kItems = 4;
+        for (int64_t i0 = threadIdx.x; i0 < items; i0 += NT * kItems) {
+            uint4 v[kItems];
+            int cl[kItems];
+            int64_t t[kItems];
+#pragma unroll
+            for (int u = 0; u < kItems; u++) {
+                const int64_t i = i0 + (int64_t)u * NT;
+                cl[u] = (int)(i / nch);
+                t[u] = (i - (int64_t)cl[u] * nch) * kVec;
+                if (i < items) v[u] = load16(fd.raw + (int64_t)(c0 + cl[u]) * fd.stride + t[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kItems; u++) {
+                if (i0 + (int64_t)u * NT >= items) break;
+                int32_t s[kVec] = {0, 0, 0, 0, 0, 0, 0, 0};
+                add8(s, v[u]);
+                int32_t part = 0;
+#pragma unroll
+                for (int k = 0; k < kVec; k++) part += (t[u] + k < n) ? s[k] : 0;
+                atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[cl[u]]), (unsigned long long)(long long)part);
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < cn; i += NT) {
+            const int32_t ped = n > 0 ? (int32_t)floor_div(2 * (int64_t)s_acc[i] + n, 2 * n) : 0;
+            if (write && fd.ped) fd.ped[c0 + i] = ped;
+            atomicAdd(reinterpret_cast<unsigned long long *>(s_ped), (unsigned long long)(long long)ped);
+        }
+        __syncthreads();
+    }
+    const int64_t sum = *s_ped;
+    __syncthreads();  // s_ped and s_acc are free again
+    return sum;
+}
+
+// Scan pass, one tile: flags, dilation, mask bits, totals. Each wave leaves
+// its totals (island samples, islands begun) in s_part; thread 0 adds them up
+// and stores the tile's word after the next tile's first barrier (or after
+// the work-group's last tile), so a tile ends without a barrier of its own
+// and tile_state needs no clearing. Before that, thread 0 stores the word of
+// the previous tile (prev_tile >= 0) from s_prev.
+template <int NT>
+__device__ __forceinline__ void put_tile_total(const KArgs &a, int64_t tile, const uint32_t *part) {
+    uint64_t m = 0, i = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; w++) {
+        m += part[w] >> 16;
+        i += part[w] & 0xFFFFu;
+    }
+    *gbl(a.tile_state + tile) = (m << 31) | i;
+}
+
 template <int NT, int R, bool Q = false>
 __device__ __forceinline__ void scan_pass_tile(const KArgs &a, const FillDev &fd, int32_t thr_eff, int64_t tile,
-                                               uint8_t *lds, int64_t ped_total = 0) {
+                                               uint8_t *lds, int64_t ped_total, uint32_t *s_part,
+                                               int64_t prev_tile, const uint32_t *s_prev) {
     const int lane = threadIdx.x & 63;
     const ChopGeom<NT> q(fd, tile);
     const uint32_t m10 = tile_mask10<NT, R, Q>(fd, q, thr_eff, lds, stream_loads(a), ped_total);
+    if (threadIdx.x == 0 && prev_tile >= 0) put_tile_total<NT>(a, prev_tile, s_prev);
     if (q.owner) {
         // the owned samples' mask byte: t0 is a multiple of 8
         const int64_t byte = (q.t0 >> 3) + (q.g - fd.gl);
@@ -1575,12 +1644,14 @@ __device__ __forceinline__ void scan_pass_tile(const KArgs &a, const FillDev &fd
     uint32_t mine = ((uint32_t)__popc(mm) << 16) | (uint32_t)__popc(rise);
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) mine += __shfl_xor(mine, d, 64);
-    if (lane == 0 && mine != 0u)
-        atomicAdd(reinterpret_cast<unsigned long long *>(a.tile_state + tile),
-                  (unsigned long long)(((uint64_t)(mine >> 16) << 31) | (uint64_t)(mine & 0xFFFFu)));
+    if (lane == 0) s_part[threadIdx.x >> 6] = mine;
 }
 
-template <int NT, int R, bool Q = false>
+// PED: the work-group computes the pedestals of each fill it meets (the
+// first min(Np, N) samples of every row, from L2 after the first reader) and
+// the tile-0 work-group writes them out; the mask guards are cleared by the
+// fill's first and last tiles. Otherwise k_prepare has done both.
+template <int NT, int R, bool Q = false, bool PED = false>
 __global__ void __launch_bounds__(NT) k_scan_pass(KArgs a) {
     // two bitmaps, used by alternate tiles: a wave still reading one tile's
     // bitmap never meets the next tile's writes, so tiles need no closing
@@ -1588,6 +1659,9 @@ __global__ void __launch_bounds__(NT) k_scan_pass(KArgs a) {
     // wave has passed)
     __shared__ __align__(16) uint8_t s_lds[2][ChopLds<NT>::kBitsBytes];
     __shared__ int64_t s_base[kLdsFills];
+    __shared__ uint32_t s_part[2][NT / 64];
+    __shared__ long long s_acc[kPedChannels];
+    __shared__ long long s_ped;
     const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
     const int64_t total = a.hdr ? a.hdr->total_tiles : a.total_tiles;
     const bool lds_fills = nf <= kLdsFills;
@@ -1599,6 +1673,7 @@ __global__ void __launch_bounds__(NT) k_scan_pass(KArgs a) {
     int32_t thr_eff = 0;
     int64_t ped_total = 0;  // Q: the sum of the fill's pedestals
     int buf = 0;
+    int64_t prev_tile = -1;
     const PartRange pr = part_range(a, nf, total);
     for (int64_t tile = pr.tile_lo + blockIdx.x; tile < pr.tile_hi; tile += gridDim.x) {
         if (cur < 0 || tile < fd.tile_base || tile >= fd.tile_base + fd.n_tiles) {
@@ -1609,63 +1684,26 @@ __global__ void __launch_bounds__(NT) k_scan_pass(KArgs a) {
                 else hi = mid - 1;
             }
             fd = fill_at(a, lo);
-            const int64_t te = *gbl(a.thr_eff + lo);
+            int64_t te;
+            if constexpr (PED) te = (int64_t)fd.thr + fill_pedestals<NT>(fd, tile == fd.tile_base, s_acc, &s_ped);
+            else te = *gbl(a.thr_eff + lo);
             thr_eff = clamp_thr(te);
             ped_total = te - (int64_t)fd.thr;
             cur = lo;
         }
-        scan_pass_tile<NT, R, Q>(a, fd, thr_eff, tile, s_lds[buf], ped_total);
+        if constexpr (PED) {
+            const int64_t lt = tile - fd.tile_base;
+            const int i = (int)threadIdx.x;
+            if (i < kMaskGuard && lt == 0) fd.mbits[i - kMaskGuard] = 0;
+            if (i < kMaskGuard && lt == fd.n_tiles - 1) fd.mbits[fd.n_tiles * fd.tout / kVec + i] = 0;
+        }
+        scan_pass_tile<NT, R, Q>(a, fd, thr_eff, tile, s_lds[buf], ped_total, s_part[buf], prev_tile, s_part[buf ^ 1]);
+        prev_tile = tile;
         buf ^= 1;
     }
+    lds_barrier();
+    if (threadIdx.x == 0 && prev_tile >= 0) put_tile_total<NT>(a, prev_tile, s_part[buf ^ 1]);
 }
-
-// Prefix pass: a block per fill scans the fill's tile totals into exclusive
-// prefixes and writes the fill's counts.
-__global__ void __launch_bounds__(256) k_prefix_pass(KArgs a) {
-    __shared__ uint64_t s_w[4];
-    const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
-    const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
-    const int64_t total = a.hdr ? a.hdr->total_tiles : a.total_tiles;
-    const PartRange pr = part_range(a, nf, total);
-    for (int f = pr.lo + blockIdx.x; f < pr.hi; f += gridDim.x) {
-        const FillDev fd = fill_at(a, f);
-        uint64_t carry = 0;
-        for (int64_t i0 = 0; i0 < fd.n_tiles; i0 += 256) {
-            const int64_t i = i0 + threadIdx.x;
-            const uint64_t v = i < fd.n_tiles ? *gbl(a.tile_state + fd.tile_base + i) : 0ull;
-            uint64_t inc = v;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const uint64_t u = __shfl_up(inc, d, 64);
-                if (lane >= d) inc += u;
-            }
-            if (lane == 63) s_w[wid] = inc;
-            lds_barrier();
-            uint64_t before = carry, all = carry;
-#pragma unroll
-            for (int w = 0; w < 4; w++) {
-                before += (w < wid) ? s_w[w] : 0ull;
-                all += s_w[w];
-            }
-            if (i < fd.n_tiles) *gbl(a.tile_pref + fd.tile_base + i) = before + inc - v;
-            carry = all;
-            lds_barrier();
-        }
-        if (threadIdx.x == 0 && fd.counts != nullptr) {
-            const int64_t n_isl = (int64_t)(carry & kField);
-            const int64_t tl = (int64_t)((carry >> 31) & kField);
-            int32_t status = (n_isl > fd.cap) ? DAQ_STATUS_CAPACITY : 0;
-            if (fd.out != nullptr && tl > fd.out_stride) status |= DAQ_STATUS_OUT_STRIDE;
-            DAQ_GLOBAL daq_counts *cnt = gbl(fd.counts);
-            cnt->n_islands = n_isl;
-            cnt->total_len = tl;
-            cnt->status = status;
-            cnt->reserved = 0;
-        }
-    }
-}
-
 
 // The run table entries (start, packed offset) of the islands the calling
 // thread begins and, for the multiple k of kCopyChunk among its packed
@@ -1700,10 +1738,12 @@ __device__ __forceinline__ void write_runs(const FillDev &fd, const TileScan &r,
     }
 }
 
-// Edge pass, one tile per wave: island edges from the mask bits, the island
-// records (capacity-limited), the fill's run table (start, offset of every
-// island) and, for every multiple k of kCopyChunk among the tile's packed
-// positions, the island holding packed position k. Lane l takes the tile's
+// Edge pass, one tile per wave: the tile's exclusive prefix (the sum of the
+// totals the scan pass wrote for the fill's earlier tiles), island edges from
+// the mask bits, the island records (capacity-limited), the fill's run table
+// (start, offset of every island), for every multiple k of kCopyChunk among
+// the tile's packed positions the island holding packed position k, and, from
+// the fill's last tile, the fill's counts. Lane l takes the tile's
 // owned mask bytes 8l .. 8l + 7 (64 samples); a tile owns at most 512 bytes.
 // Only wave-level scans: no barrier, and a work-group handles NT / 64 tiles
 // at once.
@@ -1726,7 +1766,24 @@ __device__ __forceinline__ void edge_wave_tile(const KArgs &a, const FillDev &fd
     const uint32_t cm = (uint32_t)__popcll(m), ci = (uint32_t)__popcll(rise);
     const uint32_t mine = (cm << 16) | ci;
     const uint32_t excl = wave_incl_scan_u32(mine, lane) - mine;
-    const uint64_t pref = *gbl(a.tile_pref + tile);
+    // the tile's exclusive prefix: the totals of the fill's earlier tiles
+    // (written by the scan pass, read from L2), summed by the wave
+    uint64_t pref = 0;
+    for (int64_t j = lane; j < lt; j += 64) pref += *gbl(a.tile_state + fd.tile_base + j);
+    pref = wave_sum_u64(pref);
+    if (lt == fd.n_tiles - 1 && lane == 0 && fd.counts != nullptr) {
+        // the fill's last tile writes the counts
+        const uint64_t all = pref + *gbl(a.tile_state + tile);
+        const int64_t n_isl = (int64_t)(all & kField);
+        const int64_t tl = (int64_t)((all >> 31) & kField);
+        int32_t status = (n_isl > fd.cap) ? DAQ_STATUS_CAPACITY : 0;
+        if (fd.out != nullptr && tl > fd.out_stride) status |= DAQ_STATUS_OUT_STRIDE;
+        DAQ_GLOBAL daq_counts *cnt = gbl(fd.counts);
+        cnt->n_islands = n_isl;
+        cnt->total_len = tl;
+        cnt->status = status;
+        cnt->reserved = 0;
+    }
     const int64_t mbase = (int64_t)((pref >> 31) & kField) + (int64_t)(excl >> 16);
     const int64_t ibase = (int64_t)(pref & kField) + (int64_t)(excl & 0xFFFFu);
     const int64_t p = t0 + (int64_t)b0 * 8;  // this lane's first sample
@@ -1780,6 +1837,22 @@ __global__ void __launch_bounds__(NT) k_edge_pass(KArgs a) {
     FillDev fd{};
     int cur = -1;
     const PartRange pr = part_range(a, nf, total);
+    // fills without samples have no tile: their counts and pedestals (all
+    // zero) come from here, each work-group taking some of the fills
+    for (int f = pr.lo + (int)blockIdx.x; f < pr.hi; f += (int)gridDim.x) {
+        const FillDev *fp = a.table ? a.table + f : &a.one;
+        if (fp->n_tiles != 0) continue;
+        daq_counts *cnt = fp->counts;
+        if (threadIdx.x == 0 && cnt != nullptr) {
+            cnt->n_islands = 0;
+            cnt->total_len = 0;
+            cnt->status = 0;
+            cnt->reserved = 0;
+        }
+        int32_t *ped = fp->ped;
+        if (ped != nullptr)
+            for (int c = (int)threadIdx.x; c < fp->C; c += NT) ped[c] = 0;
+    }
     for (int64_t tile = pr.tile_lo + (int64_t)blockIdx.x * NW + wid; tile < pr.tile_hi;
          tile += (int64_t)gridDim.x * NW) {
         if (cur < 0 || tile < fd.tile_base || tile >= fd.tile_base + fd.n_tiles) {
@@ -1795,15 +1868,6 @@ __global__ void __launch_bounds__(NT) k_edge_pass(KArgs a) {
         edge_wave_tile(a, fd, tile, lane);
     }
 }
-
-// Copy pass: every fill's packed rows are cut into chunks of kCopyChunk
-// packed positions; a work-group copies one chunk of every channel, so each
-// has the same work whatever the island density where the chunk came from.
-// Slot g is chunk g / n of fill g % n of the launch's n fills (chunks past a
-// fill's total length are empty). The chunk's islands (from the run table,
-// starting at the island that holds its first position) become an LDS run
-// table, written out by copy_runs.
-using CopyPassLayout = CopyLayout<kCopyChunk + 2, kCopyChunk / kVec + 3, DAQ_STAGE_WORDS / 2>;
 
 // The values a copy of chunk k needs besides the run table: the fill's
 // counts and the islands holding the chunk's first and last positions.
@@ -1850,26 +1914,242 @@ __device__ __forceinline__ void copy_chunk(const FillDev &fd, int64_t k, const C
     copy_runs<NT, L, U>(fd, v, nrun, m, q0);
 }
 
+// ---- copy pass of the split schedule ----------------------------------------------
+//
+// Writes the packed rows (the chopped islands of every channel) from the run
+// table and chunk map of the edge pass. A work item is one wave's: a fill, a
+// segment of kCopyChunk = 512 packed positions (one 16-byte word per lane)
+// and a group of kCopyGroup channels. Items are numbered fill by fill; every
+// work-group first computes the items of each fill from its counts (a prefix
+// in LDS), so the launch needs no host-side sizes and idle waves leave at
+// once. Per item the wave copies the segment's runs into its own LDS (source
+// sample of the run's first packed position, packed start relative to the
+// segment) and each lane finds the run holding its word's first position by
+// one max-scan over the lanes (run j marks the first word that starts at or
+// after its own start). Then, kCopyU channels at a time, every lane loads the
+// aligned 16-byte source words of its 8 samples (two per run piece: the word
+// holding the first sample and, when the samples run past it, the next),
+// realigns them, blends at a run boundary and writes one 16-byte word with a
+// non-temporal store: all loads of a round are in flight together and no
+// barrier is taken. A word holding pieces of three or more runs, the last
+// partial word of a row and rows whose line phase differs from their
+// neighbours' (out_stride not a multiple of 8 or out not 16-byte aligned) go
+// sample by sample.
+
+#ifndef DAQ_COPY_GROUP
+#define DAQ_COPY_GROUP 6  // channels per work item (54 = 9 x 6)
+#endif
+#ifndef DAQ_COPY_U
+#define DAQ_COPY_U 3  // channels with loads in flight per round
+#endif
+constexpr int kCopyGroup = DAQ_COPY_GROUP;
+constexpr int kCopyU = DAQ_COPY_U;
+constexpr int kSegRuns = kCopyChunk + 3;  // runs touching one segment, and two end marks
+static_assert(kCopyChunk == 64 * kVec, "a segment is one 16-byte word per lane");
+
+// Eight consecutive int16 samples from any element address (2-byte
+// aligned): one 16-byte load, which gfx950 serves unaligned (the HSA runtime
+// runs it in unaligned access mode).
+__device__ __forceinline__ uint4 load16u(const int16_t *p) {
+    u32x4 v;
+    __builtin_memcpy(&v, (const DAQ_GLOBAL int16_t *)p, 16);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// One round of the copy: the source samples of kCopyU channels starting at
+// channel c, for a lane whose word is one run (kind 1: v0) or two (kind 2:
+// v0, then v1 from element split on).
+__device__ __forceinline__ void copy_load(const FillDev &fd, int c, int c_hi, int kind, int src0, int src1,
+                                          uint4 (&v0)[kCopyU], uint4 (&v1)[kCopyU]) {
+#pragma unroll
+    for (int u = 0; u < kCopyU; u++) {
+        if (c + u < c_hi && (kind == 1 || kind == 2)) {
+            const int16_t *row = fd.raw + (int64_t)(c + u) * fd.stride;
+            v0[u] = load16u(row + src0);
+            if (kind == 2) v1[u] = load16u(row + src1);
+        }
+    }
+}
+
+__device__ __forceinline__ void copy_store(const FillDev &fd, int c, int c_hi, int kind, int split, int64_t o,
+                                           const uint4 (&v0)[kCopyU], const uint4 (&v1)[kCopyU]) {
+#pragma unroll
+    for (int u = 0; u < kCopyU; u++) {
+        if (c + u < c_hi && (kind == 1 || kind == 2)) {
+            const uint4 v = kind == 2 ? blend8(v0[u], v1[u], split) : v0[u];
+            store16(fd.out + (int64_t)(c + u) * fd.out_stride + o, v);
+        }
+    }
+}
+
+// Packed positions [q0, q0 + m) of channels [c_lo, c_hi) of fill fd; the
+// segment's nrun runs are in st[] / d[] (d relative to q0, d[0] <= 0, end
+// marks at nrun and nrun + 1). Executed by one whole wave.
+__device__ __forceinline__ void copy_segment(const FillDev &fd, int64_t q0, int m, int c_lo, int c_hi,
+                                             const int32_t *st, const int32_t *d, int32_t *slot, int nrun,
+                                             int lane) {
+    // run of each word's first position
+    slot[lane] = -1;
+    __builtin_amdgcn_wave_barrier();
+    for (int j = lane; j < nrun; j += 64) {
+        const int dj = d[j];
+        const int w = dj <= 0 ? 0 : (dj + kVec - 1) / kVec;
+        if (w < 64) atomicMax(&slot[w], j);
+    }
+    __builtin_amdgcn_wave_barrier();
+    int R = slot[lane];
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const int u = __shfl_up(R, s, 64);
+        if (lane >= s) R = R > u ? R : u;
+    }
+    const int pos = kVec * lane;                       // first packed position of this lane's word
+    const int valid = m - pos < kVec ? m - pos : kVec;  // positions of the word inside the segment
+    const int d0 = d[R], d1 = d[R + 1], d2 = d[R + 2];
+    const int st0 = st[R], st1 = st[R + 1];
+    const bool uniform = (fd.out_stride & 7) == 0 && ((uintptr_t)fd.out & 15u) == 0;
+    // kind 0: nothing; 1: one run; 2: two runs; 3: sample by sample
+    int kind = 0;
+    if (valid > 0) {
+        if (!uniform || valid < kVec) kind = 3;
+        else if (d1 >= pos + kVec) kind = 1;
+        else if (d2 >= pos + kVec) kind = 2;
+        else kind = 3;
+    }
+    // run R from source sample src0 on; run R + 1 from element split on, as
+    // source sample src1 + element. Every sample read lies in [src0, src0 + 8)
+    // or [src1, src1 + 8), inside the row: src1 >= src0 + 1 (runs are disjoint
+    // and at least one sample apart) and, for two runs, both end before the
+    // word's last sample, which is a sample of the fill.
+    const int src0 = st0 + (pos - d0);
+    const int split = kind == 2 ? d1 - pos : kVec;
+    const int src1 = st1 - split;
+    const int64_t o = q0 + pos;
+    uint4 a0[kCopyU], a1[kCopyU], b0[kCopyU], b1[kCopyU];
+#pragma unroll
+    for (int u = 0; u < kCopyU; u++) a0[u] = a1[u] = b0[u] = b1[u] = make_uint4(0, 0, 0, 0);
+    // rounds of kCopyU channels, double-buffered: the next round's loads are
+    // issued before this round's stores, so waiting for them never waits for
+    // the stores (loads and stores share one counter)
+    copy_load(fd, c_lo, c_hi, kind, src0, src1, a0, a1);
+    for (int c = c_lo; c < c_hi; c += 2 * kCopyU) {
+        if (c + kCopyU < c_hi) copy_load(fd, c + kCopyU, c_hi, kind, src0, src1, b0, b1);
+        copy_store(fd, c, c_hi, kind, split, o, a0, a1);
+        if (c + kCopyU >= c_hi) break;
+        if (c + 2 * kCopyU < c_hi) copy_load(fd, c + 2 * kCopyU, c_hi, kind, src0, src1, a0, a1);
+        copy_store(fd, c + kCopyU, c_hi, kind, split, o, b0, b1);
+    }
+    if (kind == 3) {
+        for (int c = c_lo; c < c_hi; c++) {
+            const int16_t *row = fd.raw + (int64_t)c * fd.stride;
+            DAQ_GLOBAL int16_t *orow = gbl(fd.out + (int64_t)c * fd.out_stride + q0);
+            int r = R;
+            for (int e = 0; e < valid; e++) {
+                const int q = pos + e;
+                while (r + 1 < nrun && d[r + 1] <= q) r++;
+                orow[q] = *gbl(row + st[r] + (q - d[r]));
+            }
+        }
+    }
+}
+
+constexpr int kCopyFills = kLdsFills;  // fills per window of the item prefix
+
 template <int NT>
 __global__ void __launch_bounds__(NT) k_copy_pass(KArgs a) {
-    __shared__ __align__(16) uint8_t s_lds[CopyPassLayout::kBytes];
-    const CopyView v = copy_view<CopyPassLayout>(s_lds);
+    constexpr int NW = NT / 64;
+    __shared__ int64_t s_item[kCopyFills + 1];
+    __shared__ int32_t s_tl[kCopyFills], s_nisl[kCopyFills];  // each fill's counts
+    __shared__ int32_t s_st[NW][kSegRuns];
+    __shared__ int32_t s_d[NW][kSegRuns];
+    __shared__ int32_t s_slot[NW][64];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
-    const int64_t all_slots = a.hdr ? a.hdr->copy_slots : a.copy_slots;
     const PartRange pr = part_range(a, nf, a.hdr ? a.hdr->total_tiles : a.total_tiles);
-    const int nfp = pr.hi - pr.lo;
-    const int64_t slots = nf > 0 ? all_slots / nf * nfp : 0;  // the part's fills x chunks of the longest fill
-    for (int64_t g = blockIdx.x; g < slots; g += gridDim.x) {
-        const int f = pr.lo + (int)(g % nfp);
-        const FillDev fd = fill_at(a, f);
-        if (fd.out == nullptr) continue;
-        const int64_t k = g / nfp;
-        ChunkInfo ci = chunk_info(fd, k);
-        ci.tl = __builtin_amdgcn_readfirstlane((int)ci.tl);
-        ci.n_isl = __builtin_amdgcn_readfirstlane((int)ci.n_isl);
-        ci.i0 = __builtin_amdgcn_readfirstlane(ci.i0);
-        ci.i1 = __builtin_amdgcn_readfirstlane(ci.i1);
-        copy_chunk<NT, CopyPassLayout>(fd, k, ci, v);
+    for (int w0 = pr.lo; w0 < pr.hi; w0 += kCopyFills) {
+        const int wn = pr.hi - w0 < kCopyFills ? pr.hi - w0 : kCopyFills;
+        // items of each fill of the window: segments of its packed rows x channel groups
+        for (int i = tid; i < wn; i += NT) {
+            const FillDev *fp = a.table ? a.table + w0 + i : &a.one;
+            int64_t items = 0;
+            const int16_t *out = fp->out;
+            if (out != nullptr) {
+                const daq_counts *cnt = fp->counts;
+                const int64_t tl = cnt->total_len;
+                const int64_t os = fp->out_stride;
+                const int64_t L = tl < os ? (tl > 0 ? tl : 0) : os;
+                items = (L + kCopyChunk - 1) / kCopyChunk * ((fp->C + kCopyGroup - 1) / kCopyGroup);
+                s_tl[i] = (int32_t)tl;
+                s_nisl[i] = (int32_t)cnt->n_islands;
+            }
+            s_item[i + 1] = items;
+        }
+        lds_barrier();
+        if (wid == 0) {  // inclusive scan of s_item[1 .. wn]
+            int64_t carry = 0;
+            for (int i0 = 0; i0 < wn; i0 += 64) {
+                const int i = i0 + lane;
+                int64_t v = i < wn ? s_item[i + 1] : 0;
+#pragma unroll
+                for (int s = 1; s < 64; s <<= 1) {
+                    const int64_t u = __shfl_up(v, s, 64);
+                    if (lane >= s) v += u;
+                }
+                if (i < wn) s_item[i + 1] = carry + v;
+                carry += __shfl(v, 63, 64);
+            }
+            if (lane == 0) s_item[0] = 0;
+        }
+        lds_barrier();
+        const int64_t total = s_item[wn];
+        FillDev fd{};
+        int cur = -1;
+        for (int64_t g = (int64_t)blockIdx.x * NW + wid; g < total; g += (int64_t)gridDim.x * NW) {
+            int lo = 0, hi = wn - 1;  // the fill: last i with s_item[i] <= g
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_item[mid] <= g) lo = mid;
+                else hi = mid - 1;
+            }
+            if (lo != cur) {
+                fd = fill_at(a, w0 + lo);
+                cur = lo;
+            }
+            const int groups = (fd.C + kCopyGroup - 1) / kCopyGroup;
+            const int64_t r = g - s_item[lo];
+            const int64_t k = r / groups;
+            const int cg = (int)(r - k * groups);
+            const int64_t tl = __builtin_amdgcn_readfirstlane(s_tl[lo]);
+            const int64_t n_isl = __builtin_amdgcn_readfirstlane(s_nisl[lo]);
+            const int64_t L = tl < fd.out_stride ? tl : fd.out_stride;
+            const int64_t q0 = k * kCopyChunk;
+            const int m = (int)(L - q0 < kCopyChunk ? L - q0 : kCopyChunk);
+            // both chunk-map words issued together (entry k + 1 exists: the map has two spare words)
+            const int e0 = *gbl(fd.cmap + k), e1 = *gbl(fd.cmap + k + 1);
+            const int i0 = __builtin_amdgcn_readfirstlane(e0);
+            const int i1 = q0 + kCopyChunk < tl ? __builtin_amdgcn_readfirstlane(e1) : (int)n_isl - 1;
+            int nrun = i1 - i0 + 1;  // at most kCopyChunk + 1
+            nrun = nrun < 1 ? 1 : (nrun > kSegRuns - 2 ? kSegRuns - 2 : nrun);
+            int32_t *st = s_st[wid];
+            int32_t *dd = s_d[wid];
+            for (int j = lane; j < nrun; j += 64) {
+                const DAQ_GLOBAL int32_t *e = gbl(fd.runs + 2 * (int64_t)(i0 + j));
+                st[j] = e[0];
+                dd[j] = (int32_t)((int64_t)e[1] - q0);
+            }
+            if (lane < 2) {
+                st[nrun + lane] = 0;
+                dd[nrun + lane] = 1 << 30;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int c_lo = cg * kCopyGroup;
+            const int c_hi = c_lo + kCopyGroup < fd.C ? c_lo + kCopyGroup : fd.C;
+            copy_segment(fd, q0, m, c_lo, c_hi, st, dd, s_slot[wid], nrun, lane);
+            __builtin_amdgcn_wave_barrier();
+        }
+        lds_barrier();  // the next window rewrites s_item
     }
 }
 
@@ -2177,12 +2457,11 @@ __global__ void __launch_bounds__(256) k_unpack12(const uint8_t *in, int64_t in_
     }
 }
 
-// Pedestals (Table 2 pedestal row), effective thresholds, cleared look-back
-// words and counts. A block handles whole fills; its threads take
-// (channel, 8-sample chunk) pairs of the pedestal window with 16-byte loads.
+// Effective thresholds (thr + the sum of the pedestals), pedestals, cleared
+// look-back words and counts, for the schedules whose scan does not compute
+// pedestals itself. A block handles whole fills.
 __global__ void __launch_bounds__(256) k_prepare(KArgs a) {
-    constexpr int kChan = 512;  // channels accumulated per round
-    __shared__ long long s_acc[kChan];
+    __shared__ long long s_acc[kPedChannels];
     __shared__ long long s_ped;
     const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
     const int64_t total = a.hdr ? a.hdr->total_tiles : a.total_tiles;
@@ -2191,47 +2470,7 @@ __global__ void __launch_bounds__(256) k_prepare(KArgs a) {
     if (blockIdx.x == 0 && threadIdx.x < 8) a.ticket[threadIdx.x] = 0;  // dispenser, copy cursor, flags
     for (int f = blockIdx.x; f < nf; f += gridDim.x) {
         const FillDev fd = fill_at(a, f);
-        const int64_t n = fd.n < (int64_t)fd.np ? fd.n : (int64_t)fd.np;
-        const int64_t nch = (n + kVec - 1) / kVec;
-        if (threadIdx.x == 0) s_ped = 0;
-        for (int c0 = 0; c0 < fd.C; c0 += kChan) {
-            const int cn = fd.C - c0 < kChan ? fd.C - c0 : kChan;
-            for (int i = threadIdx.x; i < cn; i += 256) s_acc[i] = 0;
-            __syncthreads();
-            const int64_t items = (int64_t)cn * nch;
-            // four items per thread and round, all loads issued before the adds
-            constexpr int kItems = 4;
-            for (int64_t i0 = threadIdx.x; i0 < items; i0 += 256 * kItems) {
-                uint4 v[kItems];
-                int cl[kItems];
-                int64_t t[kItems];
-#pragma unroll
-                for (int u = 0; u < kItems; u++) {
-                    const int64_t i = i0 + (int64_t)u * 256;
-                    cl[u] = (int)(i / nch);
-                    t[u] = (i - (int64_t)cl[u] * nch) * kVec;
-                    if (i < items) v[u] = load16(fd.raw + (int64_t)(c0 + cl[u]) * fd.stride + t[u]);
-                }
-#pragma unroll
-                for (int u = 0; u < kItems; u++) {
-                    if (i0 + (int64_t)u * 256 >= items) break;
-                    int32_t s[kVec] = {0, 0, 0, 0, 0, 0, 0, 0};
-                    add8(s, v[u]);
-                    int32_t part = 0;
-#pragma unroll
-                    for (int k = 0; k < kVec; k++) part += (t[u] + k < n) ? s[k] : 0;
-                    atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[cl[u]]),
-                              (unsigned long long)(long long)part);
-                }
-            }
-            __syncthreads();
-            for (int i = threadIdx.x; i < cn; i += 256) {
-                const int32_t ped = n > 0 ? (int32_t)floor_div(2 * (int64_t)s_acc[i] + n, 2 * n) : 0;
-                if (fd.ped) fd.ped[c0 + i] = ped;
-                atomicAdd(reinterpret_cast<unsigned long long *>(&s_ped), (unsigned long long)(long long)ped);
-            }
-            __syncthreads();
-        }
+        const int64_t ped_sum = fill_pedestals<256>(fd, true, s_acc, &s_ped);
         if (fd.qsum != nullptr)  // decimated sums built by atomic adds (fused Q-method)
             for (int64_t i = threadIdx.x; i < (fd.n + kQBin - 1) / kQBin; i += 256) fd.qsum[i] = 0;
         if (fd.mbits != nullptr && threadIdx.x < 2 * kMaskGuard) {
@@ -2240,7 +2479,7 @@ __global__ void __launch_bounds__(256) k_prepare(KArgs a) {
             fd.mbits[i < kMaskGuard ? i - kMaskGuard : nbytes + (i - kMaskGuard)] = 0;
         }
         if (threadIdx.x == 0) {
-            a.thr_eff[f] = (int64_t)fd.thr + (int64_t)s_ped;
+            a.thr_eff[f] = (int64_t)fd.thr + ped_sum;
             if (a.tile_pref) a.tile_pref[f] = 0;  // finished tiles (pipe variant)
             if (fd.counts) {
                 fd.counts->n_islands = 0;
@@ -2332,23 +2571,21 @@ hipError_t launch_scan(const KArgs &a, int threads, int grid, hipStream_t s) {
         else return hipErrorInvalidValue;
         return hipGetLastError();
     }
-    if (threads == 256) hipLaunchKernelGGL((k_scan_pass<256, DAQ_SCAN_ROWS>), dim3(grid), dim3(256), 0, s, a);
-    else if (threads == 512) hipLaunchKernelGGL((k_scan_pass<512, DAQ_SCAN_ROWS>), dim3(grid), dim3(512), 0, s, a);
+    // without the Q-method the scan computes the pedestals itself (no k_prepare)
+    if (threads == 256) hipLaunchKernelGGL((k_scan_pass<256, DAQ_SCAN_ROWS, false, true>), dim3(grid), dim3(256), 0, s, a);
+    else if (threads == 512) hipLaunchKernelGGL((k_scan_pass<512, DAQ_SCAN_ROWS, false, true>), dim3(grid), dim3(512), 0, s, a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-hipError_t launch_emit(const KArgs &a, int threads, int grid, int prefix_blocks, hipStream_t s) {
-    // the copy pass: as many work-groups as the chunks of the batch (graphs:
-    // the persistent grid, which strides over them)
-    int64_t cg = a.hdr ? (int64_t)grid : a.copy_slots;
-    cg = cg < 1 ? 1 : (cg < (1 << 30) ? cg : (1 << 30));
+hipError_t launch_emit(const KArgs &a, int threads, int grid, int copy_grid, int prefix_blocks, hipStream_t s) {
+    // the copy pass: a persistent grid whose waves stride over the work items
+    const int cg = copy_grid < 1 ? 1 : copy_grid;
+    (void)prefix_blocks;
     if (threads == 256) {
-        hipLaunchKernelGGL(k_prefix_pass, dim3(prefix_blocks), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_edge_pass<256>), dim3(grid), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_copy_pass<256>), dim3((int)cg), dim3(256), 0, s, a);
     } else if (threads == 512) {
-        hipLaunchKernelGGL(k_prefix_pass, dim3(prefix_blocks), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_edge_pass<512>), dim3(grid), dim3(512), 0, s, a);
         hipLaunchKernelGGL((k_copy_pass<512>), dim3((int)cg), dim3(512), 0, s, a);
     } else {

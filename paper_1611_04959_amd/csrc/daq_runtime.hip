@@ -45,7 +45,10 @@ constexpr int kRing = 4;          // pinned staging slots per stream
 // Launches reading more raw bytes than this stream them with non-temporal
 // loads; smaller ones keep their rows cached for the island write-out (the
 // last-level cache holds 256 MB).
-constexpr int64_t kStreamLoadBytes = 128ll << 20;
+#ifndef DAQ_STREAM_LOAD_MB
+#define DAQ_STREAM_LOAD_MB 128
+#endif
+constexpr int64_t kStreamLoadBytes = (int64_t)DAQ_STREAM_LOAD_MB << 20;
 constexpr int kPrepareBlocks = 1024;
 constexpr int kPrefixBlocks = 256;
 
@@ -97,7 +100,7 @@ struct daq_ctx {
     int n_cu = 0;
     std::string name;
     std::vector<Scratch *> scratch;
-    daq_schedule sched{256, 16, daqk::kVariantSplit, 0};
+    daq_schedule sched{512, 8, daqk::kVariantSplit, 0};
     bool graphs = true;
     bool timing = false;
     // event pairs bracketing fused-kernel launches while timing is on;
@@ -352,7 +355,7 @@ int launch_main(const daq_ctx *ctx, Scratch *sc, const KArgs &a, const daq_sched
             a1.part = 0;
             a1.parts = 1;
             HIP_TRY(daqk::launch_scan(a1, s.threads, grid, stream));
-            HIP_TRY(daqk::launch_emit(a1, s.threads, grid, pb, stream));
+            HIP_TRY(daqk::launch_emit(a1, s.threads, grid, daqk::kCopyWgsPerCu * ctx->n_cu, pb, stream));
             return DAQ_OK;
         }
         // fill group k runs on its own stream; its scan starts when group
@@ -372,7 +375,7 @@ int launch_main(const daq_ctx *ctx, Scratch *sc, const KArgs &a, const daq_sched
             }
             HIP_TRY(daqk::launch_scan(ak, s.threads, grid, sk));
             HIP_TRY(hipEventRecord(sc->ev_scan[k], sk));
-            HIP_TRY(daqk::launch_emit(ak, s.threads, grid, pb, sk));
+            HIP_TRY(daqk::launch_emit(ak, s.threads, grid, daqk::kCopyWgsPerCu * ctx->n_cu, pb, sk));
             if (k > 0) HIP_TRY(hipEventRecord(sc->ev_join[k], sk));
         }
         for (int k = 1; k < parts; k++) HIP_TRY(hipStreamWaitEvent(stream, sc->ev_join[k], 0));
@@ -384,12 +387,23 @@ int launch_main(const daq_ctx *ctx, Scratch *sc, const KArgs &a, const daq_sched
     return DAQ_OK;
 }
 
-int launch_pair(daq_ctx *ctx, Scratch *sc, const KArgs &a, int64_t total_tiles, hipStream_t stream,
-                const daq_schedule &s) {
+// Whether a launch needs k_prepare first: the split schedule's scan computes
+// the pedestals itself unless the Q-method rides along (its bins are cleared
+// by k_prepare).
+bool needs_prepare(const daq_schedule &s, const KArgs &a) {
+    return s.variant != daqk::kVariantSplit || a.q_fused != 0;
+}
+
+int prepare_blocks(const KArgs &a, int64_t total_tiles) {
     int prep_blocks = (int)std::min<int64_t>(kPrepareBlocks, std::max<int64_t>(1, (total_tiles + 2047) / 2048));
     prep_blocks = std::max(prep_blocks, std::min(a.n_fills, kPrepareBlocks));
-    prep_blocks = std::min(prep_blocks, std::max(a.n_fills, 64));
-    HIP_TRY(daqk::launch_prepare(a, prep_blocks, stream));
+    return std::min(prep_blocks, std::max(a.n_fills, 64));
+}
+
+int launch_pair(daq_ctx *ctx, Scratch *sc, const KArgs &a, int64_t total_tiles, hipStream_t stream,
+                const daq_schedule &s) {
+    // a launch without tiles only clears the counts and pedestals (k_prepare)
+    if (needs_prepare(s, a) || total_tiles == 0) HIP_TRY(daqk::launch_prepare(a, prepare_blocks(a, total_tiles), stream));
     if (total_tiles == 0) return DAQ_OK;
     size_t slot = 0;
     if (ctx->timing) {
@@ -415,15 +429,21 @@ int capture_graphs(daq_ctx *ctx, Scratch *s, const daq_schedule &sc) {
     a.thr_eff = s->thr_eff;
     a.tile_pref = s->tile_pref;
     hipGraph_t g = nullptr;
-    // prepare: grid covers the largest table this scratch holds
-    HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
-    hipError_t e = daqk::launch_prepare(a, kPrepareBlocks, ctx->capture);
-    hipError_t e2 = hipStreamEndCapture(ctx->capture, &g);
-    if (e != hipSuccess) return hip_fail(e);
-    if (e2 != hipSuccess) return hip_fail(e2);
-    e = hipGraphInstantiate(&s->g_prep, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return hip_fail(e);
+    // graphs never carry the Q-method: only schedules other than the split
+    // one need k_prepare
+    const bool prep = needs_prepare(sc, a);
+    hipError_t e = hipSuccess, e2 = hipSuccess;
+    if (prep) {
+        // prepare: grid covers the largest table this scratch holds
+        HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+        e = daqk::launch_prepare(a, kPrepareBlocks, ctx->capture);
+        e2 = hipStreamEndCapture(ctx->capture, &g);
+        if (e != hipSuccess) return hip_fail(e);
+        if (e2 != hipSuccess) return hip_fail(e2);
+        e = hipGraphInstantiate(&s->g_prep, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(e);
+    }
     HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
     const int rc0 = launch_main(ctx, s, a, sc, sc.wgs_per_cu * ctx->n_cu, ctx->capture);
     e2 = hipStreamEndCapture(ctx->capture, &g);
@@ -432,9 +452,9 @@ int capture_graphs(daq_ctx *ctx, Scratch *s, const daq_schedule &sc) {
     e = hipGraphInstantiate(&s->g_chop, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(e);
-    // prepare and main pass in one graph: one launch, no gap between the two
+    // prepare (if any) and main pass in one graph: one launch, no gap between the two
     HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
-    e = daqk::launch_prepare(a, kPrepareBlocks, ctx->capture);
+    e = prep ? daqk::launch_prepare(a, kPrepareBlocks, ctx->capture) : hipSuccess;
     const int rc1 = e == hipSuccess ? launch_main(ctx, s, a, sc, sc.wgs_per_cu * ctx->n_cu, ctx->capture) : DAQ_OK;
     e2 = hipStreamEndCapture(ctx->capture, &g);
     if (e != hipSuccess) return hip_fail(e);
@@ -592,7 +612,7 @@ int run_fused(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int
         HIP_TRY(hipGraphLaunch(s->g_all, stream));
         return DAQ_OK;
     }
-    HIP_TRY(hipGraphLaunch(s->g_prep, stream));
+    if (s->g_prep) HIP_TRY(hipGraphLaunch(s->g_prep, stream));
     size_t slot = 0;
     if (ctx->timing) {
         rc = timing_begin(ctx, stream, &slot);
@@ -867,7 +887,7 @@ NoAllocLayout noalloc_layout(const daq_fill *fills, int32_t n, const daq_schedul
 }
 
 daq_schedule noalloc_schedule(const daq_ctx *ctx) {
-    daq_schedule sc{256, 16, daqk::kVariantSplit, 0};
+    daq_schedule sc{512, 8, daqk::kVariantSplit, 0};
     if (ctx->sched.variant == daqk::kVariantSplit) {
         sc.threads = ctx->sched.threads;
         sc.wgs_per_cu = ctx->sched.wgs_per_cu > 0 ? ctx->sched.wgs_per_cu : 16;
@@ -893,6 +913,7 @@ const char *daq_strerror(int code) {
         case DAQ_EAGAIN: return "resource busy, try again";
         case DAQ_ERANGE: return "size exceeds a documented limit";
         case DAQ_EMISMATCH: return "autotune candidates produced different results";
+        case DAQ_ETIMEDOUT: return "batch outlived the server's batch time-out";
         default: return "unknown error";
     }
 }
@@ -1366,15 +1387,14 @@ int daq_process_batch_noalloc(daq_ctx *ctx, const daq_fill *fills, const daq_fil
         hipLaunchKernelGGL(k_put_descs, dim3(1), dim3(kPutFills * sizeof(FillDev) / 16), 0, stream, put);
         HIP_TRY(hipGetLastError());
     }
-    int prep_blocks = (int)std::min<int64_t>(kPrepareBlocks, std::max<int64_t>(1, (L.total_tiles + 2047) / 2048));
-    prep_blocks = std::max(prep_blocks, std::min(n, kPrepareBlocks));
-    prep_blocks = std::min(prep_blocks, std::max(n, 64));
-    HIP_TRY(daqk::launch_prepare(a, prep_blocks, stream));
-    if (L.total_tiles == 0) return DAQ_OK;
+    if (L.total_tiles == 0) {  // only counts and pedestals to clear
+        HIP_TRY(daqk::launch_prepare(a, prepare_blocks(a, 0), stream));
+        return DAQ_OK;
+    }
     const int grid = chop_grid(ctx, sc, L.total_tiles);
     HIP_TRY(daqk::launch_scan(a, sc.threads, grid, stream));
     const int pb = kPrefixBlocks;
-    HIP_TRY(daqk::launch_emit(a, sc.threads, grid, pb, stream));
+    HIP_TRY(daqk::launch_emit(a, sc.threads, grid, daqk::kCopyWgsPerCu * ctx->n_cu, pb, stream));
     return DAQ_OK;
 }
 
@@ -1467,9 +1487,9 @@ int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, 
     // the library's default first: it is the reference every other candidate
     // is compared with. The persistent variant is not on the menu (it never
     // won, and its bounded waits may give up); daq_ctx_set_schedule selects it.
-    const daq_schedule menu[] = {{256, 16, V5, 0},
+    const daq_schedule menu[] = {{512, 8, V5, 0},  {256, 16, V5, 0}, {512, 4, V5, 0},  {512, 8, V5, 2},
                                  {256, 16, V5, 2}, {256, 16, V5, 3}, {256, 16, V5, 4},
-                                 {256, 8, V5, 0},  {256, 8, V5, 2},  {512, 4, V5, 0},  {256, 4, V0, 0},
+                                 {256, 8, V5, 0},  {256, 8, V5, 2},  {256, 4, V0, 0},
                                  {256, 8, V0, 0},  {512, 2, V0, 0},  {256, 2, V2, 0},  {256, 4, V3, 0},
                                  {256, 3, V4, 0},  {128, 8, V0, 0},  {256, 1, V1, 0}};
     for (const daq_schedule &m : menu)
@@ -1508,16 +1528,20 @@ int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, 
                 break;
             }
         }
-        float tot = 0.f;
-        const int reps = 5;
+        // the median of ten timed launches (differences between the best
+        // schedules are a few percent)
+        constexpr int reps = 10;
+        float t[reps];
         for (int r = 0; r < reps && rc == DAQ_OK; r++) {
             rc = run_fused(ctx, fills, outs, n, st, true);
-            float ms = 0.f;
-            if (!rc) rc = daq_ctx_kernel_time(ctx, &ms);
-            tot += ms;
+            t[r] = 0.f;
+            if (!rc) rc = daq_ctx_kernel_time(ctx, &t[r]);
         }
-        if (!rc && tot / reps < best_ms) {
-            best_ms = tot / reps;
+        if (rc) break;
+        std::sort(t, t + reps);
+        const float med = 0.5f * (t[reps / 2 - 1] + t[reps / 2]);
+        if (med < best_ms) {
+            best_ms = med;
             best_s = cand[k];
         }
     }

@@ -9,6 +9,15 @@
 // with them on the device. A worker waits for its own batch, copies the
 // per-fill counts to the host in one transfer and publishes completions.
 //
+// Deadtime accounting (the abstract asks for deadtime-free records): a
+// fill's arrival time (given with daq_submit_fill_at by callers that retry
+// after DAQ_EAGAIN) starts its latency; fills admitted later than the
+// admission deadline count as late, and the time from a refused submit to the
+// next admission adds to the server's deadtime. A watchdog bounds each
+// worker's wait for its batch: past the batch time-out the batch's fills
+// complete with DAQ_ETIMEDOUT and the worker goes on, while their slots stay
+// held until the device has finished with them.
+//
 // Built on the public calls of the library only (daq_process_batch and the
 // context calls); the server adds host threads, the arena and one small
 // kernel that collects the counts of a batch.
@@ -88,7 +97,7 @@ SlotLayout layout_of(const daq_fill &f, int32_t flags) {
 }
 
 static_assert(sizeof(daq_completion) == 128, "daq_completion layout");
-static_assert(sizeof(daq_server_stats) == 72, "daq_server_stats layout");
+static_assert(sizeof(daq_server_stats) == 104, "daq_server_stats layout");
 
 // Gathers the counts of a batch into one array (one copy to the host).
 struct CountPtrs {
@@ -100,7 +109,8 @@ __global__ void k_collect_counts(CountPtrs ptrs, int n, daq_counts *dst) {
     if (i < n) dst[i] = *ptrs.p[i];
 }
 
-enum class State { kQueued, kRunning, kDone };
+// kHeld: completed with DAQ_ETIMEDOUT while the device may still use the slot.
+enum class State { kQueued, kRunning, kDone, kHeld };
 
 struct Job {
     uint64_t ticket = 0, tag = 0;
@@ -111,8 +121,9 @@ struct Job {
     uint8_t *dev_packed = nullptr;         // their place in the slot
     daq_fill_out out{};
     uint64_t offset = 0;    // slot offset in the arena
-    int64_t t_submit = 0;
+    int64_t t_submit = 0;   // arrival (steady clock)
     State state = State::kQueued;
+    bool released = false;  // kHeld: released by the caller, slot freed when the device is done
 };
 
 struct Worker {
@@ -122,6 +133,7 @@ struct Worker {
     daq_ctx *ctx = nullptr;
     daq_counts *d_counts = nullptr;  // kMaxBatch, device
     daq_counts *h_counts = nullptr;  // kMaxBatch, pinned host
+    std::vector<Job *> held;         // timed-out fills whose launches may still run
 };
 
 }  // namespace
@@ -142,9 +154,47 @@ struct daq_server {
     int32_t running = 0;
     daq_server_stats stats{};
     std::vector<Worker> workers;
+    std::atomic<int64_t> admit_deadline_ns{10'000'000};  // 10 ms: fill spacing in a burst
+    std::atomic<int64_t> batch_timeout_ns{10'000'000'000};
+    int64_t dead_since = -1;  // first refused submit of the current dead period, or -1
 };
 
 namespace {
+
+// Waits for `ev` at most limit_ns (yielding for the first 2 ms, then
+// sleeping 50 us between polls); *timed_out when it did not complete.
+hipError_t wait_event(hipEvent_t ev, int64_t limit_ns, bool *timed_out) {
+    const int64_t t0 = now_ns();
+    *timed_out = false;
+    for (;;) {
+        const hipError_t q = hipEventQuery(ev);
+        if (q != hipErrorNotReady) return q;
+        const int64_t dt = now_ns() - t0;
+        if (dt >= limit_ns) {
+            *timed_out = true;
+            return hipSuccess;
+        }
+        if (dt < 2'000'000) std::this_thread::yield();
+        else std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+}
+
+// With srv->mu held: once the worker's last launch has finished, its held
+// (timed-out) fills are done with: released ones give their slots back, the
+// others become ordinary finished fills.
+void reclaim_held(daq_server *srv, Worker *w) {
+    if (w->held.empty() || hipEventQuery(w->done) != hipSuccess) return;
+    for (Job *j : w->held) {
+        if (j->released) {
+            srv->arena.release(j->offset);
+            srv->jobs.erase(j->ticket);
+            delete j;
+        } else {
+            j->state = State::kDone;
+        }
+    }
+    w->held.clear();
+}
 
 void worker_loop(daq_server *srv, Worker *w) {
     (void)hipSetDevice(srv->device);
@@ -155,7 +205,12 @@ void worker_loop(daq_server *srv, Worker *w) {
         batch.clear();
         {
             std::unique_lock<std::mutex> lk(srv->mu);
-            srv->cv_work.wait(lk, [&] { return srv->stop || !srv->queue.empty(); });
+            for (;;) {
+                reclaim_held(srv, w);
+                if (srv->stop || !srv->queue.empty()) break;
+                if (w->held.empty()) srv->cv_work.wait(lk);
+                else srv->cv_work.wait_for(lk, std::chrono::milliseconds(1));
+            }
             if (srv->stop) return;
             while (!srv->queue.empty() && (int32_t)batch.size() < srv->max_batch) {
                 Job *j = srv->queue.front();
@@ -191,6 +246,7 @@ void worker_loop(daq_server *srv, Worker *w) {
             }
         }
         const int64_t t_launch = now_ns();
+        bool timed_out = false;
         if (he == hipSuccess) rc = daq_process_batch(w->ctx, fills.data(), outs.data(), n, w->stream);
         else rc = DAQ_EHIP;
         if (rc == DAQ_OK) {
@@ -202,8 +258,13 @@ void worker_loop(daq_server *srv, Worker *w) {
                 he = hipMemcpyAsync(w->h_counts, w->d_counts, (size_t)n * sizeof(daq_counts),
                                     hipMemcpyDeviceToHost, w->stream);
             if (he == hipSuccess) he = hipEventRecord(w->done, w->stream);
-            if (he == hipSuccess) he = hipEventSynchronize(w->done);
+            if (he == hipSuccess) {
+                const int64_t limit = srv->batch_timeout_ns.load(std::memory_order_relaxed);
+                if (limit > 0) he = wait_event(w->done, limit, &timed_out);
+                else he = hipEventSynchronize(w->done);
+            }
             if (he != hipSuccess) rc = DAQ_EHIP;
+            else if (timed_out) rc = DAQ_ETIMEDOUT;
         } else {
             // the copies above may be in flight: wait for the stream before
             // the slots can be handed back
@@ -224,11 +285,17 @@ void worker_loop(daq_server *srv, Worker *w) {
             c.t_submit_ns = j->t_submit;
             c.t_launch_ns = t_launch;
             c.t_ready_ns = t_ready;
-            j->state = State::kDone;
+            if (timed_out) {
+                j->state = State::kHeld;
+                w->held.push_back(j);
+            } else {
+                j->state = State::kDone;
+            }
             srv->done.push_back(c);
         }
         srv->running -= n;
         srv->stats.completed += (uint64_t)n;
+        if (timed_out) srv->stats.timed_out += (uint64_t)n;
         srv->cv_done.notify_all();
     }
 }
@@ -297,6 +364,11 @@ int daq_server_create(daq_server **out, daq_ctx *ctx, void *d_arena, size_t aren
 }
 
 int daq_submit_fill(daq_server *srv, const daq_fill *fill, int32_t flags, uint64_t tag, uint64_t *ticket) {
+    return daq_submit_fill_at(srv, fill, flags, tag, 0, ticket);
+}
+
+int daq_submit_fill_at(daq_server *srv, const daq_fill *fill, int32_t flags, uint64_t tag, int64_t t_arrive_ns,
+                       uint64_t *ticket) {
     if (!srv || !ticket) return DAQ_EINVAL;
     int rc = check_submit_fill(fill, flags);
     if (rc) return rc;
@@ -307,12 +379,23 @@ int daq_submit_fill(daq_server *srv, const daq_fill *fill, int32_t flags, uint64
         delete j;
         return DAQ_ERANGE;
     }
+    const int64_t now = now_ns();
     const int64_t off = srv->arena.alloc(L.bytes);
     if (off < 0) {
         srv->stats.rejected++;
+        if (srv->dead_since < 0) srv->dead_since = now;
         delete j;
         return DAQ_EAGAIN;
     }
+    if (srv->dead_since >= 0) {
+        srv->stats.deadtime_ns += (uint64_t)(now - srv->dead_since);
+        srv->dead_since = -1;
+    }
+    const int64_t t_arr = (t_arrive_ns > 0 && t_arrive_ns <= now) ? t_arrive_ns : now;
+    const uint64_t wait = (uint64_t)(now - t_arr);
+    if (wait > srv->stats.admit_wait_max_ns) srv->stats.admit_wait_max_ns = wait;
+    const int64_t deadline = srv->admit_deadline_ns.load(std::memory_order_relaxed);
+    if (deadline > 0 && (int64_t)wait > deadline) srv->stats.late++;
     uint8_t *base = srv->arena_base + off;
     j->ticket = srv->next_ticket++;
     j->tag = tag;
@@ -334,7 +417,7 @@ int daq_submit_fill(daq_server *srv, const daq_fill *fill, int32_t flags, uint64
     j->out.out = reinterpret_cast<int16_t *>(base + L.out);
     j->out.out_stride = L.out_stride;
     j->offset = (uint64_t)off;
-    j->t_submit = now_ns();
+    j->t_submit = t_arr;
     srv->jobs[j->ticket] = j;
     srv->queue.push_back(j);
     srv->stats.submitted++;
@@ -363,11 +446,25 @@ int daq_release(daq_server *srv, uint64_t ticket) {
     auto it = srv->jobs.find(ticket);
     if (it == srv->jobs.end()) return DAQ_EINVAL;
     Job *j = it->second;
+    if (j->state == State::kHeld) {
+        if (j->released) return DAQ_EINVAL;
+        j->released = true;  // the worker frees the slot once the device is done
+        srv->stats.released++;
+        return DAQ_OK;
+    }
     if (j->state != State::kDone) return DAQ_EAGAIN;
     srv->arena.release(j->offset);
     srv->jobs.erase(it);
     delete j;
     srv->stats.released++;
+    return DAQ_OK;
+}
+
+int daq_server_set_limits(daq_server *srv, int64_t admit_deadline_us, int64_t batch_timeout_us) {
+    if (!srv || admit_deadline_us < 0 || batch_timeout_us < 0) return DAQ_EINVAL;
+    const int64_t big = INT64_MAX / 1000;
+    srv->admit_deadline_ns.store(admit_deadline_us > big ? INT64_MAX : admit_deadline_us * 1000);
+    srv->batch_timeout_ns.store(batch_timeout_us > big ? INT64_MAX : batch_timeout_us * 1000);
     return DAQ_OK;
 }
 
@@ -393,6 +490,7 @@ void daq_server_destroy(daq_server *srv) {
         if (w.th.joinable()) w.th.join();
     for (Worker &w : srv->workers) {
         if (w.stream) (void)hipStreamSynchronize(w.stream);
+        w.held.clear();  // owned by srv->jobs
         free_worker(w);
     }
     for (auto &kv : srv->jobs) delete kv.second;

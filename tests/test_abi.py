@@ -117,6 +117,8 @@ def test_server_calls_reject_null_handles_without_touching_a_gpu():
     f = daq.daq_fill(0x1000, 10, 16, 1, 100, -200, 8, 24, 0)
     t = ctypes.c_uint64(0)
     assert lib.daq_submit_fill(None, ctypes.byref(f), 0, 0, ctypes.byref(t)) == daq.DAQ_EINVAL
+    assert lib.daq_submit_fill_at(None, ctypes.byref(f), 0, 0, 0, ctypes.byref(t)) == daq.DAQ_EINVAL
+    assert lib.daq_server_set_limits(None, 10, 10) == daq.DAQ_EINVAL
     buf = (daq.daq_completion * 4)()
     assert lib.daq_poll(None, buf, 4, 0) == daq.DAQ_EINVAL
     assert lib.daq_release(None, 1) == daq.DAQ_EINVAL
@@ -130,7 +132,7 @@ def test_server_calls_reject_null_handles_without_touching_a_gpu():
 def test_server_struct_layouts():
     assert ctypes.sizeof(daq.daq_counts) == 24
     assert ctypes.sizeof(daq.daq_completion) == 8 + 8 + 24 + 48 + 8 + 4 + 4 + 24
-    assert ctypes.sizeof(daq.daq_server_stats) == 8 * 8 + 8
+    assert ctypes.sizeof(daq.daq_server_stats) == 8 * 8 + 8 + 4 * 8
 
 
 def test_header_constants_match_the_binding():

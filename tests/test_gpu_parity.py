@@ -28,9 +28,9 @@ SCHEDULES = [(256, 2, 2, 0), (256, 1, 2, 0), (256, 0, 2, 0), (256, 4, 0, 0), (25
              (512, 1, 1, 0), (128, 8, 0, 0), (128, 2, 1, 0), (256, 0, 0, 0), (512, 0, 1, 0), (256, 4, 3, 0),
              (512, 2, 3, 0), (256, 3, 4, 0), (256, 8, 5, 0), (512, 2, 5, 0), (256, 0, 5, 0), (256, 16, 5, 2),
              (256, 16, 5, 3), (512, 4, 5, 4), (256, 0, 5, 2), (256, 4, 6, 0), (512, 2, 6, 0), (256, 0, 6, 0),
-             (256, 1, 6, 0)]
+             (256, 1, 6, 0), (512, 8, 5, 0)]
 MODES = ["chop", "twopass", "batch"]
-DEFAULT = (256, 16, 5, 0)  # the library's default schedule
+DEFAULT = (512, 8, 5, 0)  # the library's default schedule
 
 
 @pytest.fixture(scope="module")

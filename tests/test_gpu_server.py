@@ -287,3 +287,71 @@ def test_serving_burst_full_size(ctx):
         assert rejected > 0 and st.rejected == rejected  # the budget did bind
         assert sorted(c.tag for c in got) == list(range(len(fills)))
         assert st.arena_in_use == 0
+
+
+def test_deadtime_accounting_and_watchdog(ctx, workload):
+    """Forced from the host, every kernel running normally: a fill whose
+    arrival lies 50 ms back is late against the 10 ms admission deadline; the
+    time between a refused submit and the next admission is deadtime; a 1 us
+    batch time-out makes the watchdog give up on batches that are still
+    running (their fills complete with DAQ_ETIMEDOUT and their slots are held
+    until the device is done with them); with the time-out back at 10 s the
+    server serves exact results again."""
+    specs, xs, xd, fills, refs = workload
+    C = synth.CHANNELS
+    size = [daq.slot_bytes(f) for f in fills]
+    order = sorted(range(len(fills)), key=lambda i: size[i])
+    small, big1, big2 = order[0], order[-1], order[-2]
+    arena = poison(torch.empty(size[big1] + size[big2] + 256, dtype=torch.uint8, device="cuda"))
+    with daq.Server(ctx, arena, n_streams=2, max_batch=2) as srv:
+        srv.set_limits(admit_deadline_us=10_000, batch_timeout_us=10_000_000)
+        # late admission
+        t_arr = time.monotonic_ns() - 50_000_000
+        t = srv.submit(fills[small], tag=small, arrival_ns=t_arr)
+        (c,) = _drain(srv, 1).values()
+        _check(srv, c, refs[small], C, "late fill")
+        assert c.t_submit_ns == t_arr and c.t_ready_ns - c.t_submit_ns >= 50_000_000
+        st = srv.stats()
+        assert st.late == 1 and st.admit_wait_max_ns >= 50_000_000 and st.deadtime_ns == 0
+        srv.release(t)
+        # deadtime: the budget holds the two largest fills; a third is refused
+        t1 = srv.submit(fills[big1], tag=big1)
+        t2 = srv.submit(fills[big2], tag=big2)
+        assert t1 is not None and t2 is not None
+        assert srv.submit(fills[small], tag=small) is None
+        time.sleep(0.02)
+        for c in _drain(srv, 2).values():
+            _check(srv, c, refs[c.tag], C, "deadtime %d" % c.tag)
+        srv.release(t1)
+        srv.release(t2)
+        t3 = srv.submit(fills[small], tag=small)
+        assert t3 is not None
+        st = srv.stats()
+        assert st.deadtime_ns >= 20_000_000 and st.rejected == 1
+        _drain(srv, 1)
+        srv.release(t3)
+        # watchdog: a 1 us time-out expires while the batches still run
+        srv.set_limits(admit_deadline_us=10_000, batch_timeout_us=1)
+        tickets = [srv.submit(fills[i], tag=i) for i in (big1, big2)]
+        assert all(t is not None for t in tickets)
+        got = _drain(srv, 2)
+        timed_out = [c for c in got.values() if c.error == daq.DAQ_ETIMEDOUT]
+        assert timed_out, "no batch outlived a 1 us time-out"
+        for c in got.values():
+            assert c.error in (daq.DAQ_OK, daq.DAQ_ETIMEDOUT)
+            if c.error == daq.DAQ_ETIMEDOUT:
+                assert c.n_islands == 0 and c.total_len == 0
+            srv.release(c.ticket)
+        assert srv.stats().timed_out == len(timed_out)
+        t_end = time.time() + 10
+        while srv.stats().arena_in_use != 0:  # held slots come back once the device is done
+            assert time.time() < t_end, "held slots were not reclaimed"
+            time.sleep(0.005)
+        # and back to normal
+        srv.set_limits(admit_deadline_us=10_000, batch_timeout_us=10_000_000)
+        t4 = srv.submit(fills[big1], tag=big1)
+        (c,) = _drain(srv, 1).values()
+        _check(srv, c, refs[big1], C, "after the watchdog")
+        srv.release(t4)
+        with pytest.raises(daq.DaqError):
+            srv.set_limits(admit_deadline_us=-1)
