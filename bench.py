@@ -28,6 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+UNEVEN = "24 uneven calorimeter streams: N ~ U{100k..560k}, rate 0.5-4x, thr -400..-150, pre 4-16, post 16-48"
+STRESS = "whole detector: 4 fills x 24 calorimeters x 54 ch x 560,000, 10x rate, thr -100, pre 8, post 48"
 # Fill-0 results of each line, checked against the CPU oracle in the oracle
 # leg at the end: (kind, dict that receives "parity_fill0", payload).
 PENDING = []
@@ -62,27 +64,47 @@ def distinct_copies(xd, k):
     return out
 
 
-def ceiling():
-    """A plain HBM rate on this GPU for context: a 1 GiB device copy (read +
-    write bytes), by HIP events."""
+def ceiling(daq):
+    """Plain HBM rates on this GPU: a streaming read of 2 GiB (daq_read_stream,
+    the best of four grid sizes; the ceiling of the summing scan) and a
+    1 GiB device copy (read + write bytes), by HIP events."""
     import torch
     n = 1 << 30
-    src = torch.ones(n // 2, dtype=torch.int16, device="cuda")
-    dst = torch.empty_like(src)
     out = {}
-    for name, fn, nbytes in (("copy_gbs", lambda: dst.copy_(src), 2 * n),):
+    buf = torch.ones(n, dtype=torch.int16, device="cuda")  # 2 GiB
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    best = 0.0
+    for per_cu in (4, 8, 16, 32):
+        blocks = per_cu * cus
+        sink = torch.empty(blocks * 4, dtype=torch.int32, device="cuda")
         for _ in range(3):
-            fn()
+            daq.read_stream(buf, sink, blocks)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
         for _ in range(10):
-            fn()
+            daq.read_stream(buf, sink, blocks)
         b.record()
         torch.cuda.synchronize()
-        out[name] = round(nbytes * 10 / (a.elapsed_time(b) * 1e-3) / 1e9, 1)
+        rate = 2 * n * 10 / (a.elapsed_time(b) * 1e-3) / 1e9
+        if rate > best:
+            best, out["read_blocks_per_cu"] = rate, per_cu
+    out["read_gbs"] = round(best, 1)
+    del buf
+    src = torch.ones(n // 2, dtype=torch.int16, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(10):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    out["copy_gbs"] = round(2 * n * 10 / (a.elapsed_time(b) * 1e-3) / 1e9, 1)
     del src, dst
     torch.cuda.empty_cache()
-    out["what"] = "torch device copy of 1 GiB, read + write bytes"
+    out["what"] = ("read_gbs: one streaming read of 2 GiB with 16-byte non-temporal loads (daq_read_stream); "
+                   "copy_gbs: torch device copy of 1 GiB, read + write bytes")
     return out
 
 
@@ -100,7 +122,6 @@ def batch_bench(daq, synth, specs, what, steps=20, warmup=3):
     raw = sum(sp.raw_bytes for sp in specs)
     ctx = daq.Context(0)
     best = ctx.daq_autotune(fills, outs)
-    ctx.set_graphs(True)
     batch = daq.Batch(fills, outs)
     for _ in range(warmup):
         ctx.daq_process_batch(batch)
@@ -115,6 +136,7 @@ def batch_bench(daq, synth, specs, what, steps=20, warmup=3):
     ctx.set_timing(False)
     cnt = torch.stack([o.counts for o in outs]).cpu().numpy()
     tot = int(cnt[:, 1].sum())
+    graphs = ctx.get_graphs()
     ctx.close()
     res = {"workload": what, "fills": len(specs), "raw_gb": round(raw / 1e9, 3),
            "seeds": [sp.seed for sp in specs], "islands": [int(v) for v in cnt[:, 0]],
@@ -123,7 +145,7 @@ def batch_bench(daq, synth, specs, what, steps=20, warmup=3):
            "kernel_ms_mean": round(float(np.mean(kern)), 4) if kern else None,
            "occupancy": round(tot / sum(sp.n_samples for sp in specs), 4),
            "schedule": {"threads": best.threads, "wgs_per_cu": best.wgs_per_cu, "variant": best.variant,
-                        "parts": best.parts},
+                        "parts": best.parts, "graphs": graphs},
            "steps": steps, "parity_fill0": None}
     PENDING.append(("chop", res, (xs[0], specs[0], outs[0].host())))
     del xd, fills, outs
@@ -632,6 +654,8 @@ def main():
     ap.add_argument("--no-tq", action="store_true", help="skip the fused T-method + Q-method line")
     ap.add_argument("--no-stress", action="store_true",
                     help="skip the whole-detector stress batch (96 calorimeter fills, 5.8 GB)")
+    ap.add_argument("--only-batch", choices=["uneven", "stress"], default=None,
+                    help="time only that batch shape and print its line (for profiling)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -645,6 +669,11 @@ def main():
 
     import paper_1611_04959_amd as daq
     import synth
+
+    if args.only_batch:
+        what = {"uneven": (synth.config_c2(), UNEVEN), "stress": (synth.config_c4(), STRESS)}[args.only_batch]
+        print(json.dumps(batch_bench(daq, synth, what[0], what[1], steps=args.steps, warmup=args.warmup)), flush=True)
+        return
 
     specs = synth.config_c1(args.fills)
     C, N = synth.CHANNELS, specs[0].n_samples
@@ -666,8 +695,8 @@ def main():
     else:
         s = ctx.get_schedule()
         sched = (s.threads, s.wgs_per_cu, s.variant, s.parts)
-    log("schedule threads=%d wgs_per_cu=%d variant=%d parts=%d" % sched)
-    ctx.set_graphs(True)
+    graphs = ctx.get_graphs()  # the tuner's choice of graph replay or plain launches
+    log("schedule threads=%d wgs_per_cu=%d variant=%d parts=%d" % sched + (", graphs" if graphs else ", plain launches"))
 
     # ---- batched: warm-up then the timed region --------------------------------
     batch = daq.Batch(fills, outs)  # argument arrays built once
@@ -816,8 +845,8 @@ def main():
             log("plain %s: %.1f GB/s" % (mode, plain[mode]["gbs"]))
 
     # ---- plain HBM rates for context ------------------------------------------------
-    ceil = ceiling()
-    log("ceiling: device copy %.0f GB/s" % ceil["copy_gbs"])
+    ceil = ceiling(daq)
+    log("ceiling: streaming read %.0f GB/s, device copy %.0f GB/s" % (ceil["read_gbs"], ceil["copy_gbs"]))
 
     # ---- the Q-method on the same fills ---------------------------------------------------
     qmethod = None
@@ -853,13 +882,9 @@ def main():
     # ---- the other batch shapes: uneven batch, whole-detector stress -----------------
     others = {}
     if not args.no_uneven:
-        others["uneven"] = batch_bench(daq, synth, synth.config_c2(), "24 uneven calorimeter streams: N ~ "
-                                       "U{100k..560k}, rate 0.5-4x, thr -400..-150, pre 4-16, post 16-48",
-                                       steps=max(10, args.steps // 2))
+        others["uneven"] = batch_bench(daq, synth, synth.config_c2(), UNEVEN, steps=max(10, args.steps // 2))
     if not args.no_stress:
-        others["stress"] = batch_bench(daq, synth, synth.config_c4(), "whole detector: 4 fills x 24 "
-                                       "calorimeters x 54 ch x 560,000, 10x rate, thr -100, pre 8, post 48",
-                                       steps=max(5, args.steps // 10))
+        others["stress"] = batch_bench(daq, synth, synth.config_c4(), STRESS, steps=max(5, args.steps // 10))
 
     # ---- serving loop: Poisson arrivals with bursts, HBM-budget admission -------------
     serving = None
@@ -926,11 +951,11 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": "16 fills x 54 ch x 560,000 int16 samples, 3x pulse rate, "
-                               "thr -200, pre 8, post 24; batched persistent launch (graph)",
+                               "thr -200, pre 8, post 24; one batched launch per step",
                    "fills": len(specs), "channels": C, "samples": N, "rate": 3.0,
                    "threshold": -200, "pre": 8, "post": 24, "ped_samples": 100,
                    "schedule": {"threads": sched[0], "wgs_per_cu": sched[1], "variant": sched[2],
-                                "parts": sched[3]},
+                                "parts": sched[3], "graphs": graphs},
                    "seeds": [s.seed for s in specs]},
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "batched": {"gbs": round(value, 1), "p50_fill_ms": round(pct(step_ms, 50), 4),

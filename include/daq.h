@@ -377,8 +377,10 @@ int daq_decompress_batch(daq_ctx *ctx, const daq_z_stream *streams, int32_t n,
 int daq_ctx_set_schedule(daq_ctx *ctx, const daq_schedule *s);
 int daq_ctx_get_schedule(daq_ctx *ctx, daq_schedule *s);
 
-/* Use captured HIP graphs for daq_process_batch (default on). */
+/* Use captured HIP graphs for daq_process_batch (default on; daq_autotune
+ * may switch it). daq_ctx_get_graphs writes the current mode (0 or 1). */
 int daq_ctx_set_graphs(daq_ctx *ctx, int enable);
+int daq_ctx_get_graphs(daq_ctx *ctx, int *enable);
 
 /* Kernel timing: when on, each fused-kernel launch is bracketed by a pair of
  * HIP events on its stream (between the two graph launches when graphs are
@@ -403,10 +405,13 @@ int daq_ctx_kernel_times(daq_ctx *ctx, float *ms, int32_t max);
  * out_stride) with a copy of the first candidate's outputs (the library's
  * default split schedule). The menu holds the split, re-read, register and
  * LDS variants; DAQ_VARIANT_PIPE is chosen only by daq_ctx_set_schedule.
- * Allocates a device copy of the outputs for the duration of the call.
- * Synchronises `stream`; the outputs hold the last candidate's (identical)
- * results. When cache_path is not NULL the choice is looked up there first
- * and stored there after tuning, keyed by device name and batch shape. */
+ * The winning schedule is then timed replayed from its captured graph and as
+ * plain kernel launches, and the context's graph mode (daq_ctx_set_graphs)
+ * is set to the faster one. Allocates a device copy of the outputs for the
+ * duration of the call. Synchronises `stream`; the outputs hold the last
+ * candidate's (identical) results. When cache_path is not NULL the choice
+ * (schedule and graph mode) is looked up there first and stored there after
+ * tuning, keyed by device name and batch shape. */
 int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs,
                  int32_t n, void *stream, const char *cache_path,
                  daq_schedule *best);
@@ -550,6 +555,17 @@ int daq_server_get_stats(daq_server *srv, daq_server_stats *st);
  * waits for the device to finish every launch (timed-out ones included) and
  * frees the server's host and scratch memory. NULL ok. */
 void daq_server_destroy(daq_server *srv);
+
+/* ---- measurement -----------------------------------------------------------
+ * The device's plain streaming-read rate, the ceiling the chop's summing scan
+ * (which reads every raw sample once) is measured against: reads
+ * floor(bytes / 16) 16-byte words of d_buf (16-byte aligned) once with
+ * non-temporal loads in a grid of `blocks` work-groups of 256 threads, and
+ * writes one word per wave (an XOR of what it read) to d_sink, which must
+ * hold blocks * 4 words. Asynchronous on `stream`; time it with events.
+ * EINVAL for null pointers, bytes < 16, blocks < 1 or a misaligned buffer. */
+int daq_read_stream(const void *d_buf, int64_t bytes, unsigned int *d_sink,
+                    int32_t blocks, void *stream);
 
 #ifdef __cplusplus
 }

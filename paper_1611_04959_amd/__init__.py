@@ -159,9 +159,11 @@ def load_library():
         "daq_compress_batch": ([vp, ctypes.POINTER(daq_z_fill), i32, vp], ctypes.c_int),
         "daq_decompress_batch": ([vp, ctypes.POINTER(daq_z_stream), i32, vp], ctypes.c_int),
         "daq_packed12_stride": ([i64], i64),
+        "daq_read_stream": ([vp, i64, vp, i32, vp], ctypes.c_int),
         "daq_ctx_set_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
         "daq_ctx_get_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
         "daq_ctx_set_graphs": ([vp, ctypes.c_int], ctypes.c_int),
+        "daq_ctx_get_graphs": ([vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "daq_ctx_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
         "daq_ctx_kernel_time": ([vp, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
         "daq_ctx_kernel_times": ([vp, ctypes.POINTER(ctypes.c_float), i32], ctypes.c_int),
@@ -527,6 +529,11 @@ class Context:
     def set_graphs(self, enable: bool):
         _check(self._lib.daq_ctx_set_graphs(self.handle, int(bool(enable))), "daq_ctx_set_graphs")
 
+    def get_graphs(self) -> bool:
+        v = ctypes.c_int(0)
+        _check(self._lib.daq_ctx_get_graphs(self.handle, ctypes.byref(v)), "daq_ctx_get_graphs")
+        return bool(v.value)
+
     def set_timing(self, enable: bool):
         _check(self._lib.daq_ctx_set_timing(self.handle, int(bool(enable))), "daq_ctx_set_timing")
 
@@ -541,6 +548,13 @@ class Context:
         ms = ctypes.c_float()
         _check(self._lib.daq_ctx_kernel_time(self.handle, ctypes.byref(ms)), "daq_ctx_kernel_time")
         return float(ms.value)
+
+
+def read_stream(buf, sink, blocks: int, stream=None):
+    """daq_read_stream: one streaming read of a device tensor (the device's read ceiling)."""
+    _check(load_library().daq_read_stream(buf.data_ptr(), int(buf.numel() * buf.element_size()),
+                                          sink.data_ptr(), int(blocks), _stream_handle(stream)),
+           "daq_read_stream")
 
 
 def version() -> str:

@@ -15,7 +15,8 @@ LIB = os.path.join(HERE, "libdaqisland.so")
 SOURCES = [os.path.join(HERE, "csrc", "chop_kernels.hip"),
            os.path.join(HERE, "csrc", "daq_runtime.hip"),
            os.path.join(HERE, "csrc", "daq_server.hip"),
-           os.path.join(HERE, "csrc", "compress_kernels.hip")]
+           os.path.join(HERE, "csrc", "compress_kernels.hip"),
+           os.path.join(HERE, "csrc", "ceiling.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Wall", "-Wno-unused-result",

@@ -11,8 +11,13 @@ the reported figures are bytes.
          COPY_FETCH_DIR COPY_WRITE_DIR OUT_JSON [fills]
   python -m paper_1611_04959_amd.traffic stats KERNEL_STATS_CSV
 
+  python -m paper_1611_04959_amd.traffic tail KERNEL_TRACE_CSV K
+
 ``summarize`` writes OUT_JSON (read by bench.py) and prints a text summary;
-``stats`` prints a rocprofv3 ``--stats`` kernel table as markdown.
+``stats`` prints a rocprofv3 ``--stats`` kernel table as markdown; ``tail``
+prints the mean duration of each chop kernel over its last K dispatches and
+the mean span of the last K launches (first kernel start to last kernel end),
+i.e. the timed steps of a run whose autotuning came first.
 """
 from __future__ import annotations
 
@@ -137,11 +142,42 @@ def stats_table(path):
     print("One launch (every kernel above named k_*): %.1f us of kernel time." % tot)
 
 
+def tail(path, k):
+    rows = list(csv.DictReader(open(path, newline="")))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    seq = []
+    for r in rows:
+        name = short(r["Kernel_Name"])
+        if name is not None:
+            seq.append((name, int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    last = {}
+    for name, a, b, full in seq:
+        last.setdefault(name, []).append((a, b, full))
+    print("| Kernel | Dispatches | Mean of the last %d (us) |" % k)
+    print("|---|---|---|")
+    for name, v in sorted(last.items(), key=lambda kv: kv[1][-1][0]):
+        t = [(b - a) / 1e3 for a, b, _ in v[-k:]]
+        label = v[-1][2].replace("daqk::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+        print("| `%s` | %d | %.1f |" % (label, len(v), sum(t) / len(t)))
+    # launches: a scan (or fused) dispatch opens one
+    opens = [i for i, x in enumerate(seq) if x[0] in ("k_scan_pass", "k_chop", "k_pipe")]
+    spans = []
+    for j, i in enumerate(opens[-k:]):
+        nxt = opens[opens.index(i) + 1] if opens.index(i) + 1 < len(opens) else len(seq)
+        spans.append((seq[nxt - 1][2] - seq[i][1]) / 1e3)
+    if spans:
+        print()
+        print("Mean span of the last %d launches (first kernel start to last kernel end): %.1f us"
+              % (len(spans), sum(spans) / len(spans)))
+
+
 if __name__ == "__main__":
     if len(sys.argv) >= 2 and sys.argv[1] == "copy":
         copy_run(int(sys.argv[2]) if len(sys.argv) > 2 else 1024)
     elif len(sys.argv) == 3 and sys.argv[1] == "stats":
         stats_table(sys.argv[2])
+    elif len(sys.argv) == 4 and sys.argv[1] == "tail":
+        tail(sys.argv[2], int(sys.argv[3]))
     elif len(sys.argv) >= 7 and sys.argv[1] == "summarize":
         summarize(*sys.argv[2:7], fills=int(sys.argv[7]) if len(sys.argv) > 7 else 16)
     else:
