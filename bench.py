@@ -66,7 +66,7 @@ def distinct_copies(xd, k):
 
 def ceiling(daq):
     """Plain HBM rates on this GPU: a streaming read of 2 GiB (daq_read_stream,
-    the best of four grid sizes; the ceiling of the summing scan) and a
+    the best of two layouts and four grid sizes; the ceiling of the summing scan) and a
     1 GiB device copy (read + write bytes), by HIP events."""
     import torch
     n = 1 << 30
@@ -74,22 +74,45 @@ def ceiling(daq):
     buf = torch.ones(n, dtype=torch.int16, device="cuda")  # 2 GiB
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     best = 0.0
-    for per_cu in (4, 8, 16, 32):
+    for layout in (0, 1):
+        for per_cu in (4, 8, 16, 32):
+            blocks = per_cu * cus
+            sink = torch.empty(blocks * 4, dtype=torch.int32, device="cuda")
+            for _ in range(3):
+                daq.read_stream(buf, sink, blocks, layout)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(10):
+                daq.read_stream(buf, sink, blocks, layout)
+            b.record()
+            torch.cuda.synchronize()
+            rate = 2 * n * 10 / (a.elapsed_time(b) * 1e-3) / 1e9
+            if rate > best:
+                best, out["read_blocks_per_cu"], out["read_layout"] = rate, per_cu, layout
+    out["read_gbs"] = round(best, 1)
+    del buf
+    # the scan's own read pattern (tiles of 4,096 samples x 54 rows, 6 rows in
+    # flight) over 16 fills of 54 x 560,000, with nothing else done
+    nf, C, N = 16, 54, 560_000
+    raw = torch.ones(nf * C * N, dtype=torch.int16, device="cuda")
+    best_t = None
+    for per_cu in (4, 8, 16):
         blocks = per_cu * cus
-        sink = torch.empty(blocks * 4, dtype=torch.int32, device="cuda")
+        sink = torch.empty(blocks * 8, dtype=torch.int32, device="cuda")
         for _ in range(3):
-            daq.read_stream(buf, sink, blocks)
+            daq.read_tiles(raw, nf, C, N, sink, blocks)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
         for _ in range(10):
-            daq.read_stream(buf, sink, blocks)
+            daq.read_tiles(raw, nf, C, N, sink, blocks)
         b.record()
         torch.cuda.synchronize()
-        rate = 2 * n * 10 / (a.elapsed_time(b) * 1e-3) / 1e9
-        if rate > best:
-            best, out["read_blocks_per_cu"] = rate, per_cu
-    out["read_gbs"] = round(best, 1)
-    del buf
+        us = a.elapsed_time(b) * 1e3 / 10
+        if best_t is None or us < best_t:
+            best_t, out["tiles_blocks_per_cu"] = us, per_cu
+    out["scan_pattern_us_16fills"] = round(best_t, 1)
+    out["scan_pattern_gbs"] = round(2 * nf * C * N / (best_t * 1e-6) / 1e9, 1)
+    del raw
     src = torch.ones(n // 2, dtype=torch.int16, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -104,6 +127,8 @@ def ceiling(daq):
     del src, dst
     torch.cuda.empty_cache()
     out["what"] = ("read_gbs: one streaming read of 2 GiB with 16-byte non-temporal loads (daq_read_stream); "
+                   "scan_pattern_gbs: the 16 bench-shaped fills read in the chop scan's tiles and nothing else "
+                   "(daq_read_tiles), raw bytes over time; "
                    "copy_gbs: torch device copy of 1 GiB, read + write bytes")
     return out
 
@@ -126,27 +151,90 @@ def batch_bench(daq, synth, specs, what, steps=20, warmup=3):
     for _ in range(warmup):
         ctx.daq_process_batch(batch)
     torch.cuda.synchronize()
-    ctx.set_timing(True)
+    # timed as the main batch: events only at both ends of the region, then
+    # each launch between its own events for the latency percentiles
+    stream = torch.cuda.current_stream()
+    ev_a, ev_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    ev_a.record(stream)
     for _ in range(steps):
         ctx.daq_process_batch(batch)
+    ev_b.record(stream)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
-    kern = ctx.kernel_times_ms()
-    ctx.set_timing(False)
+    launch_ms = ev_a.elapsed_time(ev_b) / steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(stream)
+        ctx.daq_process_batch(batch)
+        b.record(stream)
+    torch.cuda.synchronize()
+    step_ms = [a.elapsed_time(b) for a, b in ev]
     cnt = torch.stack([o.counts for o in outs]).cpu().numpy()
     tot = int(cnt[:, 1].sum())
+    alg = sum(2 * sp.n_channels * sp.n_samples for sp in specs) \
+        + sum(2 * sp.n_channels * int(t) + 24 * int(n) + 24 + 4 * sp.n_channels
+              for sp, n, t in zip(specs, cnt[:, 0], cnt[:, 1]))
     graphs = ctx.get_graphs()
     ctx.close()
     res = {"workload": what, "fills": len(specs), "raw_gb": round(raw / 1e9, 3),
            "seeds": [sp.seed for sp in specs], "islands": [int(v) for v in cnt[:, 0]],
            "ms_per_step": round(ms, 4), "gbs": round(raw / (ms * 1e-3) / 1e9, 1),
            "pct_hbm_peak": round(100 * raw / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
-           "kernel_ms_mean": round(float(np.mean(kern)), 4) if kern else None,
+           "kernel_ms_mean": round(launch_ms, 4),
+           "algorithmic_bytes_per_launch": int(alg),
+           "algorithmic_gbs": round(alg / (launch_ms * 1e-3) / 1e9, 1),
+           "p50_fill_ms": round(pct(step_ms, 50), 4), "p99_fill_ms": round(pct(step_ms, 99), 4),
            "occupancy": round(tot / sum(sp.n_samples for sp in specs), 4),
            "schedule": {"threads": best.threads, "wgs_per_cu": best.wgs_per_cu, "variant": best.variant,
                         "parts": best.parts, "graphs": graphs},
            "steps": steps, "parity_fill0": None}
+    PENDING.append(("chop", res, (xs[0], specs[0], outs[0].host())))
+    del xd, fills, outs
+    torch.cuda.empty_cache()
+    return res
+
+
+def plain_c0_bench(daq, synth, ctx, rounds=10):
+    """The plain form at the single-fill shape: eight 54 x 560,000 fills at the
+    nominal rate (distinct seeds, 484 MB together, more than the 256 MB
+    last-level cache), one daq_chop_fill call each, in turn; per-call latency
+    by HIP events around each call."""
+    import numpy as np
+    import torch
+    specs = [synth.config_c0(i)[0] for i in range(8)]
+    xs = synth.render_many(specs)
+    xd = synth.to_device(xs)
+    fills = [daq.Fill(d, sp.n_samples, threshold=sp.threshold, pre=sp.pre, post=sp.post,
+                      ped_samples=sp.ped_samples) for d, sp in zip(xd, specs)]
+    outs = [daq.alloc_out(f) for f in fills]
+    st = torch.cuda.current_stream()
+    for f, o in zip(fills, outs):
+        ctx.daq_chop_fill(f, o, st)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(rounds * len(fills))]
+    t0 = time.perf_counter()
+    for r in range(rounds):
+        for i, (f, o) in enumerate(zip(fills, outs)):
+            a, b = ev[r * len(fills) + i]
+            a.record(st)
+            ctx.daq_chop_fill(f, o, st)
+            b.record(st)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / (rounds * len(fills))
+    lat = [a.elapsed_time(b) for a, b in ev]
+    cnt = torch.stack([o.counts for o in outs]).cpu().numpy()
+    alg = sum(2 * sp.n_channels * sp.n_samples + 2 * sp.n_channels * int(t) + 24 * int(n) + 24 + 4 * sp.n_channels
+              for sp, n, t in zip(specs, cnt[:, 0], cnt[:, 1]))
+    res = {"workload": "plain form, one call per fill: 8 fills of 54 ch x 560,000 at the nominal rate "
+                       "(thr -200, pre 8, post 24), distinct seeds, taken in turn",
+           "seeds": [sp.seed for sp in specs], "islands": [int(v) for v in cnt[:, 0]],
+           "occupancy": round(float(cnt[:, 1].sum()) / sum(sp.n_samples for sp in specs), 4),
+           "ms_per_fill": round(ms, 4), "gbs": round(specs[0].raw_bytes / (ms * 1e-3) / 1e9, 1),
+           "algorithmic_gbs": round(alg / len(specs) / (ms * 1e-3) / 1e9, 1),
+           "p50_fill_ms": round(pct(lat, 50), 4), "p99_fill_ms": round(pct(lat, 99), 4),
+           "parity_fill0": None}
     PENDING.append(("chop", res, (xs[0], specs[0], outs[0].host())))
     del xd, fills, outs
     torch.cuda.empty_cache()
@@ -578,8 +666,9 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
         st = srv.stats()
         res = {"fills": len(lat), "p50_ms": round(pct(lat, 50), 4), "p99_ms": round(pct(lat, 99), 4),
                "max_ms": round(max(lat), 4), "gbs": round(done_bytes / wall / 1e9, 1),
-               "wall_s": round(wall, 2), "batches": int(st.batches),
-               "peak_resident_gb": round(st.arena_peak / 1e9, 2),
+               "wall_s": round(wall, 2), "batches": int(st.batches - st0.batches),
+               # high-water mark of the arena since the server started (all runs so far)
+               "arena_high_water_gb": round(st.arena_peak / 1e9, 2),
                "late_fills": int(st.late - st0.late), "deadtime_ms": round((st.deadtime_ns - st0.deadtime_ns) / 1e6, 3),
                "refused_submits": int(st.rejected - st0.rejected), "timed_out": int(st.timed_out - st0.timed_out),
                "parity_fill0": None}
@@ -730,7 +819,8 @@ def main():
         ev[k][1].record(stream)
     torch.cuda.synchronize()
     step_ms = [a.elapsed_time(b) for a, b in ev]
-    # the passes after k_prepare alone, timed by the library (a separate short run)
+    # the library's own per-launch timing (event pairs around each launch,
+    # which cost a few microseconds each), in a separate short run
     ctx.set_timing(True)
     for _ in range(max(5, args.steps // 5)):
         ctx.daq_process_batch(batch, stream=stream)
@@ -801,13 +891,13 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
                 "traffic": traffic,
-                "kernel": {5: "chop launch: one graph of k_prepare, k_scan_pass, k_prefix_pass, k_edge_pass, k_copy_pass",
-                           6: "chop launch: one graph of k_prepare, k_pipe"}.get(
-                               sched[2], "chop launch: one graph of k_prepare, k_chop"),
+                "kernel": {5: "chop launch: k_scan_pass, k_edge_pass, k_copy_pass",
+                           6: "chop launch: k_prepare, k_pipe"}.get(sched[2], "chop launch: k_prepare, k_chop")
+                          + (" (one graph)" if graphs else " (plain launches)"),
                 "kernel_ms_mean": round(kmean, 4),
                 "kernel_launches_timed": args.steps,
                 "timing": "HIP events on the launch stream at both ends of the timed region",
-                "passes_without_prepare_ms_mean": round(float(np.mean(kern_ms)), 4) if kern_ms else None,
+                "library_timed_launch_ms_mean": round(float(np.mean(kern_ms)), 4) if kern_ms else None,
                 "algorithmic_bytes_per_launch": alg_bytes}
 
     # ---- plain per-fill launches (the form batching must beat) ---------------------
@@ -843,6 +933,8 @@ def main():
             plain[mode] = {"gbs": round(raw_bytes / (pms * 1e-3) / 1e9, 1), "ms_per_step": round(pms, 4),
                            "p50_fill_ms": round(pct(lat, 50), 4), "p99_fill_ms": round(pct(lat, 99), 4)}
             log("plain %s: %.1f GB/s" % (mode, plain[mode]["gbs"]))
+        log("plain form at the single-fill shape (nominal rate)")
+        plain["c0"] = plain_c0_bench(daq, synth, ctx)
 
     # ---- plain HBM rates for context ------------------------------------------------
     ceil = ceiling(daq)

@@ -382,9 +382,12 @@ int daq_ctx_get_schedule(daq_ctx *ctx, daq_schedule *s);
 int daq_ctx_set_graphs(daq_ctx *ctx, int enable);
 int daq_ctx_get_graphs(daq_ctx *ctx, int *enable);
 
-/* Kernel timing: when on, each fused-kernel launch is bracketed by a pair of
- * HIP events on its stream (between the two graph launches when graphs are
- * used). Off by default. Turning it on or off discards unread timings. */
+/* Kernel timing: when on, each chop launch of daq_process_batch (and of the
+ * single-fill calls) is bracketed by a pair of HIP events on its stream;
+ * where a schedule computes the pedestals in a kernel of its own
+ * (k_prepare), that kernel runs before the first event. Each event pair adds
+ * a few microseconds to the launch. Off by default. Turning it on or off
+ * discards unread timings. */
 int daq_ctx_set_timing(daq_ctx *ctx, int enable);
 /* Waits for the last timed launch and returns its duration in ms; marks
  * every timing read. EINVAL when no unread timed launch exists. */
@@ -560,12 +563,30 @@ void daq_server_destroy(daq_server *srv);
  * The device's plain streaming-read rate, the ceiling the chop's summing scan
  * (which reads every raw sample once) is measured against: reads
  * floor(bytes / 16) 16-byte words of d_buf (16-byte aligned) once with
- * non-temporal loads in a grid of `blocks` work-groups of 256 threads, and
- * writes one word per wave (an XOR of what it read) to d_sink, which must
- * hold blocks * 4 words. Asynchronous on `stream`; time it with events.
- * EINVAL for null pointers, bytes < 16, blocks < 1 or a misaligned buffer. */
+ * non-temporal loads (eight in flight per thread) in a grid of `blocks`
+ * work-groups of 256 threads, and writes one word per wave (an XOR of what it
+ * read) to d_sink, which must hold blocks * 4 words. layout 0: grid-stride
+ * (consecutive waves read consecutive 1 KB pieces); layout 1: each
+ * work-group reads one contiguous chunk. Asynchronous on `stream`; time it
+ * with events. EINVAL for null pointers, bytes < 16, blocks < 1, a
+ * misaligned buffer or another layout. */
 int daq_read_stream(const void *d_buf, int64_t bytes, unsigned int *d_sink,
-                    int32_t blocks, void *stream);
+                    int32_t blocks, int32_t layout, void *stream);
+
+/* The rate of the chop scan's own read pattern, with nothing else done:
+ * reads n_fills fills of `channels` rows of n_samples int16 each (row r of
+ * fill f at d_raw + (f * channels + r) * n_samples, 16-byte aligned) in the
+ * split scan's tiles at 512 threads (4,048 owned samples plus a 32-sample
+ * left and 16-sample right halo, every channel row, 6 rows in flight, 16-byte
+ * non-temporal loads; groups of 8 outside a row are skipped), in a persistent
+ * grid of `blocks` work-groups of 512 threads striding over the tiles.
+ * Writes the wrapping sum of the 32-bit words each wave read to d_sink (blocks
+ * * 8 words). Asynchronous on `stream`. EINVAL for null pointers, n_fills or
+ * channels < 1, n_samples < 8 or not a multiple of 8, blocks < 1 or a
+ * misaligned buffer. */
+int daq_read_tiles(const int16_t *d_raw, int32_t n_fills, int32_t channels,
+                   int64_t n_samples, unsigned int *d_sink, int32_t blocks,
+                   void *stream);
 
 #ifdef __cplusplus
 }

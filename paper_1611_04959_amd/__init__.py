@@ -159,7 +159,8 @@ def load_library():
         "daq_compress_batch": ([vp, ctypes.POINTER(daq_z_fill), i32, vp], ctypes.c_int),
         "daq_decompress_batch": ([vp, ctypes.POINTER(daq_z_stream), i32, vp], ctypes.c_int),
         "daq_packed12_stride": ([i64], i64),
-        "daq_read_stream": ([vp, i64, vp, i32, vp], ctypes.c_int),
+        "daq_read_stream": ([vp, i64, vp, i32, i32, vp], ctypes.c_int),
+        "daq_read_tiles": ([vp, i32, i32, i64, vp, i32, vp], ctypes.c_int),
         "daq_ctx_set_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
         "daq_ctx_get_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
         "daq_ctx_set_graphs": ([vp, ctypes.c_int], ctypes.c_int),
@@ -550,11 +551,26 @@ class Context:
         return float(ms.value)
 
 
-def read_stream(buf, sink, blocks: int, stream=None):
+def read_stream(buf, sink, blocks: int, layout: int = 0, stream=None):
     """daq_read_stream: one streaming read of a device tensor (the device's read ceiling)."""
+    if sink.numel() * sink.element_size() < 4 * 4 * int(blocks):
+        raise ValueError("the sink holds one 32-bit word per wave: %d words" % (4 * int(blocks)))
     _check(load_library().daq_read_stream(buf.data_ptr(), int(buf.numel() * buf.element_size()),
-                                          sink.data_ptr(), int(blocks), _stream_handle(stream)),
+                                          sink.data_ptr(), int(blocks), int(layout), _stream_handle(stream)),
            "daq_read_stream")
+
+
+def read_tiles(raw, n_fills: int, channels: int, n_samples: int, sink, blocks: int, stream=None):
+    """daq_read_tiles: the chop scan's read pattern alone over n_fills fills
+    stored back to back in the int16 device tensor `raw`."""
+    import torch
+    if raw.dtype != torch.int16 or raw.numel() < int(n_fills) * int(channels) * int(n_samples):
+        raise ValueError("raw must be int16 holding n_fills x channels x n_samples samples")
+    if sink.numel() * sink.element_size() < 4 * 8 * int(blocks):
+        raise ValueError("the sink holds one 32-bit word per wave: %d words" % (8 * int(blocks)))
+    _check(load_library().daq_read_tiles(raw.data_ptr(), int(n_fills), int(channels), int(n_samples),
+                                         sink.data_ptr(), int(blocks), _stream_handle(stream)),
+           "daq_read_tiles")
 
 
 def version() -> str:

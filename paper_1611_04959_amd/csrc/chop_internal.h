@@ -22,7 +22,7 @@ constexpr int kVariantResident = 1;  // rows kept in registers until written out
 constexpr int kVariantStream = 2;    // rows DMA'd into LDS; two work-groups per CU
 constexpr int kVariantReload18 = 3;  // as kVariantReload, 18 rows in flight per round (6 there)
 constexpr int kVariantReload27 = 4;  // as kVariantReload, 27 rows in flight per round
-constexpr int kVariantSplit = 5;     // scan pass (mask bits, tile totals), prefix, edge and copy passes
+constexpr int kVariantSplit = 5;     // scan pass (mask bits, tile totals), edge and copy passes
 constexpr int kVariantPipe = 6;      // one persistent kernel: scan tiles and copy chunks from shared counters
 constexpr int kVariantLast = 6;
 // Guard bytes around each fill's island-mask bits (read as zero past the ends).
@@ -147,10 +147,10 @@ inline TileShape tile_shape(int32_t pre, int32_t post, int32_t channels, int thr
 
 hipError_t launch_prepare(const KArgs &a, int blocks, hipStream_t s);
 hipError_t launch_chop(const KArgs &a, int threads, int variant, int grid, hipStream_t s);
-// Split variant: the scan pass, then the prefix, edge and copy passes, over
-// the fill group a.part of a.parts.
+// Split variant: the scan pass, then the edge and copy passes, over the fill
+// group a.part of a.parts.
 hipError_t launch_scan(const KArgs &a, int threads, int grid, hipStream_t s);
-hipError_t launch_emit(const KArgs &a, int threads, int grid, int copy_grid, int prefix_blocks, hipStream_t s);
+hipError_t launch_emit(const KArgs &a, int threads, int edge_grid, int copy_grid, hipStream_t s);
 // Work-groups per CU of the copy pass's persistent grid.
 #ifndef DAQ_COPY_WGS_PER_CU
 #define DAQ_COPY_WGS_PER_CU 4

@@ -2578,15 +2578,16 @@ hipError_t launch_scan(const KArgs &a, int threads, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_emit(const KArgs &a, int threads, int grid, int copy_grid, int prefix_blocks, hipStream_t s) {
-    // the copy pass: a persistent grid whose waves stride over the work items
+hipError_t launch_emit(const KArgs &a, int threads, int edge_grid, int copy_grid, hipStream_t s) {
+    // both passes stride over their work (tiles, copy items), so any grid of
+    // at least one work-group covers the launch
+    const int eg = edge_grid < 1 ? 1 : edge_grid;
     const int cg = copy_grid < 1 ? 1 : copy_grid;
-    (void)prefix_blocks;
     if (threads == 256) {
-        hipLaunchKernelGGL((k_edge_pass<256>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_edge_pass<256>), dim3(eg), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_copy_pass<256>), dim3((int)cg), dim3(256), 0, s, a);
     } else if (threads == 512) {
-        hipLaunchKernelGGL((k_edge_pass<512>), dim3(grid), dim3(512), 0, s, a);
+        hipLaunchKernelGGL((k_edge_pass<512>), dim3(eg), dim3(512), 0, s, a);
         hipLaunchKernelGGL((k_copy_pass<512>), dim3((int)cg), dim3(512), 0, s, a);
     } else {
         return hipErrorInvalidValue;

@@ -50,7 +50,6 @@ constexpr int kRing = 4;          // pinned staging slots per stream
 #endif
 constexpr int64_t kStreamLoadBytes = (int64_t)DAQ_STREAM_LOAD_MB << 20;
 constexpr int kPrepareBlocks = 1024;
-constexpr int kPrefixBlocks = 256;
 
 struct GraphKey {
     int threads = 0, wgs = 0, variant = 0, parts = 0;
@@ -341,21 +340,30 @@ int ensure_parts(Scratch *sc, int parts) {
     return DAQ_OK;
 }
 
+// Work-groups of the edge pass: one wave per tile, so no more than the
+// tiles need (tiles < 0: not known, as in a captured graph that may be
+// replayed for any batch its scratch holds), and at most the scan's grid.
+int edge_grid(int grid, int64_t tiles, int threads) {
+    if (tiles < 0) return grid;
+    const int64_t waves = threads / 64;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(grid, (tiles + waves - 1) / waves));
+}
+
 int launch_main(const daq_ctx *ctx, Scratch *sc, const KArgs &a, const daq_schedule &s, int grid,
-                hipStream_t stream) {
+                int64_t tiles, hipStream_t stream) {
     if (s.variant == daqk::kVariantPipe) {
         HIP_TRY(daqk::launch_pipe(a, s.threads, grid, stream));
         return DAQ_OK;
     }
     if (s.variant == daqk::kVariantSplit) {
-        const int pb = std::max(1, std::min(a.hdr ? kPrefixBlocks : a.n_fills, kPrefixBlocks));
         const int parts = (a.table && s.parts > 1) ? std::min(s.parts, daqk::kMaxParts) : 1;
+        const int eg = edge_grid(grid, tiles, s.threads);
         if (parts == 1) {
             KArgs a1 = a;
             a1.part = 0;
             a1.parts = 1;
             HIP_TRY(daqk::launch_scan(a1, s.threads, grid, stream));
-            HIP_TRY(daqk::launch_emit(a1, s.threads, grid, daqk::kCopyWgsPerCu * ctx->n_cu, pb, stream));
+            HIP_TRY(daqk::launch_emit(a1, s.threads, eg, daqk::kCopyWgsPerCu * ctx->n_cu, stream));
             return DAQ_OK;
         }
         // fill group k runs on its own stream; its scan starts when group
@@ -375,7 +383,7 @@ int launch_main(const daq_ctx *ctx, Scratch *sc, const KArgs &a, const daq_sched
             }
             HIP_TRY(daqk::launch_scan(ak, s.threads, grid, sk));
             HIP_TRY(hipEventRecord(sc->ev_scan[k], sk));
-            HIP_TRY(daqk::launch_emit(ak, s.threads, grid, daqk::kCopyWgsPerCu * ctx->n_cu, pb, sk));
+            HIP_TRY(daqk::launch_emit(ak, s.threads, eg, daqk::kCopyWgsPerCu * ctx->n_cu, sk));
             if (k > 0) HIP_TRY(hipEventRecord(sc->ev_join[k], sk));
         }
         for (int k = 1; k < parts; k++) HIP_TRY(hipStreamWaitEvent(stream, sc->ev_join[k], 0));
@@ -410,7 +418,7 @@ int launch_pair(daq_ctx *ctx, Scratch *sc, const KArgs &a, int64_t total_tiles, 
         int rc = timing_begin(ctx, stream, &slot);
         if (rc) return rc;
     }
-    int rc = launch_main(ctx, sc, a, s, chop_grid(ctx, s, total_tiles), stream);
+    int rc = launch_main(ctx, sc, a, s, chop_grid(ctx, s, total_tiles), total_tiles, stream);
     if (rc) return rc;
     if (ctx->timing) return timing_end(ctx, stream, slot);
     return DAQ_OK;
@@ -445,7 +453,7 @@ int capture_graphs(daq_ctx *ctx, Scratch *s, const daq_schedule &sc) {
         if (e != hipSuccess) return hip_fail(e);
     }
     HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
-    const int rc0 = launch_main(ctx, s, a, sc, sc.wgs_per_cu * ctx->n_cu, ctx->capture);
+    const int rc0 = launch_main(ctx, s, a, sc, sc.wgs_per_cu * ctx->n_cu, -1, ctx->capture);
     e2 = hipStreamEndCapture(ctx->capture, &g);
     if (rc0) return rc0;
     if (e2 != hipSuccess) return hip_fail(e2);
@@ -455,7 +463,7 @@ int capture_graphs(daq_ctx *ctx, Scratch *s, const daq_schedule &sc) {
     // prepare (if any) and main pass in one graph: one launch, no gap between the two
     HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
     e = prep ? daqk::launch_prepare(a, kPrepareBlocks, ctx->capture) : hipSuccess;
-    const int rc1 = e == hipSuccess ? launch_main(ctx, s, a, sc, sc.wgs_per_cu * ctx->n_cu, ctx->capture) : DAQ_OK;
+    const int rc1 = e == hipSuccess ? launch_main(ctx, s, a, sc, sc.wgs_per_cu * ctx->n_cu, -1, ctx->capture) : DAQ_OK;
     e2 = hipStreamEndCapture(ctx->capture, &g);
     if (e != hipSuccess) return hip_fail(e);
     if (rc1) return rc1;
@@ -1393,8 +1401,8 @@ int daq_process_batch_noalloc(daq_ctx *ctx, const daq_fill *fills, const daq_fil
     }
     const int grid = chop_grid(ctx, sc, L.total_tiles);
     HIP_TRY(daqk::launch_scan(a, sc.threads, grid, stream));
-    const int pb = kPrefixBlocks;
-    HIP_TRY(daqk::launch_emit(a, sc.threads, grid, daqk::kCopyWgsPerCu * ctx->n_cu, pb, stream));
+    HIP_TRY(daqk::launch_emit(a, sc.threads, edge_grid(grid, L.total_tiles, sc.threads),
+                              daqk::kCopyWgsPerCu * ctx->n_cu, stream));
     return DAQ_OK;
 }
 

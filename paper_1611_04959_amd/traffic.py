@@ -30,11 +30,10 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-#: every source the chop kernels are compiled from: the counts recorded for
-#: one version are not reported for another
-KERNEL_SOURCES = (os.path.join(HERE, "csrc", "chop_kernels.hip"), os.path.join(HERE, "csrc", "chop_internal.h"),
-                  os.path.join(os.path.dirname(HERE), "include", "daq.h"))
-PASS_KERNELS = ("k_prepare", "k_scan_pass", "k_prefix_pass", "k_edge_pass", "k_copy_pass", "k_chop", "k_pipe")
+#: the sources of the chop kernels (the kernels and their shared internal
+#: header): the counts recorded for one version are not reported for another
+KERNEL_SOURCES = (os.path.join(HERE, "csrc", "chop_kernels.hip"), os.path.join(HERE, "csrc", "chop_internal.h"))
+PASS_KERNELS = ("k_prepare", "k_scan_pass", "k_edge_pass", "k_copy_pass", "k_chop", "k_pipe")
 
 
 def kernel_sha() -> str:
@@ -150,25 +149,28 @@ def tail(path, k):
         name = short(r["Kernel_Name"])
         if name is not None:
             seq.append((name, int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
-    last = {}
-    for name, a, b, full in seq:
-        last.setdefault(name, []).append((a, b, full))
-    print("| Kernel | Dispatches | Mean of the last %d (us) |" % k)
+    # launches: a scan (or fused) dispatch opens one; keep the last k
+    opens = [i for i, x in enumerate(seq) if x[0] in ("k_scan_pass", "k_chop", "k_pipe")][-k:]
+    if not opens:
+        print("no launch found")
+        return
+    window = seq[opens[0]:]
+    per = {}
+    for name, a, b, full in window:
+        per.setdefault(name, []).append((a, b, full))
+    print("| Kernel | Dispatches in the last %d launches | Mean (us) |" % len(opens))
     print("|---|---|---|")
-    for name, v in sorted(last.items(), key=lambda kv: kv[1][-1][0]):
-        t = [(b - a) / 1e3 for a, b, _ in v[-k:]]
+    for name, v in sorted(per.items(), key=lambda kv: kv[1][0][0]):
+        t = [(b - a) / 1e3 for a, b, _ in v]
         label = v[-1][2].replace("daqk::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
         print("| `%s` | %d | %.1f |" % (label, len(v), sum(t) / len(t)))
-    # launches: a scan (or fused) dispatch opens one
-    opens = [i for i, x in enumerate(seq) if x[0] in ("k_scan_pass", "k_chop", "k_pipe")]
     spans = []
-    for j, i in enumerate(opens[-k:]):
-        nxt = opens[opens.index(i) + 1] if opens.index(i) + 1 < len(opens) else len(seq)
+    for j, i in enumerate(opens):
+        nxt = opens[j + 1] if j + 1 < len(opens) else len(seq)
         spans.append((seq[nxt - 1][2] - seq[i][1]) / 1e3)
-    if spans:
-        print()
-        print("Mean span of the last %d launches (first kernel start to last kernel end): %.1f us"
-              % (len(spans), sum(spans) / len(spans)))
+    print()
+    print("Mean span of the last %d launches (first kernel start to last kernel end): %.1f us"
+          % (len(spans), sum(spans) / len(spans)))
 
 
 if __name__ == "__main__":
