@@ -133,13 +133,19 @@ def ceiling(daq):
     return out
 
 
-def batch_bench(daq, synth, specs, what, steps=20, warmup=3):
+# first fills of each timed configuration (host copies, their specs), for the
+# oracle's single-core rate per configuration
+ORACLE_SAMPLES = {}
+
+
+def batch_bench(daq, synth, specs, what, steps=20, warmup=3, name=None):
     """One batched launch over `specs` (autotuned on that batch): raw GB/s,
     the chop pass's HIP-event time, and parity of the first fill."""
     import numpy as np
     import torch
     log("batch %s: rendering %d fills" % (what.split(":")[0], len(specs)))
     xs = synth.render_many(specs)
+    ORACLE_SAMPLES[name or what] = (xs[:2], specs[:2])
     xd = synth.to_device(xs)
     fills = [daq.Fill(d, sp.n_samples, threshold=sp.threshold, pre=sp.pre, post=sp.post,
                       ped_samples=sp.ped_samples) for d, sp in zip(xd, specs)]
@@ -204,6 +210,7 @@ def plain_c0_bench(daq, synth, ctx, rounds=10):
     import torch
     specs = [synth.config_c0(i)[0] for i in range(8)]
     xs = synth.render_many(specs)
+    ORACLE_SAMPLES["c0"] = (xs[:2], specs[:2])
     xd = synth.to_device(xs)
     fills = [daq.Fill(d, sp.n_samples, threshold=sp.threshold, pre=sp.pre, post=sp.post,
                       ped_samples=sp.ped_samples) for d, sp in zip(xd, specs)]
@@ -602,6 +609,7 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
     specs = [synth.config_c3_fill(s, 0) for s in range(n_streams_in)]
     log("serving: rendering %d stream fills" % len(specs))
     xs = synth.render_many(specs)
+    ORACLE_SAMPLES["c3"] = (xs[:2], specs[:2])
     # a pool of distinct fills in HBM, far larger than what is in flight, so
     # that no fill is read while its previous copy may still be cached: each
     # rendered fill and seven copies rotated along time
@@ -974,9 +982,11 @@ def main():
     # ---- the other batch shapes: uneven batch, whole-detector stress -----------------
     others = {}
     if not args.no_uneven:
-        others["uneven"] = batch_bench(daq, synth, synth.config_c2(), UNEVEN, steps=max(10, args.steps // 2))
+        others["uneven"] = batch_bench(daq, synth, synth.config_c2(), UNEVEN, steps=max(10, args.steps // 2),
+                                      name="c2")
     if not args.no_stress:
-        others["stress"] = batch_bench(daq, synth, synth.config_c4(), STRESS, steps=max(5, args.steps // 10))
+        others["stress"] = batch_bench(daq, synth, synth.config_c4(), STRESS, steps=max(5, args.steps // 10),
+                                      name="c4")
 
     # ---- serving loop: Poisson arrivals with bursts, HBM-budget admission -------------
     serving = None
@@ -1034,6 +1044,19 @@ def main():
                              "repeated for %.1f s (%.2f GB raw)" % (len(specs), threads, tc1 - tc0, done / 1e9),
                    "cpu_model": model, "nproc": os.cpu_count(), "threads": threads,
                    "single_core_gbs": round(single, 3)}
+            # the single-core rate on the first fills of every other timed configuration
+            per = {}
+            for name, (sx, ss) in ORACLE_SAMPLES.items():
+                done_c, k = 0, 0
+                t0c = time.perf_counter()
+                while time.perf_counter() - t0c < 1.0 or k < len(sx):
+                    sp = ss[k % len(ss)]
+                    oracle.chop(sx[k % len(sx)], n_samples=sp.n_samples, ped_samples=sp.ped_samples,
+                                threshold=sp.threshold, pre=sp.pre, post=sp.post)
+                    done_c += sp.raw_bytes
+                    k += 1
+                per[name] = round(done_c / (time.perf_counter() - t0c) / 1e9, 3)
+            cpu["single_core_gbs_by_config"] = per
         except ImportError:
             cpu = None
 

@@ -128,10 +128,10 @@ typedef struct daq_fill_out {
 #define DAQ_VARIANT_RELOAD18 3 /* as RELOAD with 18 rows in flight (6 there) */
 #define DAQ_VARIANT_RELOAD27 4 /* as RELOAD with 27 rows in flight          */
 #define DAQ_VARIANT_SPLIT 5    /* a streaming scan that writes island-mask
-                                  bits and tile totals, a prefix pass, an
-                                  edge pass (records, run table) and a copy
-                                  pass that copies only the island samples
-                                  (threads = 256 or 512)                      */
+                                  bits and tile totals, an edge pass
+                                  (prefixes, records, run table, counts) and
+                                  a copy pass that copies only the island
+                                  samples (threads = 256 or 512)             */
 #define DAQ_VARIANT_PIPE 6     /* one persistent kernel: work-groups take scan
                                   tiles (each finds its islands and prefix at
                                   once) and copy chunks of fills whose tiles

@@ -5,10 +5,13 @@
 // array and packed island samples, all in integers.
 //
 // k_prepare  per fill: pedestals (Table 2 pedestal row) and the effective
-//            threshold thr + sum(ped); clears the look-back words and counts.
+//            threshold thr + sum(ped); clears the look-back words and counts
+//            (every schedule but the split one, which sums the pedestals in
+//            its scan).
 // k_scan_pass, k_edge_pass, k_copy_pass
-//            the split schedule (the default): a streaming scan that writes
-//            one island-mask bit per sample and tile totals; an edge pass
+//            the split schedule (the default): a streaming scan that computes
+//            its fill's pedestals and writes one island-mask bit per sample
+//            and tile totals; an edge pass
 //            (one wave per tile: its prefix from the totals of the fill's
 //            earlier tiles, the island records, a run table, the counts);
 //            and a copy of the island samples in equal chunks of packed
@@ -1458,14 +1461,15 @@ __global__ void __launch_bounds__(NT) k_chop(KArgs a) {
     }
 }
 
-// ---- variant 5: scan pass, prefix pass, edge pass, copy pass ------------------------
+// ---- variant 5: scan pass, edge pass, copy pass -------------------------------------
 //
 // The scan pass streams the raw rows once and keeps nothing: per tile it
 // writes the island-mask bits of the samples it owns and the tile's totals.
-// A prefix pass turns the totals into each tile's exclusive prefix (and the
-// fill's counts); the edge pass writes the island records and a run table;
-// the copy pass copies only the island samples. No tile waits for another,
-// so the streaming pass keeps as many loads in flight as the CU holds.
+// The edge pass sums the totals of each tile's predecessors into its
+// exclusive prefix and writes the island records, a run table and the
+// fill's counts; the copy pass copies only the island samples. No tile
+// waits for another, so the streaming pass keeps as many loads in flight as
+// the CU holds.
 
 // Fills [lo, hi) and their tiles [tile_lo, tile_hi) of the launch's part of
 // the batch (the whole batch when parts <= 1).

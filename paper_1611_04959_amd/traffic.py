@@ -26,6 +26,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 from collections import defaultdict
 
@@ -36,11 +37,22 @@ KERNEL_SOURCES = (os.path.join(HERE, "csrc", "chop_kernels.hip"), os.path.join(H
 PASS_KERNELS = ("k_prepare", "k_scan_pass", "k_edge_pass", "k_copy_pass", "k_chop", "k_pipe")
 
 
+def _code_only(text: str) -> str:
+    """The source without comments and with runs of white space collapsed:
+    what the compiler sees, so that a comment edit keeps the counts valid.
+    (String literals in these sources hold no comment markers.)"""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_sha() -> str:
+    """Hash of the code (comments and spacing aside) of every source the chop
+    kernels are built from."""
     h = hashlib.sha256()
     for path in KERNEL_SOURCES:
         h.update(os.path.basename(path).encode() + b"\0")
-        h.update(open(path, "rb").read())
+        h.update(_code_only(open(path, encoding="utf-8").read()).encode())
     return h.hexdigest()[:16]
 
 

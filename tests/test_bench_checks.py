@@ -82,3 +82,18 @@ def test_compress_and_fig2_lines(bench, fill):
     assert not bench.oracle_check(oracle, "fig2", (x, x0, sp, thrs, [found[0] + 1, found[1]], truth))
     with pytest.raises(ValueError):
         bench.oracle_check(oracle, "unknown", None)
+
+
+def test_traffic_hash_follows_code_not_comments(tmp_path, monkeypatch):
+    """The traffic counts stay attached to the kernel code they were taken
+    for: a comment or spacing edit keeps the hash, any code edit changes it
+    (the bench then reports the traffic as unknown)."""
+    from paper_1611_04959_amd import traffic
+    src = tmp_path / "k.hip"
+    src.write_text("// scan\nint f(int x) {\n  return x + 1;  /* one */\n}\n")
+    monkeypatch.setattr(traffic, "KERNEL_SOURCES", [str(src)])
+    h0 = traffic.kernel_sha()
+    src.write_text("// the scan pass\nint f(int x) {   return x + 1; /* one,\n two */ }\n")
+    assert traffic.kernel_sha() == h0
+    src.write_text("// scan\nint f(int x) {\n  return x + 2;  /* one */\n}\n")
+    assert traffic.kernel_sha() != h0
