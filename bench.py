@@ -17,8 +17,9 @@ chopped fills on the same data; and the CPU oracle's throughput on a bounded
 sample, after the oracle has checked the first fill of every line.
 """
 import argparse
-import dataclasses
+import collections
 import concurrent.futures as cf
+import dataclasses
 import json
 import os
 import sys
@@ -625,7 +626,7 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
     def run(times, host=None, dur=5.0, depth=96, packed=False):
         """Open loop: offers fills at `times` (s). Closed loop (times None):
         keeps `depth` fills submitted and unfinished for `dur` seconds."""
-        pending = []          # (arrival_ns, stream) not yet admitted
+        pending = collections.deque()  # (arrival_ns, stream) not yet admitted
         arr_ns = {}
         kept = None
         st0 = srv.stats()
@@ -654,7 +655,7 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
                 if t is None:
                     break
                 arr_ns[t] = a_ns
-                pending.pop(0)
+                pending.popleft()
             for c in srv.poll(256, 200):
                 assert c.error == 0 and c.status == 0
                 lat.append((c.t_ready_ns - arr_ns.pop(c.ticket)) * 1e-6)
@@ -690,11 +691,27 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
 
     rate = 24 * 12 / 1.4
     rng = np.random.default_rng(3)
-    times = arrivals(rate, seconds, rng)
-    log("serving: %d arrivals over %.0f s (mean %.1f fills/s, 5x bursts)" % (len(times), seconds, rate))
+    # long enough for p50 / p99 over at least 10,000 fills
+    nominal_s = max(seconds, 10_000 / rate * 1.03)
+    times = arrivals(rate, nominal_s, rng)
+    log("serving: %d arrivals over %.0f s (mean %.1f fills/s, 5x bursts)" % (len(times), nominal_s, rate))
     nominal = run(times)
+    # the other reading of the rate: 12 fills per second on every stream
+    rate12 = 24 * 12.0
+    s12 = max(seconds, 10_000 / rate12 * 1.03)
+    log("serving: 12 Hz per stream, %.0f s" % s12)
+    nominal_12hz = run(arrivals(rate12, s12, rng))
+    nominal_12hz["offered_fills_per_s"] = rate12  # in place: the parity check fills this dict later
     log("serving: saturation (96 fills kept in flight)")
     sat = run(None, depth=96)
+    # open loop at multiples of the nominal rate, until the queue grows
+    sweep = []
+    for k in (50, 100, 200, 300, 400):
+        log("serving: open loop at %dx the nominal rate" % k)
+        r = run(arrivals(rate * k, 2.0, rng))
+        r["offered_fills_per_s"] = round(rate * k, 1)
+        r["offered_gbs"] = round(rate * k * specs[0].raw_bytes / 1e9, 1)
+        sweep.append(r)
     ingest = None
     try:
         host = [torch.from_numpy(x).pin_memory() for x in xs[:8]]
@@ -727,7 +744,8 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
                         "(80 ms, 10 % duty)", "offered_fills_per_s": round(rate, 1),
             "budget_gb": budget_gb, "n_streams": n_streams, "max_batch": max_batch,
             "seeds": [sp.seed for sp in specs],
-            "nominal": nominal, "saturation": sat, "ingest_pcie": ingest}
+            "nominal": nominal, "nominal_12hz": nominal_12hz,
+            "saturation": sat, "open_loop": sweep, "ingest_pcie": ingest}
 
 
 def main():
