@@ -113,7 +113,29 @@ def ceiling(daq):
             best_t, out["tiles_blocks_per_cu"] = us, per_cu
     out["scan_pattern_us_16fills"] = round(best_t, 1)
     out["scan_pattern_gbs"] = round(2 * nf * C * N / (best_t * 1e-6) / 1e9, 1)
-    del raw
+    # a single pass that writes the islands from the scan, modelled: the same
+    # read, then a fixed 1-in-7 group pattern read again (mode 1) and also
+    # written packed (mode 2), at the best grid of the plain read
+    tiles = (N + 4047) // 4048
+    outw = torch.empty(nf * tiles * C * 512 * 8, dtype=torch.int16, device="cuda")
+    blocks = out["tiles_blocks_per_cu"] * cus
+    sink = torch.empty(blocks * 8, dtype=torch.int32, device="cuda")
+    for mode, key in ((1, "scan_reread_us_16fills"), (2, "scan_reread_write_us_16fills")):
+        for _ in range(3):
+            daq.read_tiles(raw, nf, C, N, sink, blocks, mode, outw)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(10):
+            daq.read_tiles(raw, nf, C, N, sink, blocks, mode, outw)
+        b.record()
+        torch.cuda.synchronize()
+        out[key] = round(a.elapsed_time(b) * 1e3 / 10, 1)
+    pat = 0
+    for lt in range(tiles):
+        g0 = (lt * 4048 - 32) // 8
+        pat += sum(1 for g in range(max(g0, 0), min(g0 + 512, N // 8)) if g % 70 < 11)
+    out["reread_mb_16fills"] = round(nf * C * pat * 16 / 1e6, 1)
+    del raw, outw
     src = torch.ones(n // 2, dtype=torch.int16, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -129,7 +151,8 @@ def ceiling(daq):
     torch.cuda.empty_cache()
     out["what"] = ("read_gbs: one streaming read of 2 GiB with 16-byte non-temporal loads (daq_read_stream); "
                    "scan_pattern_gbs: the 16 bench-shaped fills read in the chop scan's tiles and nothing else "
-                   "(daq_read_tiles), raw bytes over time; "
+                   "(daq_read_tiles), raw bytes over time; scan_reread(_write)_us: the same read, then 1 in 7 "
+                   "of each tile's groups read again (and written packed): a model of a single pass; "
                    "copy_gbs: torch device copy of 1 GiB, read + write bytes")
     return out
 

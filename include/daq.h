@@ -581,12 +581,20 @@ int daq_read_stream(const void *d_buf, int64_t bytes, unsigned int *d_sink,
  * non-temporal loads; groups of 8 outside a row are skipped), in a persistent
  * grid of `blocks` work-groups of 512 threads striding over the tiles.
  * Writes the wrapping sum of the 32-bit words each wave read to d_sink (blocks
- * * 8 words). Asynchronous on `stream`. EINVAL for null pointers, n_fills or
- * channels < 1, n_samples < 8 or not a multiple of 8, blocks < 1 or a
- * misaligned buffer. */
+ * * 8 words). mode 0: that read alone. Modes 1 and 2 model a single pass
+ * that writes the islands from the scan: after each tile, the threads whose
+ * 8-sample group (sample / 8 of the row) is below 11 modulo 70 read their
+ * group of every row again (6 rows in flight, added to the sums); mode 2
+ * also stores each of those 16-byte words to d_out at word
+ * (t * channels + r) * 512 + k, t the tile's index in the launch (fill by
+ * fill) and k the thread's rank among the tile's pattern threads (d_out:
+ * n_fills * ceil(n_samples / 4048) * channels * 512 words of 16 bytes,
+ * 16-byte aligned; ignored by modes 0 and 1). Asynchronous on `stream`.
+ * EINVAL for null pointers, n_fills or channels < 1, n_samples < 8 or not a
+ * multiple of 8, blocks < 1, another mode or a misaligned buffer. */
 int daq_read_tiles(const int16_t *d_raw, int32_t n_fills, int32_t channels,
                    int64_t n_samples, unsigned int *d_sink, int32_t blocks,
-                   void *stream);
+                   int32_t mode, void *d_out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -160,7 +160,7 @@ def load_library():
         "daq_decompress_batch": ([vp, ctypes.POINTER(daq_z_stream), i32, vp], ctypes.c_int),
         "daq_packed12_stride": ([i64], i64),
         "daq_read_stream": ([vp, i64, vp, i32, i32, vp], ctypes.c_int),
-        "daq_read_tiles": ([vp, i32, i32, i64, vp, i32, vp], ctypes.c_int),
+        "daq_read_tiles": ([vp, i32, i32, i64, vp, i32, i32, vp, vp], ctypes.c_int),
         "daq_ctx_set_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
         "daq_ctx_get_schedule": ([vp, ctypes.POINTER(daq_schedule)], ctypes.c_int),
         "daq_ctx_set_graphs": ([vp, ctypes.c_int], ctypes.c_int),
@@ -560,16 +560,27 @@ def read_stream(buf, sink, blocks: int, layout: int = 0, stream=None):
            "daq_read_stream")
 
 
-def read_tiles(raw, n_fills: int, channels: int, n_samples: int, sink, blocks: int, stream=None):
-    """daq_read_tiles: the chop scan's read pattern alone over n_fills fills
-    stored back to back in the int16 device tensor `raw`."""
+def read_tiles(raw, n_fills: int, channels: int, n_samples: int, sink, blocks: int, mode: int = 0, out=None,
+               stream=None):
+    """daq_read_tiles: the chop scan's read pattern over n_fills fills stored
+    back to back in the int16 device tensor `raw` (mode 0), plus the re-read
+    (mode 1) and the re-read and packed write (mode 2, into `out`) of a fixed
+    island pattern."""
     import torch
     if raw.dtype != torch.int16 or raw.numel() < int(n_fills) * int(channels) * int(n_samples):
         raise ValueError("raw must be int16 holding n_fills x channels x n_samples samples")
     if sink.numel() * sink.element_size() < 4 * 8 * int(blocks):
         raise ValueError("the sink holds one 32-bit word per wave: %d words" % (8 * int(blocks)))
+    out_ptr = None
+    if int(mode) == 2:
+        tiles = (int(n_samples) + 4047) // 4048
+        need = int(n_fills) * tiles * int(channels) * 512 * 16
+        if out is None or out.numel() * out.element_size() < need:
+            raise ValueError("mode 2 writes %d bytes to out" % need)
+        out_ptr = out.data_ptr()
     _check(load_library().daq_read_tiles(raw.data_ptr(), int(n_fills), int(channels), int(n_samples),
-                                         sink.data_ptr(), int(blocks), _stream_handle(stream)),
+                                         sink.data_ptr(), int(blocks), int(mode), out_ptr,
+                                         _stream_handle(stream)),
            "daq_read_tiles")
 
 

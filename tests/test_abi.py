@@ -120,7 +120,7 @@ def test_server_calls_reject_null_handles_without_touching_a_gpu():
     assert lib.daq_submit_fill_at(None, ctypes.byref(f), 0, 0, 0, ctypes.byref(t)) == daq.DAQ_EINVAL
     assert lib.daq_server_set_limits(None, 10, 10) == daq.DAQ_EINVAL
     assert lib.daq_read_stream(None, 1 << 20, None, 4, 0, None) == daq.DAQ_EINVAL
-    assert lib.daq_read_tiles(None, 1, 54, 560_000, None, 4, None) == daq.DAQ_EINVAL
+    assert lib.daq_read_tiles(None, 1, 54, 560_000, None, 4, 0, None, None) == daq.DAQ_EINVAL
     assert lib.daq_ctx_get_graphs(None, None) == daq.DAQ_EINVAL
     buf = (daq.daq_completion * 4)()
     assert lib.daq_poll(None, buf, 4, 0) == daq.DAQ_EINVAL
