@@ -1758,23 +1758,36 @@ __device__ __forceinline__ void edge_wave_tile(const KArgs &a, const FillDev &fd
     const uint8_t *mb = fd.mbits + (t0 >> 3);
     const int b0 = lane * 8;
     const int nb = own - b0 < 0 ? 0 : (own - b0 < 8 ? own - b0 : 8);  // this lane's bytes
+    // bytes b0 - 2 .. b0 + 13 in one 16-byte load (2-byte aligned: mbits is
+    // 16-byte aligned and a tile owns an even number of bytes). It stays
+    // inside the fill's mask: byte -2 and bytes up to 12 past the last tile's
+    // owned bytes fall in the 16 guard bytes on either side. Byte b0 - 1 is
+    // zero before the fill's first sample, byte b0 + nb after its last.
+    u32x4 w = u32x4{0, 0, 0, 0};
+    if (nb > 0) __builtin_memcpy(&w, (const DAQ_GLOBAL int16_t *)(mb + b0 - 2), 16);
+    // the tile's exclusive prefix: the totals of the fill's earlier tiles
+    // (written by the scan pass), summed by the wave; these loads are issued
+    // with the mask load above, so the two wait together
+    uint64_t pref = 0;
+#pragma unroll 4
+    for (int64_t j = lane; j < lt; j += 64) pref += *gbl(a.tile_state + fd.tile_base + j);
+    pref = wave_sum_u64(pref);
     uint64_t m = 0;
     uint32_t prv = 0, nxt = 0;
     if (nb > 0) {
-        for (int k = 0; k < nb; k++) m |= (uint64_t)*gbl(mb + b0 + k) << (8 * k);
-        prv = (*gbl(mb + b0 - 1) >> 7) & 1u;   // a zero guard byte before the fill
-        nxt = *gbl(mb + b0 + nb) & 1u;         // a zero guard byte after the fill
+        const uint64_t lo = ((uint64_t)w.y << 32) | w.x;   // bytes -2 .. 5
+        const uint64_t hi = ((uint64_t)w.w << 32) | w.z;   // bytes 6 .. 13
+        m = (lo >> 16) | (hi << 48);                       // bytes 0 .. 7
+        if (nb < 8) m &= (1ull << (8 * nb)) - 1ull;
+        prv = (uint32_t)(lo >> 15) & 1u;                   // top bit of byte -1
+        const int nx = nb + 2;                             // byte b0 + nb, 2 .. 10 of the load
+        nxt = (uint32_t)((nx < 8 ? (lo >> (8 * nx)) : (hi >> (8 * (nx - 8)))) & 1u);
     }
     const uint64_t rise = m & ~((m << 1) | (uint64_t)prv);
     const uint64_t fall = nb > 0 ? (m & ~((m >> 1) | ((uint64_t)nxt << (8 * nb - 1)))) : 0ull;
     const uint32_t cm = (uint32_t)__popcll(m), ci = (uint32_t)__popcll(rise);
     const uint32_t mine = (cm << 16) | ci;
     const uint32_t excl = wave_incl_scan_u32(mine, lane) - mine;
-    // the tile's exclusive prefix: the totals of the fill's earlier tiles
-    // (written by the scan pass, read from L2), summed by the wave
-    uint64_t pref = 0;
-    for (int64_t j = lane; j < lt; j += 64) pref += *gbl(a.tile_state + fd.tile_base + j);
-    pref = wave_sum_u64(pref);
     if (lt == fd.n_tiles - 1 && lane == 0 && fd.counts != nullptr) {
         // the fill's last tile writes the counts
         const uint64_t all = pref + *gbl(a.tile_state + tile);
@@ -2059,6 +2072,13 @@ __device__ __forceinline__ void copy_segment(const FillDev &fd, int64_t q0, int 
 
 constexpr int kCopyFills = kLdsFills;  // fills per window of the item prefix
 
+// Two consecutive int32 words (4-byte aligned) in one 8-byte load.
+__device__ __forceinline__ uint64_t load8_pair(const int32_t *p) {
+    uint64_t v;
+    __builtin_memcpy(&v, (const DAQ_GLOBAL int32_t *)p, 8);
+    return v;
+}
+
 template <int NT>
 __global__ void __launch_bounds__(NT) k_copy_pass(KArgs a) {
     constexpr int NW = NT / 64;
@@ -2130,10 +2150,12 @@ __global__ void __launch_bounds__(NT) k_copy_pass(KArgs a) {
             const int64_t L = tl < fd.out_stride ? tl : fd.out_stride;
             const int64_t q0 = k * kCopyChunk;
             const int m = (int)(L - q0 < kCopyChunk ? L - q0 : kCopyChunk);
-            // both chunk-map words issued together (entry k + 1 exists: the map has two spare words)
-            const int e0 = *gbl(fd.cmap + k), e1 = *gbl(fd.cmap + k + 1);
-            const int i0 = __builtin_amdgcn_readfirstlane(e0);
-            const int i1 = q0 + kCopyChunk < tl ? __builtin_amdgcn_readfirstlane(e1) : (int)n_isl - 1;
+            // both chunk-map words in one 8-byte load (entry k + 1 exists: the
+            // map has two spare words; 4-byte alignment is enough for it)
+            const uint64_t e = load8_pair(fd.cmap + k);
+            const int i0 = __builtin_amdgcn_readfirstlane((int)(uint32_t)e);
+            const int i1 = q0 + kCopyChunk < tl ? __builtin_amdgcn_readfirstlane((int)(uint32_t)(e >> 32))
+                                                : (int)n_isl - 1;
             int nrun = i1 - i0 + 1;  // at most kCopyChunk + 1
             nrun = nrun < 1 ? 1 : (nrun > kSegRuns - 2 ? kSegRuns - 2 : nrun);
             int32_t *st = s_st[wid];
