@@ -617,7 +617,7 @@ def ingest12_bench(daq, ctx, xs, specs, steps):
             "h2d_pinned": rates, "exact": exact}
 
 
-def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch=16):
+def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch=16, saturation_only=False):
     """Serving loop on 24 calorimeter streams of plain-workload fills.
 
     Fills are pre-staged in HBM (one per stream, standing in for a NIC/DMA
@@ -714,6 +714,12 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
 
     rate = 24 * 12 / 1.4
     rng = np.random.default_rng(3)
+    if saturation_only:  # the saturation line alone, for `seconds` (profiling)
+        sat = run(None, dur=seconds, depth=96)
+        srv.close()
+        del arena
+        torch.cuda.empty_cache()
+        return {"workload": "serving loop at saturation (96 fills in flight), %.1f s" % seconds, "saturation": sat}
     # long enough for p50 / p99 over at least 10,000 fills
     nominal_s = max(seconds, 10_000 / rate * 1.03)
     times = arrivals(rate, nominal_s, rng)
@@ -792,6 +798,8 @@ def main():
     ap.add_argument("--no-tq", action="store_true", help="skip the fused T-method + Q-method line")
     ap.add_argument("--no-stress", action="store_true",
                     help="skip the whole-detector stress batch (96 calorimeter fills, 5.8 GB)")
+    ap.add_argument("--only-serving-saturation", action="store_true",
+                    help="run only the serving loop at saturation for --serve-seconds (for profiling)")
     ap.add_argument("--only-batch", choices=["uneven", "stress"], default=None,
                     help="time only that batch shape and print its line (for profiling)")
     args = ap.parse_args()
@@ -811,6 +819,12 @@ def main():
     if args.only_batch:
         what = {"uneven": (synth.config_c2(), UNEVEN), "stress": (synth.config_c4(), STRESS)}[args.only_batch]
         print(json.dumps(batch_bench(daq, synth, what[0], what[1], steps=args.steps, warmup=args.warmup)), flush=True)
+        return
+    if args.only_serving_saturation:
+        ctx = daq.Context(0)
+        res = serve_bench(daq, synth, ctx, args.serve_seconds, saturation_only=True)
+        ctx.close()
+        print(json.dumps(res), flush=True)
         return
 
     specs = synth.config_c1(args.fills)

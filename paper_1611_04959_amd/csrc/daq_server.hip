@@ -34,6 +34,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include "arena.h"
 #include "daq.h"
 
@@ -222,10 +223,15 @@ void worker_loop(daq_server *srv, Worker *w) {
             srv->stats.batches++;
         }
         const int n = (int)batch.size();
+        // profiler ranges (roctx; no cost without a profiler attached): the
+        // batch, and inside it the host-fed copies, the launch, the wait and
+        // the publication of the completions
+        roctxRangePushA("daq_server batch");
         fills.resize((size_t)n);
         outs.resize((size_t)n);
         int rc = DAQ_OK;
         hipError_t he = hipSuccess;
+        roctxRangePushA("daq_server ingest");
         for (int i = 0; i < n; i++) {
             Job *j = batch[(size_t)i];
             fills[(size_t)i] = j->fill;
@@ -245,10 +251,14 @@ void worker_loop(daq_server *srv, Worker *w) {
                     he = hipErrorUnknown;
             }
         }
+        roctxRangePop();
         const int64_t t_launch = now_ns();
         bool timed_out = false;
+        roctxRangePushA("daq_server launch");
         if (he == hipSuccess) rc = daq_process_batch(w->ctx, fills.data(), outs.data(), n, w->stream);
         else rc = DAQ_EHIP;
+        roctxRangePop();
+        roctxRangePushA("daq_server wait");
         if (rc == DAQ_OK) {
             CountPtrs cp{};
             for (int i = 0; i < n; i++) cp.p[i] = outs[(size_t)i].counts;
@@ -270,7 +280,9 @@ void worker_loop(daq_server *srv, Worker *w) {
             // the slots can be handed back
             (void)hipStreamSynchronize(w->stream);
         }
+        roctxRangePop();
         const int64_t t_ready = now_ns();
+        roctxRangePushA("daq_server publish");
         std::lock_guard<std::mutex> lk(srv->mu);
         for (int i = 0; i < n; i++) {
             Job *j = batch[(size_t)i];
@@ -297,6 +309,8 @@ void worker_loop(daq_server *srv, Worker *w) {
         srv->stats.completed += (uint64_t)n;
         if (timed_out) srv->stats.timed_out += (uint64_t)n;
         srv->cv_done.notify_all();
+        roctxRangePop();  // publish
+        roctxRangePop();  // batch
     }
 }
 
@@ -383,7 +397,10 @@ int daq_submit_fill_at(daq_server *srv, const daq_fill *fill, int32_t flags, uin
     const int64_t off = srv->arena.alloc(L.bytes);
     if (off < 0) {
         srv->stats.rejected++;
-        if (srv->dead_since < 0) srv->dead_since = now;
+        if (srv->dead_since < 0) {
+            srv->dead_since = now;
+            roctxMarkA("daq_server deadtime begins");  // the budget refuses fills from here on
+        }
         delete j;
         return DAQ_EAGAIN;
     }
