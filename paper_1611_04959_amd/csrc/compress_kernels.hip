@@ -342,21 +342,43 @@ __global__ void __launch_bounds__(kZWaves * 64) k_unz(ZDecArgs a) {
         wave_lds_order();
         int32_t v[kVec];
         int32_t run = 0;
+        if ((kb0 + kZGroup) * kZBlock <= L) {
+            // every block of the group holds 64 samples (wave-uniform): no
+            // per-code tests, 32-bit positions, one funnel shift per code;
+            // the word index is clamped into the buffer (a damaged offset
+            // reads other words of the group, never outside it)
+            const int64_t rel64 = off - start;
+            const int rel = (int)(rel64 < 0 ? 0 : (rel64 > kZGroupWords ? kZGroupWords : rel64));
+            const uint32_t mask = (1u << w) - 1u;  // w <= 17; 0 for a constant block
+            int pos = rel * 32 + (sub * kVec - 1) * (int)w;
 #pragma unroll
-        for (int e = 0; e < kVec; e++) {
-            const int i = sub * kVec + e;
-            int32_t d = 0;
-            if (i >= 1 && i < n && w > 0) {
-                const int64_t pos = (off - start) * 32 + (int64_t)(i - 1) * w;
-                const int64_t wi = pos >> 5;
-                const uint32_t sh = (uint32_t)(pos & 31);
-                uint64_t pair = 0;
-                if (wi >= 0 && wi < kZGroupWords) pair = (uint64_t)buf[wi] | ((uint64_t)buf[wi + 1] << 32);
-                const uint32_t z = (uint32_t)(pair >> sh) & ((1u << w) - 1u);
-                d = (int32_t)(z >> 1) ^ -(int32_t)(z & 1u);
+            for (int e = 0; e < kVec; e++) {
+                const int p = pos < 0 ? 0 : pos;  // sample 0 of a block has no code
+                const int wi = (p >> 5) < kZGroupWords ? (p >> 5) : kZGroupWords;
+                const uint32_t z = __builtin_amdgcn_alignbit(buf[wi + 1], buf[wi], (uint32_t)p & 31u) & mask;
+                int32_t d = (int32_t)(z >> 1) ^ -(int32_t)(z & 1u);
+                if (e == 0 && sub == 0) d = 0;
+                run += d;
+                v[e] = run;
+                pos += (int)w;
             }
-            run += d;
-            v[e] = run;
+        } else {
+#pragma unroll
+            for (int e = 0; e < kVec; e++) {
+                const int i = sub * kVec + e;
+                int32_t d = 0;
+                if (i >= 1 && i < n && w > 0) {
+                    const int64_t pos = (off - start) * 32 + (int64_t)(i - 1) * w;
+                    const int64_t wi = pos >> 5;
+                    const uint32_t sh = (uint32_t)(pos & 31);
+                    uint64_t pair = 0;
+                    if (wi >= 0 && wi < kZGroupWords) pair = (uint64_t)buf[wi] | ((uint64_t)buf[wi + 1] << 32);
+                    const uint32_t z = (uint32_t)(pair >> sh) & ((1u << w) - 1u);
+                    d = (int32_t)(z >> 1) ^ -(int32_t)(z & 1u);
+                }
+                run += d;
+                v[e] = run;
+            }
         }
         // exclusive prefix of the lane totals over the block's 8 lanes
         int32_t inc = run;
