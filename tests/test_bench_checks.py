@@ -97,3 +97,18 @@ def test_traffic_hash_follows_code_not_comments(tmp_path, monkeypatch):
     assert traffic.kernel_sha() == h0
     src.write_text("// scan\nint f(int x) {\n  return x + 2;  /* one */\n}\n")
     assert traffic.kernel_sha() != h0
+
+
+def test_arrivals_rate_and_bursts(bench):
+    """The serving workload's arrivals: a Poisson process whose long-run mean
+    is the requested rate, 5 times denser inside the 80 ms bursts that take a
+    tenth of the time, and sorted."""
+    rng = np.random.default_rng(11)
+    rate, seconds = 2000.0, 40.0
+    t = np.array(bench.arrivals(rate, seconds, rng))
+    assert np.all(np.diff(t) >= 0) and t[0] >= 0 and t[-1] < seconds
+    assert abs(len(t) / seconds - rate) < 0.03 * rate
+    in_burst = (t % 0.8) < 0.08
+    dense = in_burst.sum() / (0.1 * seconds)
+    sparse = (~in_burst).sum() / (0.9 * seconds)
+    assert 4.5 < dense / sparse < 5.5
