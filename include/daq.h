@@ -202,11 +202,13 @@ int daq_gather_islands(daq_ctx *ctx, const daq_fill *fill,
 int daq_chop_fill(daq_ctx *ctx, const daq_fill *fill, const daq_fill_out *out,
                   void *stream);
 
-/* Many independent fills (uneven N, thresholds, windows) in one persistent
- * launch of the fused kernel, replayed from a captured HIP graph when the
- * context's graphs are on. Results per fill are identical to daq_chop_fill.
- * The two arrays are host arrays of n entries; they are copied before the
- * call returns. n = 0 is a no-op. */
+/* Many independent fills (uneven N, thresholds, windows) in one launch of
+ * the context's schedule (by default the split schedule's three kernels over
+ * every fill, with persistent grids), replayed from a captured HIP graph when
+ * the context's graphs are on and launched plainly otherwise. Results per
+ * fill are identical to daq_chop_fill whatever the schedule. The two arrays
+ * are host arrays of n entries; they are copied before the call returns.
+ * n = 0 is a no-op. */
 int daq_process_batch(daq_ctx *ctx, const daq_fill *fills,
                       const daq_fill_out *outs, int32_t n, void *stream);
 
