@@ -11,7 +11,7 @@ the library's autotuner). Inputs are resident in HBM before timing starts.
 
 Printed (one JSON line): raw ADC GB/s (value) and its fraction of the HBM
 peak, p50/p99 fill latency for the batched and the plain per-fill forms, the
-fused kernel's roofline figures timed live with HIP events over the timed
+chop launch's roofline figures timed live with HIP events over the timed
 region; lines for the Q-method, the 12-bit ingest and the compression of the
 chopped fills on the same data; and the CPU oracle's throughput on a bounded
 sample, after the oracle has checked the first fill of every line.
@@ -841,7 +841,7 @@ def main():
 
     # ---- schedule ---------------------------------------------------------
     if not args.no_tune:
-        log("autotuning the fused kernel schedule")
+        log("autotuning the chop schedule")
         best = ctx.daq_autotune(fills, outs)
         sched = (best.threads, best.wgs_per_cu, best.variant, best.parts)
     else:
@@ -940,7 +940,7 @@ def main():
     main_check = {}
     PENDING.append(("chop", main_check, (xs[0], specs[0], outs[0].host())))
 
-    # ---- roofline of the fused kernel -------------------------------------------
+    # ---- roofline of the chop launch --------------------------------------------
     alg_bytes = sum(2 * C * s.n_samples for s in specs) + sum(2 * C * t for t in tot) \
         + sum(24 * n for n in n_isl) + len(specs) * (24 + 4 * C)
     kmean = launch_ms

@@ -117,7 +117,7 @@ typedef struct daq_fill_out {
     int64_t out_stride;  /* elements per packed row; N never overflows        */
 } daq_fill_out;
 
-/* Launch schedule of the fused kernel (chosen by daq_autotune or set). */
+/* Launch schedule of the chop (chosen by daq_autotune or set). */
 #define DAQ_VARIANT_RELOAD 0   /* rows read into registers, read again for the
                                   write-out                                   */
 #define DAQ_VARIANT_REGISTERS 1 /* 54-channel tiles kept in registers; a call
@@ -196,9 +196,10 @@ int daq_gather_islands(daq_ctx *ctx, const daq_fill *fill,
                        daq_counts *d_counts, int16_t *d_out, int64_t out_stride,
                        void *stream);
 
-/* Both calls in one pass over the fill: the fused kernel finds the islands
- * and writes the packed samples in the same read of the raw data. Same
- * results as daq_find_islands followed by daq_gather_islands. */
+/* Both calls at once, with the context's schedule: by default the split
+ * schedule's scan, edge and copy passes; the fused schedules find the
+ * islands and write the packed samples in the same read of the raw data.
+ * Same results as daq_find_islands followed by daq_gather_islands. */
 int daq_chop_fill(daq_ctx *ctx, const daq_fill *fill, const daq_fill_out *out,
                   void *stream);
 
@@ -373,7 +374,7 @@ typedef struct daq_z_stream {
 int daq_decompress_batch(daq_ctx *ctx, const daq_z_stream *streams, int32_t n,
                          void *stream);
 
-/* Schedule of the fused kernel used by daq_chop_fill / daq_process_batch
+/* Schedule of the chop used by daq_chop_fill / daq_process_batch
  * (a new context holds the split variant, 512 threads, 8 work-groups per
  * CU). EINVAL for values outside the documented sets. */
 int daq_ctx_set_schedule(daq_ctx *ctx, const daq_schedule *s);
