@@ -65,6 +65,42 @@ def build_c_client(verbose: bool = False) -> str:
     return C_CLIENT
 
 
+SAN_DIR = os.path.join(ROOT, "tests", "native", "sanitized")
+SAN_LIB = os.path.join(SAN_DIR, "libdaqisland.so")
+SAN_STRESS_SRC = os.path.join(ROOT, "tests", "native", "server_stress.cpp")
+SAN_STRESS = os.path.join(SAN_DIR, "server_stress")
+# host code only: each sanitizer flag applies to the host compilation (the
+# device code of the library is built as usual)
+HOST_SANITIZERS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                   "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """The library with AddressSanitizer and UndefinedBehaviorSanitizer on its
+    host code, and the serving-loop stress program linked against it (both
+    under tests/native/sanitized, used by tests/test_gpu_server_sanitized.py)."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    os.makedirs(SAN_DIR, exist_ok=True)
+    cmd = [HIPCC] + FLAGS + HOST_SANITIZERS + SOURCES + LIBS + ["-o", SAN_LIB]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc (sanitized) failed:\n" + r.stderr)
+    clang = os.path.join(rocm, "llvm", "bin", "clang++")
+    cmd = [clang, "-O1", "-g", "-std=c++17", "-Wall", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+           "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(rocm, "include"), "-I", os.path.join(ROOT, "include"),
+           SAN_STRESS_SRC, "-L", SAN_DIR, "-ldaqisland", "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+           "-lpthread", "-Wl,-rpath,$ORIGIN", "-Wl,-rpath," + os.path.join(rocm, "lib"), "-o", SAN_STRESS]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("clang++ (sanitized stress) failed:\n" + r.stderr)
+    return SAN_STRESS
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
     print(build_c_client(verbose=True))
+    print(build_sanitized(verbose=True))
