@@ -777,6 +777,26 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
             "saturation": sat, "open_loop": sweep, "ingest_pcie": ingest}
 
 
+def cpu_model():
+    """The host CPU's model name (empty where /proc/cpuinfo does not say)."""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
+def device_info():
+    """Name, architecture, compute units and memory of GPU 0."""
+    import torch
+    props = torch.cuda.get_device_properties(0)
+    return {"name": props.name, "arch": getattr(props, "gcnArchName", ""),
+            "compute_units": props.multi_processor_count, "memory_gib": round(props.total_memory / 2 ** 30, 1),
+            "torch": torch.__version__, "hip": getattr(torch.version, "hip", None)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1085,14 +1105,7 @@ def main():
                 while time.perf_counter() - tc0 < args.cpu_seconds:
                     done += sum(ex.map(one, range(max(threads, len(specs)))))
             tc1 = time.perf_counter()
-            model = ""
-            try:
-                for ln in open("/proc/cpuinfo"):
-                    if ln.startswith("model name"):
-                        model = ln.split(":", 1)[1].strip()
-                        break
-            except OSError:
-                pass
+            model = cpu_model()
             cpu = {"value": round(done / (tc1 - tc0) / 1e9, 3), "unit": "GB/s", "cores": threads,
                    "kind": "oracle",
                    "sample": "the %d bench fills, each chopped whole by one thread, %d threads at a time, "
@@ -1127,6 +1140,8 @@ def main():
                    "schedule": {"threads": sched[0], "wgs_per_cu": sched[1], "variant": sched[2],
                                 "parts": sched[3], "graphs": graphs},
                    "seeds": [s.seed for s in specs]},
+        "device": device_info(),
+        "host": {"cpu_model": cpu_model(), "nproc": os.cpu_count()},
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "batched": {"gbs": round(value, 1), "p50_fill_ms": round(pct(step_ms, 50), 4),
                     "p99_fill_ms": round(pct(step_ms, 99), 4)},

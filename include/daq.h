@@ -168,7 +168,21 @@ int daq_last_hip_error(void);
 int64_t daq_max_islands(int64_t n_samples, int32_t pre, int32_t post);
 
 /* Create a context on HIP device `device` (allocates nothing large; scratch
- * grows on demand). *out receives the handle. */
+ * grows on demand). *out receives the handle.
+ *
+ * Two environment variables, read by the library itself:
+ *   DAQ_SCHEDULE="threads,wgs_per_cu,variant,parts[,graphs]" gives every new
+ *     context that schedule (and, with the fifth field 0 or 1, the graph mode
+ *     of daq_ctx_set_graphs); daq_autotune then returns it without tuning.
+ *     daq_ctx_set_schedule still changes it. A value that does not parse or
+ *     that daq_ctx_set_schedule refuses makes daq_ctx_create fail with
+ *     DAQ_EINVAL and print the reason on stderr.
+ *   DAQ_LOG=0|1|2 (read once per process; unset is 0) prints diagnostic lines
+ *     starting "[daq] " on stderr: 1, failures (failed HIP calls named,
+ *     batches the server's watchdog gave up on or that failed); 2, also
+ *     context creation, every schedule the tuner timed and the one it kept,
+ *     graph captures, scratch growth, server creation and shutdown with its
+ *     counters, and the start of each deadtime period. */
 int daq_ctx_create(daq_ctx **out, int device);
 /* Waits for the context's streams, frees its scratch and graphs. NULL ok. */
 void daq_ctx_destroy(daq_ctx *ctx);
@@ -417,7 +431,9 @@ int daq_ctx_kernel_times(daq_ctx *ctx, float *ms, int32_t max);
  * duration of the call. Synchronises `stream`; the outputs hold the last
  * candidate's (identical) results. When cache_path is not NULL the choice
  * (schedule and graph mode) is looked up there first and stored there after
- * tuning, keyed by device name and batch shape. */
+ * tuning, keyed by device name and batch shape. A context whose schedule
+ * came from DAQ_SCHEDULE (daq_ctx_create) is not tuned: *best receives that
+ * schedule and DAQ_OK is returned. */
 int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs,
                  int32_t n, void *stream, const char *cache_path,
                  daq_schedule *best);

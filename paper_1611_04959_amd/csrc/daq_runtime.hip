@@ -20,6 +20,7 @@
 
 #include "chop_internal.h"
 #include "daq.h"
+#include "daq_log.h"
 
 using daqk::BatchHdr;
 using daqk::FillDev;
@@ -30,15 +31,17 @@ namespace {
 
 thread_local int g_last_hip = 0;
 
-int hip_fail(hipError_t e) {
+// Records a failed HIP call (daq_last_hip_error) and maps it to a status.
+int hip_fail(hipError_t e, const char *what = "a HIP call") {
     g_last_hip = (int)e;
+    daqlog::say(1, "%s failed: %s (%d)", what, hipGetErrorName(e), (int)e);
     return e == hipErrorOutOfMemory ? DAQ_ENOMEM : DAQ_EHIP;
 }
 
-#define HIP_TRY(expr)                                  \
-    do {                                               \
-        hipError_t e_ = (expr);                        \
-        if (e_ != hipSuccess) return hip_fail(e_);     \
+#define HIP_TRY(expr)                                     \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
     } while (0)
 
 constexpr int kRing = 4;          // pinned staging slots per stream
@@ -102,6 +105,7 @@ struct daq_ctx {
     daq_schedule sched{512, 8, daqk::kVariantSplit, 0};
     bool graphs = true;
     bool timing = false;
+    bool pinned = false;  // schedule (and graph mode) fixed by DAQ_SCHEDULE
     // event pairs bracketing fused-kernel launches while timing is on;
     // launches [t_read, t_next) have not been reported yet
     std::vector<hipEvent_t> ev_start, ev_stop;
@@ -133,7 +137,7 @@ int timing_begin(daq_ctx *ctx, hipStream_t stream, size_t *slot) {
         hipError_t e = hipEventCreate(&b);
         if (e != hipSuccess) {
             (void)hipEventDestroy(a);
-            return hip_fail(e);
+            return hip_fail(e, "hipEventCreate");
         }
         ctx->ev_start.push_back(a);
         ctx->ev_stop.push_back(b);
@@ -199,6 +203,8 @@ int ensure_scratch(Scratch *s, int64_t tiles, int32_t fills, int64_t mask_bytes)
         return DAQ_OK;
     HIP_TRY(hipStreamSynchronize(s->stream));
     free_graphs(s);
+    daqlog::say(2, "scratch of stream %p grows for %lld tiles, %d fills, %lld mask bytes", (void *)s->stream,
+                (long long)tiles, fills, (long long)mask_bytes);
     if (tiles > s->tile_cap) {
         int64_t cap = std::max<int64_t>(tiles + tiles / 2, 4096);
         (void)hipFree(s->tile_state);
@@ -446,37 +452,39 @@ int capture_graphs(daq_ctx *ctx, Scratch *s, const daq_schedule &sc) {
         HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
         e = daqk::launch_prepare(a, kPrepareBlocks, ctx->capture);
         e2 = hipStreamEndCapture(ctx->capture, &g);
-        if (e != hipSuccess) return hip_fail(e);
-        if (e2 != hipSuccess) return hip_fail(e2);
+        if (e != hipSuccess) return hip_fail(e, "launch_prepare (capture)");
+        if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
         e = hipGraphInstantiate(&s->g_prep, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return hip_fail(e);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
     }
     HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
     const int rc0 = launch_main(ctx, s, a, sc, sc.wgs_per_cu * ctx->n_cu, -1, ctx->capture);
     e2 = hipStreamEndCapture(ctx->capture, &g);
     if (rc0) return rc0;
-    if (e2 != hipSuccess) return hip_fail(e2);
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
     e = hipGraphInstantiate(&s->g_chop, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return hip_fail(e);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
     // prepare (if any) and main pass in one graph: one launch, no gap between the two
     HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
     e = prep ? daqk::launch_prepare(a, kPrepareBlocks, ctx->capture) : hipSuccess;
     const int rc1 = e == hipSuccess ? launch_main(ctx, s, a, sc, sc.wgs_per_cu * ctx->n_cu, -1, ctx->capture) : DAQ_OK;
     e2 = hipStreamEndCapture(ctx->capture, &g);
-    if (e != hipSuccess) return hip_fail(e);
+    if (e != hipSuccess) return hip_fail(e, "launch_prepare (capture)");
     if (rc1) return rc1;
-    if (e2 != hipSuccess) return hip_fail(e2);
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
     e = hipGraphInstantiate(&s->g_all, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return hip_fail(e);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
     s->key.threads = sc.threads;
     s->key.wgs = sc.wgs_per_cu;
     s->key.variant = sc.variant;
     s->key.parts = sc.parts;
     s->key.table = s->table;
     s->key.state = s->tile_state;
+    daqlog::say(2, "graphs captured for schedule %d/%d/%d/%d on stream %p", sc.threads, sc.wgs_per_cu, sc.variant,
+                sc.parts, (void *)s->stream);
     return DAQ_OK;
 }
 
@@ -826,8 +834,32 @@ int noalloc_init(int device) {
     if (g_noalloc_ptr[device]) return DAQ_OK;
     void *p = nullptr;
     const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
-    if (e != hipSuccess || p == nullptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol);
+    if (e != hipSuccess || p == nullptr)
+        return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
     g_noalloc_ptr[device] = static_cast<uint8_t *>(p);
+    return DAQ_OK;
+}
+
+// DAQ_SCHEDULE="threads,wgs_per_cu,variant,parts[,graphs]" fixes a new
+// context's schedule (and, with the fifth field, whether launches replay
+// captured graphs); daq_autotune then keeps it instead of timing the menu.
+// A value that does not parse, or that daq_ctx_set_schedule would refuse,
+// fails the context's creation and says why on stderr at every log level.
+int schedule_from_env(daq_ctx *c) {
+    const char *env = std::getenv("DAQ_SCHEDULE");
+    if (!env || !*env) return DAQ_OK;
+    daq_schedule s{};
+    int graphs = -1, used = 0;
+    const int got = std::sscanf(env, "%d,%d,%d,%d%n,%d%n", &s.threads, &s.wgs_per_cu, &s.variant, &s.parts, &used,
+                                &graphs, &used);
+    if (got < 4 || env[used] != '\0' || (got == 5 && graphs != 0 && graphs != 1) ||
+        daq_ctx_set_schedule(c, &s) != DAQ_OK) {
+        daqlog::say(0, "DAQ_SCHEDULE=\"%s\" refused: expected threads,wgs_per_cu,variant,parts[,graphs] "
+                       "that daq_ctx_set_schedule accepts, graphs 0 or 1", env);
+        return DAQ_EINVAL;
+    }
+    if (got == 5) c->graphs = graphs == 1;
+    c->pinned = true;
     return DAQ_OK;
 }
 
@@ -947,15 +979,19 @@ int daq_ctx_create(daq_ctx **out, int device) {
     hipError_t e = hipGetDeviceProperties(&prop, device);
     if (e != hipSuccess) {
         delete c;
-        return hip_fail(e);
+        return hip_fail(e, "hipGetDeviceProperties");
     }
     c->n_cu = prop.multiProcessorCount;
     c->name = prop.gcnArchName;
-    const int rc = noalloc_init(device);
+    int rc = noalloc_init(device);
+    if (rc == DAQ_OK) rc = schedule_from_env(c);
     if (rc != DAQ_OK) {
         delete c;
         return rc;
     }
+    daqlog::say(2, "context on device %d: %s, %s, %d compute units, schedule %d/%d/%d/%d%s", device, prop.name,
+                prop.gcnArchName, c->n_cu, c->sched.threads, c->sched.wgs_per_cu, c->sched.variant, c->sched.parts,
+                c->pinned ? " (DAQ_SCHEDULE)" : "");
     *out = c;
     return DAQ_OK;
 }
@@ -1478,6 +1514,12 @@ int daq_ctx_kernel_time(daq_ctx *ctx, float *ms) {
 int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, int32_t n, void *stream,
                  const char *cache_path, daq_schedule *best) {
     if (!ctx || n <= 0 || !fills || !outs) return DAQ_EINVAL;
+    if (ctx->pinned) {
+        daqlog::say(2, "autotune: schedule %d/%d/%d/%d fixed by DAQ_SCHEDULE, not tuned", ctx->sched.threads,
+                    ctx->sched.wgs_per_cu, ctx->sched.variant, ctx->sched.parts);
+        if (best) *best = ctx->sched;
+        return DAQ_OK;
+    }
     hipStream_t st = (hipStream_t)stream;
     const std::string key = shape_key(ctx, fills, n);
     if (cache_path) {
@@ -1493,6 +1535,8 @@ int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, 
                                    &s.parts, &ms, &graphs);
             if (got >= 4 && daq_ctx_set_schedule(ctx, &s) == DAQ_OK) {
                 if (got == 6) ctx->graphs = graphs != 0;
+                daqlog::say(2, "autotune: schedule %d/%d/%d/%d (graphs %d) from %s", s.threads, s.wgs_per_cu,
+                            s.variant, s.parts, ctx->graphs ? 1 : 0, cache_path);
                 if (best) *best = s;
                 return DAQ_OK;
             }
@@ -1542,6 +1586,9 @@ int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, 
             rc = compare_outputs(s, n, st, ref, &same);
             if (rc) break;
             if (!same) {
+                daqlog::say(1, "autotune: schedule %d/%d/%d/%d wrote outputs that differ from %d/%d/%d/%d's",
+                            cand[k].threads, cand[k].wgs_per_cu, cand[k].variant, cand[k].parts, cand[0].threads,
+                            cand[0].wgs_per_cu, cand[0].variant, cand[0].parts);
                 rc = DAQ_EMISMATCH;
                 break;
             }
@@ -1558,6 +1605,8 @@ int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, 
         if (rc) break;
         std::sort(t, t + reps);
         const float med = 0.5f * (t[reps / 2 - 1] + t[reps / 2]);
+        daqlog::say(2, "autotune: schedule %d/%d/%d/%d median %.4f ms", cand[k].threads, cand[k].wgs_per_cu,
+                    cand[k].variant, cand[k].parts, med);
         if (med < best_ms) {
             best_ms = med;
             best_s = cand[k];
@@ -1595,6 +1644,9 @@ int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs, 
     }
     ctx->sched = best_s;
     ctx->graphs = mode_ms[1] <= mode_ms[0];
+    daqlog::say(2, "autotune: kept %d/%d/%d/%d with %s (plain launches %.4f ms, graph replay %.4f ms)",
+                best_s.threads, best_s.wgs_per_cu, best_s.variant, best_s.parts,
+                ctx->graphs ? "graph replay" : "plain launches", mode_ms[0], mode_ms[1]);
     if (best) *best = best_s;
     if (cache_path) {
         std::ofstream o(cache_path, std::ios::app);

@@ -37,6 +37,7 @@
 #include <rocprofiler-sdk-roctx/roctx.h>
 #include "arena.h"
 #include "daq.h"
+#include "daq_log.h"
 
 namespace {
 
@@ -272,10 +273,19 @@ void worker_loop(daq_server *srv, Worker *w) {
                 const int64_t limit = srv->batch_timeout_ns.load(std::memory_order_relaxed);
                 if (limit > 0) he = wait_event(w->done, limit, &timed_out);
                 else he = hipEventSynchronize(w->done);
+                if (timed_out)
+                    daqlog::say(1, "server: a batch of %d fills outlived the %lld ns time-out; its slots stay held "
+                                   "until the device is done with them", n, (long long)limit);
             }
-            if (he != hipSuccess) rc = DAQ_EHIP;
-            else if (timed_out) rc = DAQ_ETIMEDOUT;
+            if (he != hipSuccess) {
+                daqlog::say(1, "server: waiting for a batch of %d fills failed: %s", n, hipGetErrorName(he));
+                rc = DAQ_EHIP;
+            } else if (timed_out) {
+                rc = DAQ_ETIMEDOUT;
+            }
         } else {
+            daqlog::say(1, "server: a batch of %d fills failed to launch: status %d, HIP error %d", n, rc,
+                        (int)he);
             // the copies above may be in flight: wait for the stream before
             // the slots can be handed back
             (void)hipStreamSynchronize(w->stream);
@@ -373,6 +383,8 @@ int daq_server_create(daq_server **out, daq_ctx *ctx, void *d_arena, size_t aren
         return rc;
     }
     for (Worker &w : srv->workers) w.th = std::thread(worker_loop, srv, &w);
+    daqlog::say(2, "server on device %d: %d workers, batches of up to %d fills, arena of %llu bytes", dev, n_streams,
+                max_batch, (unsigned long long)srv->arena.size());
     *out = srv;
     return DAQ_OK;
 }
@@ -400,6 +412,8 @@ int daq_submit_fill_at(daq_server *srv, const daq_fill *fill, int32_t flags, uin
         if (srv->dead_since < 0) {
             srv->dead_since = now;
             roctxMarkA("daq_server deadtime begins");  // the budget refuses fills from here on
+            daqlog::say(2, "server: deadtime begins, %llu of %llu arena bytes in use",
+                        (unsigned long long)srv->arena.in_use(), (unsigned long long)srv->arena.size());
         }
         delete j;
         return DAQ_EAGAIN;
@@ -511,6 +525,12 @@ void daq_server_destroy(daq_server *srv) {
         free_worker(w);
     }
     for (auto &kv : srv->jobs) delete kv.second;
+    const daq_server_stats &t = srv->stats;
+    daqlog::say(2, "server shut down: %llu admitted, %llu refused, %llu completed in %llu batches, %llu late, "
+                   "%llu timed out, %.3f ms of deadtime, arena peak %llu bytes",
+                (unsigned long long)t.submitted, (unsigned long long)t.rejected, (unsigned long long)t.completed,
+                (unsigned long long)t.batches, (unsigned long long)t.late, (unsigned long long)t.timed_out,
+                t.deadtime_ns / 1e6, (unsigned long long)srv->arena.peak());
     delete srv;
 }
 

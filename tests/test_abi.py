@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -191,3 +192,32 @@ def test_fused_call_rejects_bad_arguments_without_touching_a_gpu():
     q = (daq.daq_q_out * 1)(daq.daq_q_out(0x6000, 0x7000, 16, None))
     assert lib.daq_process_batch_q(None, f, o, q, 1, None) == daq.DAQ_EINVAL
     assert lib.daq_qmethod_batch(None, f, q, 1, None) == daq.DAQ_EINVAL
+
+
+def _no_device_child(env_extra):
+    """Runs daq_ctx_create in a child process (the library reads DAQ_LOG once
+    per process) and returns (status, last HIP error, stderr)."""
+    code = ("import ctypes, paper_1611_04959_amd as daq\n"
+            "lib = ctypes.CDLL(daq.LIB_PATH)\n"
+            "h = ctypes.c_void_p()\n"
+            "print(lib.daq_ctx_create(ctypes.byref(h), 0), lib.daq_last_hip_error())\n")
+    env = {k: v for k, v in os.environ.items() if k not in ("DAQ_LOG", "DAQ_SCHEDULE")}
+    env.update(env_extra)
+    env["PYTHONPATH"] = ROOT
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120, env=env)
+    assert r.returncode == 0, r.stderr[-2000:]
+    rc, hip = (int(v) for v in r.stdout.split())
+    return rc, hip, r.stderr
+
+
+def test_failed_hip_call_is_logged_at_level_one():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present: daq_ctx_create succeeds")
+    rc, hip, err = _no_device_child({"DAQ_LOG": "1"})
+    assert rc == daq.DAQ_EHIP and hip != 0
+    lines = [ln for ln in err.splitlines() if ln.startswith("[daq] ")]
+    assert len(lines) == 1 and "hipGetDeviceCount" in lines[0] and "failed" in lines[0], err
+    rc0, _, err0 = _no_device_child({})
+    assert rc0 == daq.DAQ_EHIP
+    assert "[daq]" not in err0
