@@ -777,6 +777,26 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
             "saturation": sat, "open_loop": sweep, "ingest_pcie": ingest}
 
 
+def island_line_bytes(records, row_bases, line=128):
+    """Bytes of the `line`-byte cache lines that hold island samples: records
+    is one (n, 2) array of [start, stop) per fill, row_bases the byte address
+    of each of that fill's int16 channel rows. Islands never overlap but two
+    may end and begin in one line, which is counted once. Any kernel that
+    reads the island samples from the raw rows fetches at least this much."""
+    import numpy as np
+    total = 0
+    for rec, bases in zip(records, row_bases):
+        rec = np.asarray(rec, np.int64).reshape(-1, 2)
+        if rec.shape[0] == 0:
+            continue
+        for b in np.asarray(bases, np.int64):
+            first = (b + 2 * rec[:, 0]) // line
+            last = (b + 2 * rec[:, 1] - 1) // line
+            shared = int(np.count_nonzero(first[1:] == last[:-1]))
+            total += (int((last - first + 1).sum()) - shared) * line
+    return total
+
+
 def cpu_model():
     """The host CPU's model name (empty where /proc/cpuinfo does not say)."""
     try:
@@ -970,6 +990,13 @@ def main():
         tr = json.load(open(TRAFFIC_FILE))
         if tr.get("kernel_sha") == kernel_sha() and tr.get("fills") == len(specs):
             traffic = tr.get("bytes_per_launch")
+    # the fetch floor of reading the island samples back from the raw rows
+    recs = [o.islands[:n].cpu().numpy()[:, :2] for o, n in zip(outs, n_isl)]
+    bases = [[x.data_ptr() + 2 * c * x.stride(0) for c in range(x.shape[0])] for x in xd]
+    line_floor = island_line_bytes(recs, bases)
+    copy_fetch = None
+    if traffic is not None:
+        copy_fetch = round(json.load(open(TRAFFIC_FILE))["kernels"].get("k_copy_pass", {}).get("fetch_bytes", 0))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
@@ -981,7 +1008,13 @@ def main():
                 "kernel_launches_timed": args.steps,
                 "timing": "HIP events on the launch stream at both ends of the timed region",
                 "library_timed_launch_ms_mean": round(float(np.mean(kern_ms)), 4) if kern_ms else None,
-                "algorithmic_bytes_per_launch": alg_bytes}
+                "algorithmic_bytes_per_launch": alg_bytes,
+                "island_line_floor": {"bytes": line_floor, "copied_bytes": sum(2 * C * t for t in tot),
+                                      "copy_pass_fetch_bytes": copy_fetch,
+                                      "what": "bytes of the 128-byte lines holding island samples in the "
+                                              "raw rows (the least a copy from the raw rows fetches), the "
+                                              "island samples themselves, and what the copy pass fetched "
+                                              "by the counter runs"}}
 
     # ---- plain per-fill launches (the form batching must beat) ---------------------
     plain = {}

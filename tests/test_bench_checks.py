@@ -112,3 +112,22 @@ def test_arrivals_rate_and_bursts(bench):
     dense = in_burst.sum() / (0.1 * seconds)
     sparse = (~in_burst).sum() / (0.9 * seconds)
     assert 4.5 < dense / sparse < 5.5
+
+
+def test_island_line_bytes_against_brute_force(bench):
+    rng = np.random.default_rng(3)
+    records, bases, want = [], [], 0
+    for _ in range(5):
+        n = int(rng.integers(0, 12))
+        cuts = np.sort(rng.choice(np.arange(1, 4000), size=2 * n, replace=False))
+        rec = cuts.reshape(-1, 2)  # disjoint [start, stop), increasing
+        row = [int(rng.integers(0, 1 << 20)) * 2 for _ in range(3)]
+        records.append(rec)
+        bases.append(row)
+        for b in row:
+            lines = {(b + 2 * t + k) // 128 for s, e in rec for t in range(s, e) for k in (0, 1)}
+            want += 128 * len(lines)
+    assert bench.island_line_bytes(records, bases) == want
+    # two islands in one line count it once; one sample straddling nothing
+    assert bench.island_line_bytes([np.array([[0, 10], [20, 30]])], [[0]]) == 128
+    assert bench.island_line_bytes([np.array([[63, 65]])], [[0]]) == 256
