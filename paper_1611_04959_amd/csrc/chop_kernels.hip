@@ -1943,11 +1943,11 @@ __device__ __forceinline__ void copy_chunk(const FillDev &fd, int64_t k, const C
 // sample of the run's first packed position, packed start relative to the
 // segment) and each lane finds the run holding its word's first position by
 // one max-scan over the lanes (run j marks the first word that starts at or
-// after its own start). Then, kCopyU channels at a time, every lane loads the
-// aligned 16-byte source words of its 8 samples (two per run piece: the word
-// holding the first sample and, when the samples run past it, the next),
-// realigns them, blends at a run boundary and writes one 16-byte word with a
-// non-temporal store: all loads of a round are in flight together and no
+// after its own start). Then, kCopyU channels at a time, every lane loads its
+// 8 source samples with one unaligned 16-byte load per run piece (two where
+// its word holds the end of one run and the start of the next), blends them
+// at the run boundary and writes one 16-byte word with a non-temporal store;
+// the next round's loads are issued before this round's stores, and no
 // barrier is taken. A word holding pieces of three or more runs, the last
 // partial word of a row and rows whose line phase differs from their
 // neighbours' (out_stride not a multiple of 8 or out not 16-byte aligned) go
