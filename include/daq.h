@@ -433,7 +433,9 @@ int daq_ctx_kernel_times(daq_ctx *ctx, float *ms, int32_t max);
  * (schedule and graph mode) is looked up there first and stored there after
  * tuning, keyed by device name and batch shape. A context whose schedule
  * came from DAQ_SCHEDULE (daq_ctx_create) is not tuned: *best receives that
- * schedule and DAQ_OK is returned. */
+ * schedule and DAQ_OK is returned. In both of these cases (a cached choice,
+ * a schedule from the environment) nothing is launched and the outputs are
+ * left as they were. */
 int daq_autotune(daq_ctx *ctx, const daq_fill *fills, const daq_fill_out *outs,
                  int32_t n, void *stream, const char *cache_path,
                  daq_schedule *best);
