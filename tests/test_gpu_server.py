@@ -355,3 +355,43 @@ def test_deadtime_accounting_and_watchdog(ctx, workload):
         srv.release(t4)
         with pytest.raises(daq.DaqError):
             srv.set_limits(admit_deadline_us=-1)
+
+
+def test_consumer_that_never_polls_loses_nothing(ctx, workload):
+    """A consumer that stops polling and releasing: the budget fills, every
+    later submit is refused with DAQ_EAGAIN (none is admitted and dropped),
+    the refusals count as deadtime, and when the consumer comes back every
+    admitted fill's completion is there, exact."""
+    specs, xs, xd, fills, refs = workload
+    C = synth.CHANNELS
+    size = [daq.slot_bytes(f) for f in fills]
+    budget = sum(sorted(size)[:4]) + 256
+    arena = poison(torch.empty(budget, dtype=torch.uint8, device="cuda"))
+    with daq.Server(ctx, arena, n_streams=2, max_batch=4) as srv:
+        admitted, refused = {}, 0
+        t_end = time.time() + 0.3
+        k = 0
+        while time.time() < t_end:  # submit round-robin, never poll
+            i = k % len(fills)
+            k += 1
+            t = srv.submit(fills[i], tag=i)
+            if t is None:
+                refused += 1
+            else:
+                admitted[t] = i
+        log("never-polling consumer: %d admitted, %d refused" % (len(admitted), refused))
+        assert len(admitted) >= 1 and refused > 100
+        st = srv.stats()
+        assert st.submitted == len(admitted) and st.rejected == refused
+        assert st.arena_in_use <= budget
+        time.sleep(0.05)
+        got = _drain(srv, len(admitted))
+        assert sorted(got) == sorted(admitted)
+        for t, c in got.items():
+            assert c.tag == admitted[t]
+            _check(srv, c, refs[c.tag], C, "never-polled %d" % c.tag)
+            srv.release(t)
+        assert srv.submit(fills[0], tag=0) is not None  # admits again, and the dead period ends
+        st = srv.stats()
+        assert st.deadtime_ns > 0 and st.completed == len(admitted)
+        _drain(srv, 1)
