@@ -221,9 +221,14 @@ int daq_chop_fill(daq_ctx *ctx, const daq_fill *fill, const daq_fill_out *out,
  * the context's schedule (by default the split schedule's three kernels over
  * every fill, with persistent grids), replayed from a captured HIP graph when
  * the context's graphs are on and launched plainly otherwise. Results per
- * fill are identical to daq_chop_fill whatever the schedule. The two arrays
- * are host arrays of n entries; they are copied before the call returns.
- * n = 0 is a no-op. */
+ * fill are identical to daq_chop_fill whatever the schedule. The paper
+ * chops each fill as it arrives (Section 3, fills in bursts at 12 Hz);
+ * taking several in one launch is this library's addition, for throughput.
+ * The two arrays are host arrays of n entries; they are copied before the
+ * call returns. n = 0 is a no-op. Errors: EINVAL (NULL ctx, n < 0, NULL
+ * arrays with n > 0, or any fill or output that daq_chop_fill would refuse),
+ * EALIGN, ERANGE, all checked for every fill before anything is launched;
+ * ENOMEM or EHIP when scratch cannot grow or a launch fails. */
 int daq_process_batch(daq_ctx *ctx, const daq_fill *fills,
                       const daq_fill_out *outs, int32_t n, void *stream);
 
