@@ -603,14 +603,14 @@ int daq_read_stream(const void *d_buf, int64_t bytes, unsigned int *d_sink,
  * reads n_fills fills of `channels` rows of n_samples int16 each (row r of
  * fill f at d_raw + (f * channels + r) * n_samples, 16-byte aligned) in the
  * split scan's tiles at 512 threads (4,048 owned samples plus a 32-sample
- * left and 16-sample right halo, every channel row, 6 rows in flight, 16-byte
+ * left and 16-sample right halo, every channel row, 9 rows in flight, 16-byte
  * non-temporal loads; groups of 8 outside a row are skipped), in a persistent
  * grid of `blocks` work-groups of 512 threads striding over the tiles.
  * Writes the wrapping sum of the 32-bit words each wave read to d_sink (blocks
  * * 8 words). mode 0: that read alone. Modes 1 and 2 model a single pass
  * that writes the islands from the scan: after each tile, the threads whose
  * 8-sample group (sample / 8 of the row) is below 11 modulo 70 read their
- * group of every row again (6 rows in flight, added to the sums); mode 2
+ * group of every row again (9 rows in flight, added to the sums); mode 2
  * also stores each of those 16-byte words to d_out at word
  * (t * channels + r) * 512 + k, t the tile's index in the launch (fill by
  * fill) and k the thread's rank among the tile's pattern threads (d_out:

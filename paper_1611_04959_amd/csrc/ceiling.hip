@@ -5,7 +5,7 @@
 // in flight per thread, grid-stride), folds the words with XOR so the loads
 // cannot be dropped, and leaves one word per wave in a sink.
 // k_read_tiles reads calorimeter fills in the scan's own pattern (tiles of
-// 4,096 samples x every channel row, 6 rows in flight, the same halo
+// 4,096 samples x every channel row, 9 rows in flight, the same halo
 // overlap) and does nothing else: the rate of that access pattern alone.
 // Its two other modes model a single pass that writes the islands from the
 // scan: after each tile the threads of a fixed one-in-seven pattern of
@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(256) k_read_stream(const u32x4 *p, int64_t n16
 constexpr int kTileThreads = 512;
 constexpr int kTileOwned = 4048;
 constexpr int kTileLeft = 32;
-constexpr int kTileRows = 6;
+constexpr int kTileRows = 9;
 
 // Groups of the island pattern of modes 1 and 2: group index (sample / 8)
 // of the row modulo 70 below 11.
@@ -70,7 +70,7 @@ constexpr int kPatGroups = 11;
 // at lt * 4048 - 32 + 8 i of each row when it lies inside the row. Each wave
 // leaves the wrapping sum of the 32-bit words it read in sink[wave of grid].
 // MODE 1 and 2: pattern threads then read their group of every row again
-// (6 rows in flight) and add it to the sum; MODE 2 also stores each such
+// (9 rows in flight) and add it to the sum; MODE 2 also stores each such
 // word to out[(t * C + c) * 512 + k], k the thread's rank among the tile's
 // pattern threads.
 template <int MODE>

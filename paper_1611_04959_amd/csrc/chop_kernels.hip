@@ -1492,7 +1492,7 @@ __device__ __forceinline__ PartRange part_range(const KArgs &a, int nf, int64_t 
 #define DAQ_Q_SCAN_ROWS 4  // the same with the Q-method fused (three loads per row)
 #endif
 #ifndef DAQ_SCAN_ROWS
-#define DAQ_SCAN_ROWS 6  // channel rows each thread has in flight
+#define DAQ_SCAN_ROWS 9  // channel rows each thread has in flight
 #endif
 
 // Flags and dilation of one tile (Table 2 threshold and pre/post rows): the
