@@ -126,6 +126,42 @@ __device__ __forceinline__ int64_t tile_base_at(const KArgs &a, int f) {
     return a.table ? gbl(a.table + f)->tile_base : a.one.tile_base;
 }
 
+// The edge pass copies the descriptors of batches of at most kFdLds fills
+// into LDS once per work-group, with the tile bases: a wave that meets a new
+// fill then reads its descriptor from LDS instead of waiting on a global
+// load. (The scan does not: its work-groups start streaming raw rows at
+// once, and the copy there cost more than the load it saves.)
+constexpr int kFdLds = 16;
+constexpr int kFdWords = (int)(sizeof(FillDev) / 16);
+
+// Copies the first nf descriptors of the table into s (call before the
+// barrier that publishes it); false when the batch is too large or has no table.
+template <int NT>
+__device__ __forceinline__ bool stage_fills(const KArgs &a, int nf, u32x4 *s) {
+    if (a.table == nullptr || nf > kFdLds) return false;
+    const DAQ_GLOBAL u32x4 *src = (const DAQ_GLOBAL u32x4 *)a.table;
+    for (int i = threadIdx.x; i < nf * kFdWords; i += NT) s[i] = src[i];
+    return true;
+}
+
+// Descriptor of fill f from the LDS copy (f the same in every lane).
+__device__ __forceinline__ FillDev fill_from_lds(const u32x4 *s, int f) {
+    f = __builtin_amdgcn_readfirstlane(f);
+    union {
+        FillDev d;
+        u32x4 v[kFdWords];
+    } u;
+#pragma unroll
+    for (int i = 0; i < kFdWords; i++) {
+        const u32x4 w = s[f * kFdWords + i];
+        u.v[i] = u32x4{(unsigned)__builtin_amdgcn_readfirstlane((int)w.x),
+                       (unsigned)__builtin_amdgcn_readfirstlane((int)w.y),
+                       (unsigned)__builtin_amdgcn_readfirstlane((int)w.z),
+                       (unsigned)__builtin_amdgcn_readfirstlane((int)w.w)};
+    }
+    return u.d;
+}
+
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 
 // Adds the eight int16 samples of one 16-byte row chunk to eight sums: one
@@ -1843,11 +1879,13 @@ template <int NT>
 __global__ void __launch_bounds__(NT) k_edge_pass(KArgs a) {
     constexpr int NW = NT / 64;
     __shared__ int64_t s_base[kLdsFills];
+    __shared__ u32x4 s_fd[kFdLds * kFdWords];
     const int nf = a.hdr ? a.hdr->n_fills : a.n_fills;
     const int64_t total = a.hdr ? a.hdr->total_tiles : a.total_tiles;
     const bool lds_fills = nf <= kLdsFills;
     if (lds_fills)
         for (int i = threadIdx.x; i < nf; i += NT) s_base[i] = tile_base_at(a, i);
+    const bool fd_lds = stage_fills<NT>(a, nf, s_fd);
     lds_barrier();
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1879,7 +1917,7 @@ __global__ void __launch_bounds__(NT) k_edge_pass(KArgs a) {
                 if ((lds_fills ? s_base[mid] : tile_base_at(a, mid)) <= tile) lo = mid;
                 else hi = mid - 1;
             }
-            fd = fill_at(a, lo);
+            fd = fd_lds ? fill_from_lds(s_fd, lo) : fill_at(a, lo);
             cur = lo;
         }
         edge_wave_tile(a, fd, tile, lane);
