@@ -129,8 +129,8 @@ __device__ __forceinline__ int64_t tile_base_at(const KArgs &a, int f) {
 // The edge pass copies the descriptors of batches of at most kFdLds fills
 // into LDS once per work-group, with the tile bases: a wave that meets a new
 // fill then reads its descriptor from LDS instead of waiting on a global
-// load. (The scan does not: its work-groups start streaming raw rows at
-// once, and the copy there cost more than the load it saves.)
+// load. (The scan and copy passes do not: there the copy cost as much as
+// the load it saves, or more.)
 constexpr int kFdLds = 16;
 constexpr int kFdWords = (int)(sizeof(FillDev) / 16);
 
