@@ -643,6 +643,7 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
                       ped_samples=sp0.ped_samples) for d in xd]
     n_pool = len(fills)
     raw = specs[0].raw_bytes
+    C = synth.CHANNELS
     arena = torch.empty(int(budget_gb * 1e9), dtype=torch.uint8, device="cuda")
     srv = daq.Server(ctx, arena, n_streams=n_streams, max_batch=max_batch)
 
@@ -653,7 +654,7 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
         arr_ns = {}
         kept = None
         st0 = srv.stats()
-        lat, done_bytes = [], 0
+        lat, done_bytes, alg_bytes = [], 0, 0
         t0 = time.monotonic_ns()
         i, n_off = 0, 0
         end_ns = t0 + int(dur * 1e9)
@@ -683,6 +684,9 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
                 assert c.error == 0 and c.status == 0
                 lat.append((c.t_ready_ns - arr_ns.pop(c.ticket)) * 1e-6)
                 done_bytes += raw
+                # as the batched line counts them: raw read, packed samples,
+                # records, counts and pedestals written
+                alg_bytes += raw + 2 * C * c.total_len + 24 * c.n_islands + 24 + 4 * C
                 # the first completion whose samples are a rendered fill is kept
                 # (its slot unreleased) for the oracle check after the run
                 data = (c.tag % len(host)) if host is not None else (c.tag if c.tag < len(xs) else None)
@@ -698,6 +702,9 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
         st = srv.stats()
         res = {"fills": len(lat), "p50_ms": round(pct(lat, 50), 4), "p99_ms": round(pct(lat, 99), 4),
                "max_ms": round(max(lat), 4), "gbs": round(done_bytes / wall / 1e9, 1),
+               "pct_hbm_peak": round(100 * done_bytes / wall / 1e9 / HBM_PEAK_GBS, 2),
+               "algorithmic_gbs": round(alg_bytes / wall / 1e9, 1),
+               "pct_hbm_peak_algorithmic": round(100 * alg_bytes / wall / 1e9 / HBM_PEAK_GBS, 2),
                "wall_s": round(wall, 2), "batches": int(st.batches - st0.batches),
                # high-water mark of the arena since the server started (all runs so far)
                "arena_high_water_gb": round(st.arena_peak / 1e9, 2),
