@@ -31,6 +31,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 UNEVEN = "24 uneven calorimeter streams: N ~ U{100k..560k}, rate 0.5-4x, thr -400..-150, pre 4-16, post 16-48"
 STRESS = "whole detector: 4 fills x 24 calorimeters x 54 ch x 560,000, 10x rate, thr -100, pre 8, post 48"
+SERVED = ("16 serving-stream fills in one launch: 54 ch x 560,000, the nominal rate, thr -200, pre 8, post 24 "
+          "(the served fills' shape)")
 # Fill-0 results of each line, checked against the CPU oracle in the oracle
 # leg at the end: (kind, dict that receives "parity_fill0", payload).
 PENDING = []
@@ -654,7 +656,7 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
         arr_ns = {}
         kept = None
         st0 = srv.stats()
-        lat, done_bytes, alg_bytes = [], 0, 0
+        lat, done_bytes, alg_bytes, island_samples = [], 0, 0, 0
         t0 = time.monotonic_ns()
         i, n_off = 0, 0
         end_ns = t0 + int(dur * 1e9)
@@ -687,6 +689,7 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
                 # as the batched line counts them: raw read, packed samples,
                 # records, counts and pedestals written
                 alg_bytes += raw + 2 * C * c.total_len + 24 * c.n_islands + 24 + 4 * C
+                island_samples += c.total_len
                 # the first completion whose samples are a rendered fill is kept
                 # (its slot unreleased) for the oracle check after the run
                 data = (c.tag % len(host)) if host is not None else (c.tag if c.tag < len(xs) else None)
@@ -705,6 +708,7 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
                "pct_hbm_peak": round(100 * done_bytes / wall / 1e9 / HBM_PEAK_GBS, 2),
                "algorithmic_gbs": round(alg_bytes / wall / 1e9, 1),
                "pct_hbm_peak_algorithmic": round(100 * alg_bytes / wall / 1e9 / HBM_PEAK_GBS, 2),
+               "occupancy": round(island_samples / max(1, len(lat) * specs[0].n_samples), 4),
                "wall_s": round(wall, 2), "batches": int(st.batches - st0.batches),
                # high-water mark of the arena since the server started (all runs so far)
                "arena_high_water_gb": round(st.arena_peak / 1e9, 2),
@@ -837,6 +841,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="serving loop at the nominal arrival rate (0 = skip)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch line")
+    ap.add_argument("--no-served-shape", action="store_true",
+                    help="skip the batched line over 16 fills of the serving streams' shape")
     ap.add_argument("--no-pipelined", action="store_true", help="skip the two-stream batched line")
     ap.add_argument("--no-qmethod", action="store_true", help="skip the Q-method line")
     ap.add_argument("--no-ingest", action="store_true", help="skip the 12-bit ingest line")
@@ -1102,6 +1108,9 @@ def main():
     if not args.no_stress:
         others["stress"] = batch_bench(daq, synth, synth.config_c4(), STRESS, steps=max(5, args.steps // 10),
                                       name="c4")
+    if not args.no_served_shape:
+        others["served_shape"] = batch_bench(daq, synth, [synth.config_c3_fill(s, 0) for s in range(16)], SERVED,
+                                             steps=max(10, args.steps // 2), name="c3 batched")
 
     # ---- serving loop: Poisson arrivals with bursts, HBM-budget admission -------------
     serving = None
