@@ -638,7 +638,7 @@ def serve_bench(daq, synth, ctx, seconds, budget_gb=32.0, n_streams=3, max_batch
     ORACLE_SAMPLES["c3"] = (xs[:2], specs[:2])
     # a pool of distinct fills in HBM, far larger than what is in flight, so
     # that no fill is read while its previous copy may still be cached: each
-    # rendered fill and seven copies rotated along time
+    # rendered fill and seven copies of it in memory of their own
     xd = distinct_copies(synth.to_device(xs), 8)
     sp0 = specs[0]
     fills = [daq.Fill(d, sp0.n_samples, threshold=sp0.threshold, pre=sp0.pre, post=sp0.post,
