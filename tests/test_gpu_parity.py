@@ -415,3 +415,42 @@ def test_autotune_candidates_agree(ctx, tmp_path):
     best2 = ctx.daq_autotune(fills, outs, cache_path=str(tmp_path / "tune.txt"))
     assert (best2.threads, best2.wgs_per_cu, best2.variant) == (best.threads, best.wgs_per_cu, best.variant)
     ctx.set_schedule(*DEFAULT)
+
+
+def test_batches_alternating_over_two_streams():
+    """The benchmark's job form: consecutive batches alternate over two HIP
+    streams, each stream with its own context, its own copy of the fills and
+    its own outputs, so that batches overlap on the device. Every launch's
+    results equal the oracle's (outputs poisoned before each launch is
+    issued; the results are checked after the last one)."""
+    specs = synth.config_c1(4)
+    xs = synth.render_many(specs)
+    ps = [params(s.threshold, s.pre, s.post) for s in specs]
+    refs = oracle_many(xs, [s.n_samples for s in specs], ps)
+    xd = synth.to_device(xs)
+    copies = [xd, [d.clone() for d in xd]]
+    ctxs = [daq.Context(0), daq.Context(0)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    try:
+        for c in ctxs:
+            c.set_schedule(*DEFAULT)
+            c.set_graphs(False)
+        fills = [[make_fill(d, s.n_samples, p) for d, s, p in zip(cp, specs, ps)] for cp in copies]
+        outs = [[daq.alloc_out(f) for f in fs] for fs in fills]
+        for rnd in range(3):
+            log("two streams, round %d" % rnd)
+            torch.cuda.synchronize()
+            for k in range(2):
+                for o in outs[k]:
+                    poison_out(o)
+            torch.cuda.synchronize()
+            for i in range(6):  # launches alternate; the last two are the ones checked
+                k = i % 2
+                ctxs[k].daq_process_batch(fills[k], outs[k], streams[k])
+            torch.cuda.synchronize()
+            for k in range(2):
+                for j, (o, r) in enumerate(zip(outs[k], refs)):
+                    assert_same(o, r, ctx="stream %d fill %d round %d" % (k, j, rnd))
+    finally:
+        for c in ctxs:
+            c.close()
