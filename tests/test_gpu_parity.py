@@ -6,6 +6,7 @@ ragged tails, every schedule, the three entry forms (fused per fill, find +
 gather, batched launch), edge cases, and the benchmark workloads at full size.
 """
 import ctypes
+import os
 
 import numpy as np
 import pytest
@@ -398,6 +399,8 @@ def test_workload_detector_stress(ctx, sched):
 
 
 def test_autotune_candidates_agree(ctx, tmp_path):
+    if os.environ.get("DAQ_SCHEDULE"):
+        pytest.skip("DAQ_SCHEDULE fixes the schedule: the tuner launches nothing")
     specs = synth.config_c1(4)
     xs = synth.render_many(specs)
     ps = [params(s.threshold, s.pre, s.post) for s in specs]
