@@ -12,12 +12,15 @@ the reported figures are bytes.
   python -m paper_1611_04959_amd.traffic stats KERNEL_STATS_CSV
 
   python -m paper_1611_04959_amd.traffic tail KERNEL_TRACE_CSV K
+  python -m paper_1611_04959_amd.traffic streams KERNEL_TRACE_CSV K
 
 ``summarize`` writes OUT_JSON (read by bench.py) and prints a text summary;
 ``stats`` prints a rocprofv3 ``--stats`` kernel table as markdown; ``tail``
 prints the mean duration of each chop kernel over its last K dispatches and
 the mean span of the last K launches (first kernel start to last kernel end),
-i.e. the timed steps of a run whose autotuning came first.
+i.e. the timed steps of a run whose autotuning came first; ``streams`` does
+the same for launches that alternate over several streams, with the span of
+all K and the share of it during which two or more streams ran kernels.
 """
 from __future__ import annotations
 
@@ -185,6 +188,53 @@ def tail(path, k):
           % (len(spans), sum(spans) / len(spans)))
 
 
+def streams(path, k):
+    """The last k launches of a run whose launches alternate over several
+    streams: each chop kernel's mean duration, the launches per stream, the
+    wall span from the first of those launches' start to the last kernel's
+    end (and that span over k), and the share of the span during which
+    kernels of two or more streams ran at once."""
+    rows = list(csv.DictReader(open(path, newline="")))
+    seq = []
+    for r in rows:
+        name = short(r["Kernel_Name"])
+        if name is not None:
+            seq.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), name, r.get("Stream_Id", "0")))
+    seq.sort()
+    opens = [i for i, x in enumerate(seq) if x[2] in ("k_scan_pass", "k_chop", "k_pipe")][-k:]
+    if not opens:
+        print("no launch found")
+        return None
+    window = seq[opens[0]:]
+    per, by_stream = defaultdict(list), defaultdict(int)
+    for a, b, name, sid in window:
+        per[name].append((b - a) / 1e3)
+        if name in ("k_scan_pass", "k_chop", "k_pipe"):
+            by_stream[sid] += 1
+    t0 = window[0][0]
+    t1 = max(b for _, b, _, _ in window)
+    # time with kernels of two or more streams in flight (sweep over edges)
+    edges = sorted([(a, 1, sid) for a, _, _, sid in window] + [(b, -1, sid) for _, b, _, sid in window])
+    live, both, last = defaultdict(int), 0, t0
+    for t, d, sid in edges:
+        if sum(1 for v in live.values() if v > 0) >= 2:
+            both += t - last
+        live[sid] += d
+        last = t
+    span = (t1 - t0) / 1e3
+    print("| Kernel | Dispatches in the last %d launches | Mean (us) |" % len(opens))
+    print("|---|---|---|")
+    for name in ("k_prepare", "k_scan_pass", "k_edge_pass", "k_copy_pass", "k_chop", "k_pipe"):
+        if name in per:
+            print("| `%s` | %d | %.1f |" % (name, len(per[name]), sum(per[name]) / len(per[name])))
+    print()
+    print("Launches per stream: %s" % ", ".join("%s: %d" % kv for kv in sorted(by_stream.items())))
+    print("Span of the last %d launches: %.1f us, %.1f us per launch; kernels of two or more streams "
+          "in flight for %.0f %% of it" % (len(opens), span, span / len(opens), 100.0 * both / 1e3 / span))
+    return {"span_us": span, "per_launch_us": span / len(opens), "overlap": both / 1e3 / span,
+            "streams": dict(by_stream), "mean_us": {n: sum(v) / len(v) for n, v in per.items()}}
+
+
 if __name__ == "__main__":
     if len(sys.argv) >= 2 and sys.argv[1] == "copy":
         copy_run(int(sys.argv[2]) if len(sys.argv) > 2 else 1024)
@@ -192,6 +242,8 @@ if __name__ == "__main__":
         stats_table(sys.argv[2])
     elif len(sys.argv) == 4 and sys.argv[1] == "tail":
         tail(sys.argv[2], int(sys.argv[3]))
+    elif len(sys.argv) == 4 and sys.argv[1] == "streams":
+        streams(sys.argv[2], int(sys.argv[3]))
     elif len(sys.argv) >= 7 and sys.argv[1] == "summarize":
         summarize(*sys.argv[2:7], fills=int(sys.argv[7]) if len(sys.argv) > 7 else 16)
     else:

@@ -77,3 +77,28 @@ def test_tail_finds_the_last_launches(tmp_path, capsys):
     assert "| `k_edge_pass<512>` | 3 | 10.0 |" in out
     assert "| `k_copy_pass<512>` | 3 | 70.0 |" in out
     assert "last 3 launches (first kernel start to last kernel end): 230.0 us" in out
+
+
+def test_streams_measures_span_and_overlap(tmp_path, capsys):
+    """Two streams, launches of 100 us offset by 50 us: four launches span
+    250 us (62.5 us each), and kernels of both streams run at once for the
+    150 us between the second launch's start and the third's end."""
+    path = tmp_path / "trace.csv"
+    rows = []
+    for i in range(4):
+        t = 1000 + 50 * i
+        sid = str(i % 2)
+        for name, a, b in (("k_scan_pass<512, 9, false, true>", 0, 60), ("k_edge_pass<512>", 60, 70),
+                           ("k_copy_pass<512>", 70, 100)):
+            rows.append({"Kernel_Name": "void daqk::(anonymous namespace)::%s(daqk::KArgs)" % name,
+                         "Start_Timestamp": (t + a) * 1000, "End_Timestamp": (t + b) * 1000, "Stream_Id": sid})
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=TRACE_FIELDS + ["Stream_Id"])
+        w.writeheader()
+        w.writerows(rows)
+    res = traffic.streams(str(path), 4)
+    out = capsys.readouterr().out
+    assert res["streams"] == {"0": 2, "1": 2}
+    assert abs(res["span_us"] - 250.0) < 1e-9 and abs(res["per_launch_us"] - 62.5) < 1e-9
+    assert abs(res["overlap"] - 150.0 / 250.0) < 1e-9
+    assert "| `k_scan_pass` | 4 | 60.0 |" in out
