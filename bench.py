@@ -955,6 +955,7 @@ def main():
                            ped_samples=s.ped_samples) for d, s in zip(xd2, specs)]
         outs2 = [daq.alloc_out(f) for f in fills2]
         ctx2 = daq.Context(0)
+        ctx2.set_graphs(graphs)  # the launch mode the tuner chose for the first context
         stream2 = torch.cuda.Stream()
         pipe = [(ctx, daq.Batch(fills, outs), stream), (ctx2, daq.Batch(fills2, outs2), stream2)]
         pipelined = None

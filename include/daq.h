@@ -531,8 +531,9 @@ typedef struct daq_server_stats {
  * daq_find_islands for a bad fill, or a NULL `bytes`; host-only. */
 int daq_server_slot_bytes(const daq_fill *fill, int32_t flags, uint64_t *bytes);
 
-/* Starts a server on ctx's device with ctx's current schedule (ctx is not
- * used afterwards). d_arena: caller-owned device memory of arena_bytes,
+/* Starts a server on ctx's device with ctx's current schedule and graph mode
+ * (each worker has a context of its own with both; ctx is not used
+ * afterwards). d_arena: caller-owned device memory of arena_bytes,
  * 256-byte aligned, that the server sub-allocates (never frees).
  * n_streams: 1..8 workers; max_batch: 1..256 fills per launch. */
 int daq_server_create(daq_server **out, daq_ctx *ctx, void *d_arena,

@@ -354,8 +354,10 @@ int daq_server_create(daq_server **out, daq_ctx *ctx, void *d_arena, size_t aren
     daq_server *srv = new daq_server();
     int dev = 0;
     hipError_t he = hipSuccess;
+    int graphs = 1;
     int rc = daq_ctx_get_device(ctx, &dev);
     if (rc == DAQ_OK) rc = daq_ctx_get_schedule(ctx, &srv->sched);
+    if (rc == DAQ_OK) rc = daq_ctx_get_graphs(ctx, &graphs);
     if (rc == DAQ_OK && (he = hipSetDevice(dev)) != hipSuccess) rc = DAQ_EHIP;
     srv->device = dev;
     srv->arena_base = static_cast<uint8_t *>(d_arena);
@@ -367,6 +369,7 @@ int daq_server_create(daq_server **out, daq_ctx *ctx, void *d_arena, size_t aren
         Worker &w = srv->workers[(size_t)i];
         rc = daq_ctx_create(&w.ctx, dev);
         if (rc == DAQ_OK) rc = daq_ctx_set_schedule(w.ctx, &srv->sched);
+        if (rc == DAQ_OK) rc = daq_ctx_set_graphs(w.ctx, graphs);
         if (rc == DAQ_OK && (he = hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking)) != hipSuccess)
             rc = DAQ_EHIP;
         if (rc == DAQ_OK && (he = hipEventCreateWithFlags(&w.done, hipEventDisableTiming)) != hipSuccess)
